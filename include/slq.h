@@ -1,0 +1,237 @@
+/*
+ * slq.h - C ABI of libslq, the MI355X (gfx950) hot path of self-learning
+ * determinantal quantum Monte Carlo (Xu, Qi, Liu, Fu, Meng, arXiv:1612.03804).
+ *
+ * Notation (paper, "Basics of DQMC", Eq. 1):
+ *   lattice        periodic lx x ly square lattice, N = lx*ly, site i = x + lx*y
+ *   slices         l = 1..L imaginary-time slices, L*dtau = beta
+ *   field          s_{i,l} = +-1, stored int8 s[l-1][i] (slice-major)
+ *   kinetic        K_ij = -t on nearest-neighbour bonds (a length-2 dimension
+ *                  carries the bond twice), K_ii = -mu;  E = exp(-dtau K)
+ *   slice matrix   B_l = E diag(exp(-dtau xi s_{.,l}))
+ *   weight         W_f(s) = det(1 + B_L ... B_1)    (fermion determinant of Eq. 1)
+ *   Green's fn.    G = (1 + B_L ... B_1)^{-1},  G[i][j] = <c_i c_j^dag>, row-major
+ *
+ * Conventions shared by every call:
+ *   - Return value: SLQ_OK or a negative SLQ_ERR_* code; slq_last_error()
+ *     returns a thread-local message for the last failure.  Nothing throws.
+ *   - Pointers named d_* are device pointers owned by the caller; the library
+ *     never frees or retains them past the call.  Pointers without d_ are host
+ *     pointers, read during the call only.
+ *   - Calls are asynchronous on the caller's HIP stream `stream` (0 = the null
+ *     stream): host-side argument checks return at once; everything else is
+ *     enqueued.  Results are valid after the caller synchronises the stream.
+ *   - Per-item problems found on the device (a spin that is not +-1, a
+ *     non-finite intermediate, a singular final matrix) are written to
+ *     d_status[b] (0 = ok, SLQ_ST_* bits otherwise) and do not abort the batch.
+ *   - A plan (slq_plan) owns device workspace sized for one model and a
+ *     maximum batch; it is created and destroyed on the host (allocation and
+ *     release are synchronous).  Calls on one plan must not overlap in time:
+ *     they share its workspace.  Distinct plans are independent.
+ *   - Random numbers: Philox4x64-10 (Salmon et al., SC'11), key (seed, tag),
+ *     4-word counter chosen per decision as documented per call; uniform
+ *     u = (word0 >> 11) * 2^-53, integer in [0,n) = ((word0 >> 32) * n) >> 32.
+ *     Chain index = chain0 + batch position.
+ */
+#ifndef SLQ_H
+#define SLQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SLQ_OK = 0,
+  SLQ_ERR_ARG = -1,       /* invalid argument (sizes, null pointers, unusable terms) */
+  SLQ_ERR_DEVICE = -2,    /* no HIP device, or a HIP runtime call failed */
+  SLQ_ERR_WORKSPACE = -3, /* batch larger than the plan was created for */
+  SLQ_ERR_NUMERIC = -4    /* host-visible numeric failure (fit: singular normal equations) */
+};
+
+/* d_status bits */
+enum {
+  SLQ_ST_BAD_SPIN = 1,    /* a field entry is not +-1 */
+  SLQ_ST_NONFINITE = 2,   /* a non-finite value appeared in the stabilised chain */
+  SLQ_ST_SINGULAR = 4     /* the final matrix M has a zero pivot (W_f = 0) */
+};
+
+typedef struct slq_model {
+  int32_t lx, ly;      /* lattice extents, >= 1 each, N = lx*ly <= 2400 */
+  int32_t n_slices;    /* L >= 1 */
+  int32_t n_stab;      /* slices multiplied between QR stabilisations, >= 1 */
+  double t, mu;        /* hopping and chemical potential */
+  double dtau, xi;     /* slice width (> 0) and Ising-fermion coupling */
+} slq_model;
+
+typedef struct slq_plan slq_plan;
+
+/* Library version string and the last error message of this thread. */
+const char* slq_version(void);
+const char* slq_last_error(void);
+
+/*
+ * slq_plan_create - allocate device workspace for `model` and up to
+ * `max_batch` simultaneous fields on the current HIP device, and build
+ * E = exp(-dtau K) and E^{-1} there (closed form: K is diagonal in lattice
+ * momentum, so E is e^{dtau mu} times the Kronecker product of two circulant
+ * 1-D propagators).  Model definition: "Basics of DQMC" (B^tau = exp(dtau K)
+ * exp(V)) with the sign conventions at the top of this header.
+ * Synchronous.  *out receives the plan; free it with slq_plan_destroy.
+ * Errors: SLQ_ERR_ARG (sizes), SLQ_ERR_DEVICE (allocation / launch failure).
+ */
+int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out);
+int slq_plan_destroy(slq_plan* plan);
+/* Device bytes held by the plan. */
+int slq_plan_bytes(const slq_plan* plan, size_t* bytes);
+/* Copy E (or E^{-1} when inverse != 0) into caller memory d_out [N][N]. */
+int slq_kinetic(slq_plan* plan, int32_t inverse, double* d_out, hipStream_t stream);
+
+/*
+ * Kernel timing of the chain product, the dominant kernel of every exact
+ * evaluation (X <- E diag(d_l) X for all fields of a batch, one launch per
+ * slice; Eq. 1's B(beta,0) as products of B^tau).  While enabled, HIP events
+ * are recorded on the call's stream around each such launch.  slq_profile_read
+ * waits for those events and returns their summed duration in ms, the number
+ * of launches and the algorithmic flops (2 N^3 per field per launch), then
+ * clears the record.  Enabling also clears it.  Host-side only, synchronous.
+ */
+int slq_profile_enable(slq_plan* plan, int32_t enable);
+int slq_profile_read(slq_plan* plan, double* ms, int64_t* launches, double* flops);
+
+/*
+ * slq_weight - exact fermion weight of Eq. 1 for `batch` fields:
+ *   d_logabs[b] = log|det(1 + B_L...B_1)|, d_sign[b] = sign (+1/-1, 0 if W_f = 0).
+ * d_s: int8 [batch][L][N].  The chain is kept as U diag(D) V and refactored by
+ * a column-pre-pivoted Householder QR every n_stab slices (the paper cites
+ * the standard O(beta N^3) stabilised algorithm without describing it).
+ * d_status: int32 [batch] (may be NULL).  Errors: SLQ_ERR_ARG,
+ * SLQ_ERR_WORKSPACE (batch > max_batch), SLQ_ERR_DEVICE.
+ */
+int slq_weight(slq_plan* plan, int32_t batch, const int8_t* d_s,
+               double* d_logabs, int8_t* d_sign, int32_t* d_status, hipStream_t stream);
+
+/*
+ * slq_green - as slq_weight, and also the equal-time Green's function
+ * d_G[b] = (1 + B_L...B_1)^{-1}, FP64 [batch][N][N] row-major.
+ */
+int slq_green(slq_plan* plan, int32_t batch, const int8_t* d_s, double* d_G,
+              double* d_logabs, int8_t* d_sign, int32_t* d_status, hipStream_t stream);
+
+/*
+ * slq_udv - the stabilised factorisation U diag(D) V of the cyclic chain that
+ * starts at slice slice0 + 1:  B_{k(L)} ... B_{k(1)}, k(j) = (slice0 + j - 1)
+ * mod L + 1 (slice0 = 0 gives B_L ... B_1).  U is orthogonal, D > 0 holds
+ * the graded scales and V is well conditioned; the factorisation is the one
+ * slq_weight/slq_green finish from.  d_U, d_V: FP64 [batch][N][N] row-major;
+ * d_D: FP64 [batch][N].  0 <= slice0 < L.
+ */
+int slq_udv(slq_plan* plan, int32_t batch, const int8_t* d_s, int32_t slice0,
+            double* d_U, double* d_D, double* d_V, int32_t* d_status, hipStream_t stream);
+
+/*
+ * slq_sweep_local - n_sweeps local-update DQMC sweeps ("Basics of DQMC") on
+ * `batch` independent chains, in place.  For each slice l = 1..L and site
+ * i = 0..N-1 in ascending order the flip s_{i,l} -> -s_{i,l} has ratio
+ * R = 1 + delta (1 - G_ii), delta = exp(2 dtau xi s_{i,l}) - 1, with G the
+ * Green's function whose cyclic chain ends at B_l; it is accepted iff
+ * u < |R| (Metropolis on |W_f|) and G is updated by Sherman-Morrison
+ * G -= (delta/R)(e_i - G[:,i]) G[i,:] (applied in delayed blocks).  After
+ * each slice G <- B_l G B_l^{-1}; when l % n_stab == 0 G is recomputed from
+ * the stabilised chain and the wrap drift max|G_wrapped - G_fresh| recorded.
+ * u: key (seed, 1), counter (i, l-1, sweep0 + k, chain0 + b) for sweep k.
+ * In/out: d_s [batch][L][N]; d_G [batch][N][N] must hold G of the incoming
+ * fields (from slq_green) and holds G of the outgoing ones; d_logabs and
+ * d_sign are advanced by log|R| and sign R of accepted flips.
+ * Out: d_accepts int64 [batch] (accepted flips, summed over the sweeps),
+ * d_drift FP64 [batch] (largest drift seen), d_status (may be NULL).
+ */
+int slq_sweep_local(slq_plan* plan, int32_t batch, int8_t* d_s, double* d_G,
+                    double* d_logabs, int8_t* d_sign, int32_t n_sweeps,
+                    uint64_t seed, uint64_t sweep0, uint64_t chain0,
+                    int64_t* d_accepts, double* d_drift, int32_t* d_status,
+                    hipStream_t stream);
+
+/*
+ * Effective bosonic action, Eq. 2 with symmetry-reduced couplings:
+ *   S_eff(s) = c0 + sum_k lambda_k F_k(s),  F_k = 1/2 sum_x s_x h_k(x),
+ *   h_k((i,l)) = sum over delta in spatial shell r_k of
+ *                s_{i+delta, l+dl_k} + s_{i+delta, l-dl_k}   (dl_k > 0)
+ *                s_{i+delta, l}                               (dl_k = 0)
+ * with time taken modulo L.  Shell r holds the lattice offsets of the r-th
+ * smallest squared length (0: (0,0); 1: (+-1,0),(0,+-1); 2: (+-1,+-1);
+ * 3: (+-2,0),(0,+-2); 4: (+-2,+-1),(+-1,+-2); 5: (+-2,+-2)).
+ * lambda_k = -beta J_k and c0 = -beta E_0, so S_eff approximates ln|W_f|
+ * (Eq. 3).  A term needs 0 <= r <= 5, 0 <= dl <= L/2, (r,dl) != (0,0) and no
+ * site may be its own partner.
+ * Effective moves (step iii) act on colour classes: one class is one time
+ * slice and one colour of the greedy colouring (ascending site index,
+ * smallest free colour) of the graph of dl = 0 couplings; class index =
+ * colour + n_colours*(l-1).  A move draws a class uniformly and applies
+ * Metropolis u < exp(dS), dS = -2 s_x sum_k lambda_k h_k(x), to all its sites.
+ */
+typedef struct slq_eff slq_eff;
+
+/* Create from host arrays terms [n_terms][2] = (r, dl), lambda [n_terms], c0.
+ * Builds the colour classes and copies the tables to the device; synchronous. */
+int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms,
+                   const double* lambda, double c0, slq_eff** out);
+int slq_eff_destroy(slq_eff* eff);
+/* Number of colour classes (n_colours * L). */
+int slq_eff_classes(const slq_eff* eff, int32_t* n_classes);
+/* Replace (c0, lambda) from device memory d_theta [1 + n_terms] on `stream`
+ * (e.g. the output of slq_fit_effective). */
+int slq_eff_set_theta(slq_eff* eff, const double* d_theta, hipStream_t stream);
+
+/*
+ * slq_eff_sweep - n_moves effective moves on each of `batch` fields, in place
+ * (step iii of the paper, "Formalism of SLDQMC").  The class of move m of
+ * chain b uses counter (0, m, step, chain0+b); the Metropolis draw of site
+ * (i, l) uses counter (1 + (l-1)*N + i, m, step, chain0+b); key (seed, 2).
+ * Out (may be NULL): d_accepts int64 [batch], d_dS FP64 [batch] = sum of the
+ * accepted dS.
+ */
+int slq_eff_sweep(slq_plan* plan, const slq_eff* eff, int32_t batch, int8_t* d_s,
+                  int32_t n_moves, uint64_t seed, uint64_t step, uint64_t chain0,
+                  int64_t* d_accepts, double* d_dS, hipStream_t stream);
+
+/* slq_eff_features - d_F FP64 [batch][n_terms] = F_k(s_b) (exact half-integers). */
+int slq_eff_features(slq_plan* plan, const slq_eff* eff, int32_t batch,
+                     const int8_t* d_s, double* d_F, hipStream_t stream);
+
+/*
+ * slq_cumulative_step - one cumulative update (steps iii-iv, Eq. 4) of each
+ * of `batch` chains: s' = s after n_moves effective moves (as slq_eff_sweep
+ * with the same seed/step/chain0), logA = [ln|W(s')| - ln|W(s)|] -
+ * [S_eff(s') - S_eff(s)], accepted iff ln u < min(0, logA) with u from key
+ * (seed, 3), counter (0, 0, step, chain0+b).  On acceptance s, logabs and
+ * sign are replaced by those of s'.  d_logabs / d_sign must hold the exact
+ * weight of the incoming fields (from slq_weight).
+ * Out (may be NULL): d_accepted int8 [batch], d_logA FP64 [batch], d_status.
+ */
+int slq_cumulative_step(slq_plan* plan, const slq_eff* eff, int32_t batch,
+                        int8_t* d_s, double* d_logabs, int8_t* d_sign,
+                        int32_t n_moves, uint64_t seed, uint64_t step, uint64_t chain0,
+                        int8_t* d_accepted, double* d_logA, int32_t* d_status,
+                        hipStream_t stream);
+
+/*
+ * slq_fit_effective - multi-linear regression of Eq. 3 (step ii):
+ * ordinary least squares with an intercept of y_n = d_logabs[n] on the
+ * features F_k(s_n) of the terms of `eff`, for n_samples fields d_S
+ * [n_samples][L][N].  Writes d_theta [1 + n_terms] = (c0, lambda_1..K) and
+ * d_r2 [1] = 1 - sum (y - yhat)^2 / sum (y - ybar)^2 (the paper's R^2 score,
+ * "Results").  Needs n_samples >= n_terms + 2.  A singular system leaves
+ * d_theta as NaN.  Device work only; does not change `eff`.
+ */
+int slq_fit_effective(slq_plan* plan, const slq_eff* eff, int64_t n_samples,
+                      const int8_t* d_S, const double* d_logabs,
+                      double* d_theta, double* d_r2, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLQ_H */

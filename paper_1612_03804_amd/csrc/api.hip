@@ -1,0 +1,432 @@
+// C ABI of libslq: plans, argument checks and the orchestration of the
+// stabilised chain (every arithmetic step runs in the kernels of this library).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "slq_internal.h"
+
+namespace slq {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+static int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+__global__ void k_fill_f64(double* x, long n, double v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = v;
+}
+__global__ void k_fill_i32(int32_t* x, long n, int32_t v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = v;
+}
+__global__ void k_fill_i64(int64_t* x, long n, int64_t v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = v;
+}
+__global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) b[i] = a[i];
+}
+__global__ void k_copy_i8(const int8_t* __restrict__ a, int8_t* __restrict__ b, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+static unsigned grid_for(long n) { return (unsigned)std::max<long>(1, std::min<long>((n + 255) / 256, 2048)); }
+
+int fill_f64(double* x, long n, double v, hipStream_t st) {
+  if (n <= 0) return SLQ_OK;
+  k_fill_f64<<<grid_for(n), 256, 0, st>>>(x, n, v);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+int fill_i32(int32_t* x, long n, int32_t v, hipStream_t st) {
+  if (n <= 0) return SLQ_OK;
+  k_fill_i32<<<grid_for(n), 256, 0, st>>>(x, n, v);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+int fill_i64(int64_t* x, long n, int64_t v, hipStream_t st) {
+  if (n <= 0) return SLQ_OK;
+  k_fill_i64<<<grid_for(n), 256, 0, st>>>(x, n, v);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+int copy_f64(const double* a, double* b, long n, hipStream_t st) {
+  if (n <= 0) return SLQ_OK;
+  k_copy_f64<<<grid_for(n), 256, 0, st>>>(a, b, n);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+int copy_i8(const int8_t* a, int8_t* b, long n, hipStream_t st) {
+  if (n <= 0) return SLQ_OK;
+  k_copy_i8<<<grid_for(n), 256, 0, st>>>(a, b, n);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+
+#define SLQ_TRY(x)              \
+  do {                          \
+    int rc_ = (x);              \
+    if (rc_ != SLQ_OK) return rc_; \
+  } while (0)
+
+static int check_model(const slq_model* m) {
+  if (!m) return fail(SLQ_ERR_ARG, "model is NULL");
+  if (m->lx < 1 || m->ly < 1) return fail(SLQ_ERR_ARG, "lx and ly must be >= 1");
+  const long n = (long)m->lx * m->ly;
+  if (n > 2400) return fail(SLQ_ERR_ARG, "N = lx*ly must be <= 2400");
+  if (m->n_slices < 1) return fail(SLQ_ERR_ARG, "n_slices must be >= 1");
+  if (m->n_stab < 1) return fail(SLQ_ERR_ARG, "n_stab must be >= 1");
+  if (!(m->dtau > 0.0) || !std::isfinite(m->dtau)) return fail(SLQ_ERR_ARG, "dtau must be positive and finite");
+  if (!std::isfinite(m->t) || !std::isfinite(m->mu) || !std::isfinite(m->xi))
+    return fail(SLQ_ERR_ARG, "t, mu and xi must be finite");
+  return SLQ_OK;
+}
+
+int check_batch(const Plan& p, long batch) {
+  if (batch < 0) return fail(SLQ_ERR_ARG, "batch must be >= 0");
+  if (batch > p.max_batch) return fail(SLQ_ERR_WORKSPACE, "batch exceeds the plan's max_batch");
+  return SLQ_OK;
+}
+
+// One chain-product GEMM X <- E diag(d_l) X, bracketed by events when timing is on.
+static int timed_chain_gemm(Plan& p, const GemmArgs& g, hipStream_t st) {
+  if (!p.prof) return launch_gemm(g, false, false, st);
+  if (p.ev_used + 2 > p.ev.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      SLQ_HIP(hipEventCreate(&e));
+      p.ev.push_back(e);
+    }
+  }
+  hipEvent_t a = p.ev[p.ev_used], b = p.ev[p.ev_used + 1];
+  p.ev_used += 2;
+  SLQ_HIP(hipEventRecord(a, st));
+  int rc = launch_gemm(g, false, false, st);
+  SLQ_HIP(hipEventRecord(b, st));
+  p.prof_flops += 2.0 * (double)g.M * g.N * g.K * g.batch;
+  return rc;
+}
+
+// U D V of the cyclic chain B_{k(L)} ... B_{k(1)} with k(j) = (slice0 + j - 1) mod L + 1,
+// i.e. slices slice0+1, ..., L, 1, ..., slice0 multiplied from the right to the left.
+int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, hipStream_t st) {
+  const int N = p.n, L = p.L, ns = p.m.n_stab;
+  const long NN = (long)N * N;
+  const long strideS = (long)L * N;
+  SLQ_TRY(fill_f64(p.D, (long)batch * N, 1.0, st));
+  SLQ_TRY(launch_set_identity(p, batch, p.V, st));
+  GemmArgs g{};
+  g.M = N;
+  g.N = N;
+  g.K = N;
+  g.A = p.E;
+  g.lda = N;
+  g.strideA = 0;
+  g.ldb = N;
+  g.strideB = NN;
+  g.ldc = N;
+  g.strideC = NN;
+  g.S = s;
+  g.strideS = strideS;
+  g.inv_scale = 0;
+  g.consts = p.consts;
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  g.batch = batch;
+  for (int j0 = 0; j0 < L; j0 += ns) {
+    const int jend = std::min(j0 + ns, L);
+    double* cur = p.Xa;
+    double* oth = p.Xb;
+    int j = j0;
+    if (j0 == 0) {
+      SLQ_TRY(launch_first_slice(p, batch, s, strideS, (slice0 + 0) % L, cur, st));
+    } else {
+      g.B = p.U;
+      g.C = cur;
+      g.slice = (slice0 + j0) % L;
+      SLQ_TRY(timed_chain_gemm(p, g, st));
+    }
+    for (j = j0 + 1; j < jend; ++j) {
+      g.B = cur;
+      g.C = oth;
+      g.slice = (slice0 + j) % L;
+      SLQ_TRY(timed_chain_gemm(p, g, st));
+      std::swap(cur, oth);
+    }
+    SLQ_TRY(launch_qr(p, batch, cur, status, st));
+    SLQ_TRY(launch_permute_rows(p, batch, p.V, p.Vt, st));
+    GemmArgs v{};
+    v.M = N;
+    v.N = N;
+    v.K = N;
+    v.A = p.W;
+    v.lda = N;
+    v.strideA = NN;
+    v.B = p.Vt;
+    v.ldb = N;
+    v.strideB = NN;
+    v.C = p.V;
+    v.ldc = N;
+    v.strideC = NN;
+    v.rowscale = p.invD;
+    v.strideRS = N;
+    v.alpha = 1.0;
+    v.beta = 0.0;
+    v.a_upper = 1;
+    v.batch = batch;
+    SLQ_TRY(launch_gemm(v, false, false, st));
+  }
+  return SLQ_OK;
+}
+
+static int weight_or_green(slq_plan* plan, int32_t batch, const int8_t* d_s, double* d_G, double* d_logabs,
+                           int8_t* d_sign, int32_t* d_status, hipStream_t st) {
+  if (!plan) return fail(SLQ_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  SLQ_TRY(check_batch(p, batch));
+  if (batch == 0) return SLQ_OK;
+  if (!d_s || !d_logabs || !d_sign) return fail(SLQ_ERR_ARG, "d_s, d_logabs and d_sign must not be NULL");
+  SLQ_HIP(hipSetDevice(p.device));
+  int32_t* status = d_status ? d_status : p.status;
+  SLQ_TRY(fill_i32(status, batch, 0, st));
+  SLQ_TRY(launch_check_spins(p, batch, d_s, status, st));
+  SLQ_TRY(run_chain(p, batch, d_s, 0, status, st));
+  return launch_finish(p, batch, d_G, d_logabs, d_sign, status, st);
+}
+
+}  // namespace slq
+
+using namespace slq;
+
+extern "C" {
+
+const char* slq_version(void) { return "libslq 0.1 (gfx950)"; }
+const char* slq_last_error(void) { return g_err.c_str(); }
+
+int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
+  if (!out) return fail(SLQ_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  SLQ_TRY(check_model(model));
+  if (max_batch < 1) return fail(SLQ_ERR_ARG, "max_batch must be >= 1");
+  int dev = 0, ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(SLQ_ERR_DEVICE, "no HIP device");
+  SLQ_HIP(hipGetDevice(&dev));
+  slq_plan* h = new (std::nothrow) slq_plan();
+  if (!h) return fail(SLQ_ERR_DEVICE, "host allocation failed");
+  Plan& p = h->p;
+  p.m = *model;
+  p.n = model->lx * model->ly;
+  p.L = model->n_slices;
+  p.max_batch = max_batch;
+  p.device = dev;
+  const long N = p.n, NN = N * N, B = max_batch;
+  // byte layout, every block 256-byte aligned
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t oE = take(8 * NN), oEi = take(8 * NN), oTab = take(8 * (2 * (model->lx + model->ly) + 8)),
+               oC = take(8 * 8);
+  const size_t oXa = take(8 * NN * B), oXb = take(8 * NN * B), oW = take(8 * NN * B), oU = take(8 * NN * B),
+               oV = take(8 * NN * B), oVt = take(8 * NN * B);
+  const size_t oD = take(8 * N * B), oID = take(8 * N * B), oT = take(8 * (N + 16) * 16 * B);
+  const size_t oPerm = take(4 * N * B), oPiv = take(4 * N * B), oNref = take(4 * B), oSt = take(4 * B);
+  const size_t oSw = take((size_t)p.L * N * B), oDv = take(8 * B), oDv2 = take(8 * B), oIv = take(8 * B);
+  const size_t oX = take(8 * N * SWEEP_KD * B), oY = take(8 * N * SWEEP_KD * B), oA = take(8 * SWEEP_KD * B);
+  const size_t oFo = take(8 * 64 * B), oFn = take(8 * 64 * B), oSg = take(B);
+  p.bytes = off;
+  void* base = nullptr;
+  if (hipMalloc(&base, off) != hipSuccess) {
+    delete h;
+    return fail(SLQ_ERR_DEVICE, "hipMalloc of " + std::to_string(off) + " bytes failed");
+  }
+  char* c = (char*)base;
+  p.base = (double*)base;
+  p.E = (double*)(c + oE);
+  p.Einv = (double*)(c + oEi);
+  p.tabs = (double*)(c + oTab);
+  p.consts = (double*)(c + oC);
+  p.Xa = (double*)(c + oXa);
+  p.Xb = (double*)(c + oXb);
+  p.W = (double*)(c + oW);
+  p.U = (double*)(c + oU);
+  p.V = (double*)(c + oV);
+  p.Vt = (double*)(c + oVt);
+  p.D = (double*)(c + oD);
+  p.invD = (double*)(c + oID);
+  p.Tblk = (double*)(c + oT);
+  p.perm = (int32_t*)(c + oPerm);
+  p.ipiv = (int32_t*)(c + oPiv);
+  p.nref = (int32_t*)(c + oNref);
+  p.status = (int32_t*)(c + oSt);
+  p.s_work = (int8_t*)(c + oSw);
+  p.dvec = (double*)(c + oDv);
+  p.dvec2 = (double*)(c + oDv2);
+  p.ivec = (int64_t*)(c + oIv);
+  p.dX = (double*)(c + oX);
+  p.dY = (double*)(c + oY);
+  p.dA = (double*)(c + oA);
+  p.F_old = (double*)(c + oFo);
+  p.F_new = (double*)(c + oFn);
+  p.sgn_work = (int8_t*)(c + oSg);
+  int rc = launch_kinetic(p, 0);
+  if (rc == SLQ_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(SLQ_ERR_DEVICE, "kinetic build failed");
+  if (rc != SLQ_OK) {
+    hipFree(base);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return SLQ_OK;
+}
+
+int slq_profile_enable(slq_plan* plan, int32_t enable) {
+  if (!plan) return fail(SLQ_ERR_ARG, "plan is NULL");
+  plan->p.prof = enable != 0;
+  plan->p.ev_used = 0;
+  plan->p.prof_flops = 0.0;
+  return SLQ_OK;
+}
+
+int slq_profile_read(slq_plan* plan, double* ms, int64_t* launches, double* flops) {
+  if (!plan || !ms || !launches || !flops) return fail(SLQ_ERR_ARG, "NULL argument");
+  Plan& p = plan->p;
+  SLQ_HIP(hipSetDevice(p.device));
+  double tot = 0.0;
+  for (size_t k = 0; k + 1 < p.ev_used; k += 2) {
+    SLQ_HIP(hipEventSynchronize(p.ev[k + 1]));
+    float t = 0.f;
+    SLQ_HIP(hipEventElapsedTime(&t, p.ev[k], p.ev[k + 1]));
+    tot += t;
+  }
+  *ms = tot;
+  *launches = (int64_t)(p.ev_used / 2);
+  *flops = p.prof_flops;
+  p.ev_used = 0;
+  p.prof_flops = 0.0;
+  return SLQ_OK;
+}
+
+int slq_plan_destroy(slq_plan* plan) {
+  if (!plan) return SLQ_OK;
+  hipSetDevice(plan->p.device);
+  hipDeviceSynchronize();
+  for (hipEvent_t e : plan->p.ev) hipEventDestroy(e);
+  hipFree(plan->p.base);
+  delete plan;
+  return SLQ_OK;
+}
+
+int slq_plan_bytes(const slq_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(SLQ_ERR_ARG, "NULL argument");
+  *bytes = plan->p.bytes;
+  return SLQ_OK;
+}
+
+int slq_kinetic(slq_plan* plan, int32_t inverse, double* d_out, hipStream_t stream) {
+  if (!plan || !d_out) return fail(SLQ_ERR_ARG, "NULL argument");
+  Plan& p = plan->p;
+  SLQ_HIP(hipSetDevice(p.device));
+  return copy_f64(inverse ? p.Einv : p.E, d_out, (long)p.n * p.n, stream);
+}
+
+int slq_weight(slq_plan* plan, int32_t batch, const int8_t* d_s, double* d_logabs, int8_t* d_sign,
+               int32_t* d_status, hipStream_t stream) {
+  return weight_or_green(plan, batch, d_s, nullptr, d_logabs, d_sign, d_status, stream);
+}
+
+int slq_green(slq_plan* plan, int32_t batch, const int8_t* d_s, double* d_G, double* d_logabs, int8_t* d_sign,
+              int32_t* d_status, hipStream_t stream) {
+  if (!d_G) return fail(SLQ_ERR_ARG, "d_G must not be NULL");
+  return weight_or_green(plan, batch, d_s, d_G, d_logabs, d_sign, d_status, stream);
+}
+
+int slq_udv(slq_plan* plan, int32_t batch, const int8_t* d_s, int32_t slice0, double* d_U, double* d_D,
+            double* d_V, int32_t* d_status, hipStream_t stream) {
+  if (!plan) return fail(SLQ_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  SLQ_TRY(check_batch(p, batch));
+  if (batch == 0) return SLQ_OK;
+  if (!d_s || !d_U || !d_D || !d_V) return fail(SLQ_ERR_ARG, "NULL device pointer");
+  if (slice0 < 0 || slice0 >= p.L) return fail(SLQ_ERR_ARG, "slice0 must be in [0, L)");
+  SLQ_HIP(hipSetDevice(p.device));
+  int32_t* status = d_status ? d_status : p.status;
+  SLQ_TRY(fill_i32(status, batch, 0, stream));
+  SLQ_TRY(launch_check_spins(p, batch, d_s, status, stream));
+  SLQ_TRY(run_chain(p, batch, d_s, slice0, status, stream));
+  const long NN = (long)p.n * p.n;
+  SLQ_TRY(copy_f64(p.U, d_U, NN * batch, stream));
+  SLQ_TRY(copy_f64(p.D, d_D, (long)p.n * batch, stream));
+  SLQ_TRY(copy_f64(p.V, d_V, NN * batch, stream));
+  return SLQ_OK;
+}
+
+int slq_sweep_local(slq_plan* plan, int32_t batch, int8_t* d_s, double* d_G, double* d_logabs, int8_t* d_sign,
+                    int32_t n_sweeps, uint64_t seed, uint64_t sweep0, uint64_t chain0, int64_t* d_accepts,
+                    double* d_drift, int32_t* d_status, hipStream_t st) {
+  if (!plan) return fail(SLQ_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  SLQ_TRY(check_batch(p, batch));
+  if (batch == 0 || n_sweeps == 0) return SLQ_OK;
+  if (n_sweeps < 0) return fail(SLQ_ERR_ARG, "n_sweeps must be >= 0");
+  if (!d_s || !d_G || !d_logabs || !d_sign) return fail(SLQ_ERR_ARG, "NULL device pointer");
+  SLQ_HIP(hipSetDevice(p.device));
+  const int N = p.n, L = p.L;
+  const long NN = (long)N * N;
+  int32_t* status = d_status ? d_status : p.status;
+  int64_t* acc = d_accepts ? d_accepts : p.ivec;
+  double* drift = d_drift ? d_drift : p.dvec2;
+  SLQ_TRY(fill_i32(status, batch, 0, st));
+  SLQ_TRY(launch_check_spins(p, batch, d_s, status, st));
+  SLQ_TRY(fill_i64(acc, batch, 0, st));
+  SLQ_TRY(fill_f64(drift, batch, 0.0, st));
+  GemmArgs w1{};
+  w1.M = N;
+  w1.N = N;
+  w1.K = N;
+  w1.A = p.E;
+  w1.lda = N;
+  w1.strideA = 0;
+  w1.B = d_G;
+  w1.ldb = N;
+  w1.strideB = NN;
+  w1.C = p.Xa;
+  w1.ldc = N;
+  w1.strideC = NN;
+  w1.S = d_s;
+  w1.strideS = (long)L * N;
+  w1.inv_scale = 0;
+  w1.consts = p.consts;
+  w1.alpha = 1.0;
+  w1.batch = batch;
+  GemmArgs w2 = w1;  // G <- T diag(1/d_l) E^{-1}
+  w2.A = p.Xa;
+  w2.strideA = NN;
+  w2.B = p.Einv;
+  w2.strideB = 0;
+  w2.C = d_G;
+  w2.inv_scale = 1;
+  for (int k = 0; k < n_sweeps; ++k) {
+    for (int l = 1; l <= L; ++l) {
+      SLQ_TRY(launch_flip_slice(p, batch, d_s, d_G, d_logabs, d_sign, l - 1, seed, sweep0 + k, chain0, acc, st));
+      w1.slice = l - 1;
+      w2.slice = l - 1;
+      SLQ_TRY(launch_gemm(w1, false, false, st));
+      SLQ_TRY(launch_gemm(w2, false, false, st));
+      if (l % p.m.n_stab == 0) {
+        SLQ_TRY(run_chain(p, batch, d_s, l % L, status, st));
+        SLQ_TRY(launch_finish(p, batch, p.Xa, p.dvec, p.sgn_work, status, st));
+        SLQ_TRY(launch_drift(p, batch, d_G, p.Xa, drift, st));
+      }
+    }
+  }
+  return SLQ_OK;
+}
+
+}  // extern "C"

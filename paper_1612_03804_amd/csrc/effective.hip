@@ -1,0 +1,519 @@
+// Effective bosonic action and the moves, features, acceptance and fit built
+// on it ("Formalism of SLDQMC", Eqs. 2-4, and the R^2 score of "Results").
+//
+//   S_eff(s) = c0 + sum_k lambda_k F_k(s),   F_k = 1/2 sum_x s_x h_k(x),
+//   h_k((i, l)) = sum_{delta in shell r_k} s_{i+delta, l+dl_k} + s_{i+delta, l-dl_k}  (dl_k > 0)
+//               = sum_{delta in shell r_k} s_{i+delta, l}                             (dl_k = 0)
+//
+// A flip of x changes S_eff by dS = -2 s_x sum_k lambda_k h_k(x).  Moves act
+// on colour classes (one slice, one colour of the greedy colouring of the
+// dl = 0 coupling graph), so all sites of a class are updated at once without
+// touching each other's partners; drawing the class at random keeps the
+// effective chain reversible for exp(S_eff), which the cumulative-update
+// acceptance of Eq. 4 relies on.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <set>
+#include <vector>
+
+#include "slq_internal.h"
+
+namespace slq {
+
+
+constexpr int MAX_TERMS = 64;
+constexpr int MAX_SHELL = 5;
+
+// Offsets of shells 0..5, ordered by squared length 0, 1, 2, 4, 5, 8.
+static const int kShellOff[MAX_SHELL + 2] = {0, 1, 5, 9, 13, 21, 25};
+static const int kShellDxy[25][2] = {
+    {0, 0},                                              // 0
+    {1, 0},  {-1, 0}, {0, 1},  {0, -1},                  // 1
+    {1, 1},  {1, -1}, {-1, 1}, {-1, -1},                 // 2
+    {2, 0},  {-2, 0}, {0, 2},  {0, -2},                  // 3
+    {2, 1},  {2, -1}, {-2, 1}, {-2, -1}, {1, 2}, {1, -2}, {-1, 2}, {-1, -2},  // 4
+    {2, 2},  {2, -2}, {-2, 2}, {-2, -2}};                // 5
+
+struct EffDev {
+  int lx, ly, L, N;
+  int n_terms, n_colours, n_classes;
+  const int32_t* terms;      // [K][2]
+  const double* theta;       // [1 + K]
+  const int32_t* col_sites;  // [N]
+  const int32_t* col_off;    // [n_colours + 1]
+  const int32_t* shell_off;  // [7]
+  const int32_t* shell_dxy;  // [25][2]
+};
+
+static EffDev dev_view(const Plan& p, const Eff& e) {
+  EffDev d;
+  d.lx = p.m.lx;
+  d.ly = p.m.ly;
+  d.L = p.L;
+  d.N = p.n;
+  d.n_terms = e.n_terms;
+  d.n_colours = e.n_colours;
+  d.n_classes = e.n_classes;
+  d.terms = e.d_terms;
+  d.theta = e.d_theta;
+  d.col_sites = e.d_col_sites;
+  d.col_off = e.d_col_off;
+  d.shell_off = e.d_shell_off;
+  d.shell_dxy = e.d_shell_dxy;
+  return d;
+}
+
+// h_k((i, l)) for one term, l 0-based, s the field of one chain [L][N]
+__device__ __forceinline__ int local_field(const EffDev& d, const int8_t* __restrict__ s, int k, int i, int l) {
+  const int r = d.terms[2 * k], dl = d.terms[2 * k + 1];
+  const int x = i % d.lx, y = i / d.lx;
+  int h = 0;
+  const int lp = (l + dl) % d.L, lm = (l - dl + d.L) % d.L;
+  for (int o = d.shell_off[r]; o < d.shell_off[r + 1]; ++o) {
+    const int xx = ((x + d.shell_dxy[2 * o]) % d.lx + d.lx) % d.lx;
+    const int yy = ((y + d.shell_dxy[2 * o + 1]) % d.ly + d.ly) % d.ly;
+    const int j = xx + d.lx * yy;
+    if (dl == 0) {
+      h += s[(long)l * d.N + j];
+    } else {
+      h += s[(long)lp * d.N + j] + s[(long)lm * d.N + j];
+    }
+  }
+  return h;
+}
+
+// ------------------------------------------------------------ moves ----
+__global__ __launch_bounds__(256) void k_eff_sweep(EffDev d, int8_t* s_all, int n_moves, uint64_t seed,
+                                                   uint64_t step, uint64_t chain0, int64_t* accepts, double* dS_out) {
+  __shared__ double redd[4];
+  __shared__ long long redi[4];
+  const int b = blockIdx.x;
+  int8_t* s = s_all + (long)b * d.L * d.N;
+  const uint64_t chain = chain0 + b;
+  long long acc = 0;
+  double dsum = 0.0;
+  for (int mv = 0; mv < n_moves; ++mv) {
+    const uint32_t cls = philox_below((uint32_t)d.n_classes, 0, (uint64_t)mv, step, chain, seed, TAG_EFFECTIVE);
+    const int colour = (int)(cls % d.n_colours);
+    const int l = (int)(cls / d.n_colours);  // 0-based slice
+    const int beg = d.col_off[colour], end = d.col_off[colour + 1];
+    for (int t = beg + threadIdx.x; t < end; t += blockDim.x) {
+      const int i = d.col_sites[t];
+      double hs = 0.0;
+      for (int k = 0; k < d.n_terms; ++k) hs += d.theta[1 + k] * (double)local_field(d, s, k, i, l);
+      const double sx = (double)s[(long)l * d.N + i];
+      const double dS = -2.0 * sx * hs;
+      const double u = philox_uniform((uint64_t)(1 + (long)l * d.N + i), (uint64_t)mv, step, chain, seed,
+                                      TAG_EFFECTIVE);
+      if (u < exp(dS)) {
+        s[(long)l * d.N + i] = (int8_t)(-s[(long)l * d.N + i]);
+        ++acc;
+        dsum += dS;
+      }
+    }
+    __syncthreads();
+  }
+  dsum = wave_sum(dsum);
+  long long a2 = acc;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a2 += __shfl_xor(a2, o, 64);
+  if ((threadIdx.x & 63) == 0) {
+    redd[threadIdx.x >> 6] = dsum;
+    redi[threadIdx.x >> 6] = a2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (accepts) accepts[b] = redi[0] + redi[1] + redi[2] + redi[3];
+    if (dS_out) dS_out[b] = ((redd[0] + redd[1]) + redd[2]) + redd[3];
+  }
+}
+
+int launch_eff_sweep(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, uint64_t seed, uint64_t step,
+                     uint64_t chain0, int64_t* accepts, double* dS, hipStream_t st) {
+  if (batch <= 0) return SLQ_OK;
+  k_eff_sweep<<<batch, 256, 0, st>>>(dev_view(p, e), s, n_moves, seed, step, chain0, accepts, dS);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+
+// --------------------------------------------------------- features ----
+// F[b][k] = 1/2 sum_x s_x h_k(x); integer sums, exact.
+__global__ __launch_bounds__(256) void k_features(EffDev d, const int8_t* s_all, double* F) {
+  __shared__ long long acc[MAX_TERMS];
+  const long b = blockIdx.x;
+  const int8_t* s = s_all + b * d.L * d.N;
+  for (int k = threadIdx.x; k < d.n_terms; k += blockDim.x) acc[k] = 0;
+  __syncthreads();
+  const long total = (long)d.L * d.N;
+  for (int k = 0; k < d.n_terms; ++k) {
+    long long part = 0;
+    for (long x = threadIdx.x; x < total; x += blockDim.x) {
+      const int l = (int)(x / d.N), i = (int)(x % d.N);
+      part += (long long)s[x] * local_field(d, s, k, i, l);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long*)&acc[k], (unsigned long long)part);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < d.n_terms; k += blockDim.x) F[b * d.n_terms + k] = 0.5 * (double)acc[k];
+}
+
+int launch_features(Plan& p, const Eff& e, long count, const int8_t* s, double* F, hipStream_t st) {
+  if (count <= 0) return SLQ_OK;
+  k_features<<<(unsigned)count, 256, 0, st>>>(dev_view(p, e), s, F);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+
+// ----------------------------------------------------------- accept ----
+// Eq. 4: logA = [ln|W(s')| - ln|W(s)|] - [S_eff(s') - S_eff(s)]
+__global__ __launch_bounds__(256) void k_accept(EffDev d, int8_t* s_all, const int8_t* sp_all, double* logabs,
+                                                int8_t* sign, const double* new_logabs, const int8_t* new_sign,
+                                                const double* F_old, const double* F_new, uint64_t seed,
+                                                uint64_t step, uint64_t chain0, int8_t* accepted, double* logA) {
+  __shared__ int take;
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0) {
+    double dS = 0.0;
+    for (int k = 0; k < d.n_terms; ++k)
+      dS += d.theta[1 + k] * (F_new[(long)b * d.n_terms + k] - F_old[(long)b * d.n_terms + k]);
+    const double la = (new_logabs[b] - logabs[b]) - dS;
+    const double u = philox_uniform(0, 0, step, chain0 + b, seed, TAG_CUMULATIVE);
+    const double lu = (u == 0.0) ? -INFINITY : log(u);
+    const bool ok = new_sign[b] != 0 && lu < fmin(0.0, la);
+    take = ok;
+    if (accepted) accepted[b] = ok ? 1 : 0;
+    if (logA) logA[b] = la;
+    if (ok) {
+      logabs[b] = new_logabs[b];
+      sign[b] = new_sign[b];
+    }
+  }
+  __syncthreads();
+  if (take) {
+    const long total = (long)d.L * d.N;
+    for (long x = threadIdx.x; x < total; x += blockDim.x) s_all[b * total + x] = sp_all[b * total + x];
+  }
+}
+
+int launch_accept(Plan& p, const Eff& e, int batch, int8_t* s, const int8_t* sprop, double* logabs, int8_t* sign,
+                  const double* new_logabs, const int8_t* new_sign, const double* F_old, const double* F_new,
+                  uint64_t seed, uint64_t step, uint64_t chain0, int8_t* accepted, double* logA, hipStream_t st) {
+  if (batch <= 0) return SLQ_OK;
+  k_accept<<<batch, 256, 0, st>>>(dev_view(p, e), s, sprop, logabs, sign, new_logabs, new_sign, F_old, F_new, seed,
+                                  step, chain0, accepted, logA);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+
+// -------------------------------------------------------------- fit ----
+// OLS with an intercept on centred features: lambda = (Fc^T Fc)^{-1} Fc^T yc,
+// c0 = ybar - Fbar . lambda; R^2 from the explicit residuals.  One workgroup,
+// fixed summation order (deterministic).
+constexpr int FIT_THREADS = 1024;
+
+__global__ __launch_bounds__(FIT_THREADS) void k_fit(long n, int K, const double* __restrict__ F,
+                                                     const double* __restrict__ y, double* theta, double* r2) {
+  __shared__ double mean[MAX_TERMS + 1];
+  __shared__ double A[MAX_TERMS][MAX_TERMS + 1];
+  __shared__ double rhs[MAX_TERMS];
+  __shared__ double red[FIT_THREADS / 64];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  // means (one thread per column, sequential over samples)
+  for (int k = tid; k <= K; k += FIT_THREADS) {
+    double s = 0.0;
+    for (long i = 0; i < n; ++i) s += (k < K) ? F[i * K + k] : y[i];
+    mean[k] = s / (double)n;
+  }
+  __syncthreads();
+  // centred Gram matrix and right-hand side
+  const int npair = K * (K + 1) / 2;
+  for (int pr = tid; pr < npair + K; pr += FIT_THREADS) {
+    if (pr < npair) {
+      int k1 = 0, rem = pr;
+      while (rem >= K - k1) {
+        rem -= K - k1;
+        ++k1;
+      }
+      const int k2 = k1 + rem;
+      double s = 0.0;
+      for (long i = 0; i < n; ++i) s += (F[i * K + k1] - mean[k1]) * (F[i * K + k2] - mean[k2]);
+      A[k1][k2] = s;
+      A[k2][k1] = s;
+    } else {
+      const int k = pr - npair;
+      double s = 0.0;
+      for (long i = 0; i < n; ++i) s += (F[i * K + k] - mean[k]) * (y[i] - mean[K]);
+      rhs[k] = s;
+    }
+  }
+  __syncthreads();
+  // Cholesky A = L L^T in place (lower part)
+  for (int j = 0; j < K; ++j) {
+    if (tid == 0) {
+      double djj = A[j][j];
+      for (int m = 0; m < j; ++m) djj -= A[j][m] * A[j][m];
+      if (!(djj > 0.0)) {
+        bad = 1;
+        djj = 1.0;
+      }
+      A[j][j] = sqrt(djj);
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < K; i += FIT_THREADS) {
+      double v = A[i][j];
+      for (int m = 0; m < j; ++m) v -= A[i][m] * A[j][m];
+      A[i][j] = v / A[j][j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double z[MAX_TERMS];
+    for (int i = 0; i < K; ++i) {
+      double v = rhs[i];
+      for (int m = 0; m < i; ++m) v -= A[i][m] * z[m];
+      z[i] = v / A[i][i];
+    }
+    for (int i = K - 1; i >= 0; --i) {
+      double v = z[i];
+      for (int m = i + 1; m < K; ++m) v -= A[m][i] * rhs[m];
+      rhs[i] = v / A[i][i];  // lambda_i (rhs reused, filled from the back)
+    }
+    double c0 = mean[K];
+    for (int k = 0; k < K; ++k) c0 -= mean[k] * rhs[k];
+    theta[0] = bad ? NAN : c0;
+    for (int k = 0; k < K; ++k) theta[1 + k] = bad ? NAN : rhs[k];
+  }
+  __syncthreads();
+  // R^2 from explicit residuals
+  double ssr = 0.0, sst = 0.0;
+  for (long i = tid; i < n; i += FIT_THREADS) {
+    double yh = theta[0];
+    for (int k = 0; k < K; ++k) yh += theta[1 + k] * F[i * K + k];
+    const double e = y[i] - yh, c = y[i] - mean[K];
+    ssr += e * e;
+    sst += c * c;
+  }
+  ssr = wave_sum(ssr);
+  sst = wave_sum(sst);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = ssr;
+  __syncthreads();
+  double tssr = 0.0;
+  for (int w = 0; w < FIT_THREADS / 64; ++w) tssr += red[w];
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = sst;
+  __syncthreads();
+  if (tid == 0) {
+    double tsst = 0.0;
+    for (int w = 0; w < FIT_THREADS / 64; ++w) tsst += red[w];
+    r2[0] = 1.0 - tssr / tsst;
+  }
+}
+
+int launch_fit(Plan& p, const Eff& e, long n, const double* F, const double* y, double* theta, double* r2,
+               hipStream_t st) {
+  k_fit<<<1, FIT_THREADS, 0, st>>>(n, e.n_terms, F, y, theta, r2);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+
+static int efail(int code, const char* msg) {
+  set_error(msg);
+  return code;
+}
+
+}  // namespace slq
+
+using namespace slq;
+
+extern "C" {
+
+int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const double* lambda, double c0,
+                   slq_eff** out) {
+  if (!plan || !out || !terms || !lambda) return efail(SLQ_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  Plan& p = plan->p;
+  if (n_terms < 1 || n_terms > MAX_TERMS) return efail(SLQ_ERR_ARG, "n_terms must be in [1, 64]");
+  const int lx = p.m.lx, ly = p.m.ly, N = p.n, L = p.L;
+  std::vector<std::set<int>> nbr(N);
+  for (int k = 0; k < n_terms; ++k) {
+    const int r = terms[2 * k], dl = terms[2 * k + 1];
+    if (r < 0 || r > MAX_SHELL || dl < 0 || dl > L / 2 || (r == 0 && dl == 0))
+      return efail(SLQ_ERR_ARG, "unusable term (r, dl)");
+    if (dl == 0) {
+      for (int o = kShellOff[r]; o < kShellOff[r + 1]; ++o) {
+        const int dx = ((kShellDxy[o][0] % lx) + lx) % lx, dy = ((kShellDxy[o][1] % ly) + ly) % ly;
+        if (dx == 0 && dy == 0) return efail(SLQ_ERR_ARG, "a term makes a site its own partner on this lattice");
+      }
+      for (int i = 0; i < N; ++i) {
+        const int x = i % lx, y = i / lx;
+        for (int o = kShellOff[r]; o < kShellOff[r + 1]; ++o) {
+          const int j = ((x + kShellDxy[o][0]) % lx + lx) % lx + lx * (((y + kShellDxy[o][1]) % ly + ly) % ly);
+          if (j != i) {
+            nbr[i].insert(j);
+            nbr[j].insert(i);
+          }
+        }
+      }
+    }
+  }
+  // greedy colouring, ascending site index, smallest free colour
+  std::vector<int> col(N, -1);
+  int nc = 0;
+  for (int i = 0; i < N; ++i) {
+    std::set<int> used;
+    for (int j : nbr[i])
+      if (col[j] >= 0) used.insert(col[j]);
+    int c = 0;
+    while (used.count(c)) ++c;
+    col[i] = c;
+    nc = std::max(nc, c + 1);
+  }
+  std::vector<int32_t> sites, off(nc + 1, 0);
+  int maxc = 0;
+  for (int c = 0; c < nc; ++c) {
+    off[c] = (int32_t)sites.size();
+    for (int i = 0; i < N; ++i)
+      if (col[i] == c) sites.push_back(i);
+    maxc = std::max(maxc, (int)sites.size() - off[c]);
+  }
+  off[nc] = (int32_t)sites.size();
+  std::vector<double> theta(1 + n_terms);
+  theta[0] = c0;
+  for (int k = 0; k < n_terms; ++k) theta[1 + k] = lambda[k];
+  std::vector<int32_t> shoff(kShellOff, kShellOff + MAX_SHELL + 2);
+  std::vector<int32_t> shd(2 * 25);
+  for (int o = 0; o < 25; ++o) {
+    shd[2 * o] = kShellDxy[o][0];
+    shd[2 * o + 1] = kShellDxy[o][1];
+  }
+  slq_eff* h = new (std::nothrow) slq_eff();
+  if (!h) return efail(SLQ_ERR_DEVICE, "host allocation failed");
+  Eff& e = h->e;
+  e.plan = &p;
+  e.n_terms = n_terms;
+  e.n_colours = nc;
+  e.n_classes = nc * L;
+  e.max_class = maxc;
+  const size_t b_terms = 8 * n_terms, b_theta = 8 * (1 + n_terms), b_sites = 4 * N, b_off = 4 * (nc + 1),
+               b_shoff = 4 * shoff.size(), b_shd = 4 * shd.size();
+  const size_t o1 = 0, o2 = o1 + (b_terms + 255) / 256 * 256, o3 = o2 + (b_theta + 255) / 256 * 256,
+               o4 = o3 + (b_sites + 255) / 256 * 256, o5 = o4 + (b_off + 255) / 256 * 256,
+               o6 = o5 + (b_shoff + 255) / 256 * 256, total = o6 + (b_shd + 255) / 256 * 256;
+  char* base = nullptr;
+  if (hipSetDevice(p.device) != hipSuccess || hipMalloc((void**)&base, total) != hipSuccess) {
+    delete h;
+    return efail(SLQ_ERR_DEVICE, "hipMalloc failed");
+  }
+  e.d_terms = (int32_t*)(base + o1);
+  e.d_theta = (double*)(base + o2);
+  e.d_col_sites = (int32_t*)(base + o3);
+  e.d_col_off = (int32_t*)(base + o4);
+  e.d_shell_off = (int32_t*)(base + o5);
+  e.d_shell_dxy = (int32_t*)(base + o6);
+  bool ok = hipMemcpy(e.d_terms, terms, b_terms, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(e.d_theta, theta.data(), b_theta, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(e.d_col_sites, sites.data(), b_sites, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(e.d_col_off, off.data(), b_off, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(e.d_shell_off, shoff.data(), b_shoff, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(e.d_shell_dxy, shd.data(), b_shd, hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    hipFree(base);
+    delete h;
+    return efail(SLQ_ERR_DEVICE, "hipMemcpy failed");
+  }
+  *out = h;
+  return SLQ_OK;
+}
+
+int slq_eff_destroy(slq_eff* eff) {
+  if (!eff) return SLQ_OK;
+  hipSetDevice(eff->e.plan->device);
+  hipDeviceSynchronize();
+  hipFree(eff->e.d_terms);
+  delete eff;
+  return SLQ_OK;
+}
+
+int slq_eff_classes(const slq_eff* eff, int32_t* n_classes) {
+  if (!eff || !n_classes) return efail(SLQ_ERR_ARG, "NULL argument");
+  *n_classes = eff->e.n_classes;
+  return SLQ_OK;
+}
+
+int slq_eff_set_theta(slq_eff* eff, const double* d_theta, hipStream_t stream) {
+  if (!eff || !d_theta) return efail(SLQ_ERR_ARG, "NULL argument");
+  SLQ_HIP(hipSetDevice(eff->e.plan->device));
+  return copy_f64(d_theta, eff->e.d_theta, 1 + eff->e.n_terms, stream);
+}
+
+int slq_eff_sweep(slq_plan* plan, const slq_eff* eff, int32_t batch, int8_t* d_s, int32_t n_moves, uint64_t seed,
+                  uint64_t step, uint64_t chain0, int64_t* d_accepts, double* d_dS, hipStream_t stream) {
+  if (!plan || !eff || !d_s) return efail(SLQ_ERR_ARG, "NULL argument");
+  Plan& p = plan->p;
+  if (eff->e.plan != &p) return efail(SLQ_ERR_ARG, "eff belongs to another plan");
+  if (batch < 0 || n_moves < 0) return efail(SLQ_ERR_ARG, "batch and n_moves must be >= 0");
+  SLQ_HIP(hipSetDevice(p.device));
+  return launch_eff_sweep(p, eff->e, batch, d_s, n_moves, seed, step, chain0, d_accepts, d_dS, stream);
+}
+
+int slq_eff_features(slq_plan* plan, const slq_eff* eff, int32_t batch, const int8_t* d_s, double* d_F,
+                     hipStream_t stream) {
+  if (!plan || !eff || !d_s || !d_F) return efail(SLQ_ERR_ARG, "NULL argument");
+  if (eff->e.plan != &plan->p) return efail(SLQ_ERR_ARG, "eff belongs to another plan");
+  if (batch < 0) return efail(SLQ_ERR_ARG, "batch must be >= 0");
+  SLQ_HIP(hipSetDevice(plan->p.device));
+  return launch_features(plan->p, eff->e, batch, d_s, d_F, stream);
+}
+
+int slq_cumulative_step(slq_plan* plan, const slq_eff* eff, int32_t batch, int8_t* d_s, double* d_logabs,
+                        int8_t* d_sign, int32_t n_moves, uint64_t seed, uint64_t step, uint64_t chain0,
+                        int8_t* d_accepted, double* d_logA, int32_t* d_status, hipStream_t stream) {
+  if (!plan || !eff || !d_s || !d_logabs || !d_sign) return efail(SLQ_ERR_ARG, "NULL argument");
+  Plan& p = plan->p;
+  const Eff& e = eff->e;
+  if (e.plan != &p) return efail(SLQ_ERR_ARG, "eff belongs to another plan");
+  int rc = check_batch(p, batch);
+  if (rc != SLQ_OK) return rc;
+  if (batch == 0) return SLQ_OK;
+  if (n_moves < 0) return efail(SLQ_ERR_ARG, "n_moves must be >= 0");
+  SLQ_HIP(hipSetDevice(p.device));
+  const long per = (long)p.L * p.n;
+  int32_t* status = d_status ? d_status : p.status;
+  if ((rc = fill_i32(status, batch, 0, stream)) != SLQ_OK) return rc;
+  if ((rc = copy_i8(d_s, p.s_work, per * batch, stream)) != SLQ_OK) return rc;
+  if ((rc = launch_eff_sweep(p, e, batch, p.s_work, n_moves, seed, step, chain0, nullptr, nullptr, stream)) != SLQ_OK)
+    return rc;
+  if ((rc = launch_features(p, e, batch, d_s, p.F_old, stream)) != SLQ_OK) return rc;
+  if ((rc = launch_features(p, e, batch, p.s_work, p.F_new, stream)) != SLQ_OK) return rc;
+  if ((rc = launch_check_spins(p, batch, d_s, status, stream)) != SLQ_OK) return rc;
+  rc = run_chain(p, batch, p.s_work, 0, status, stream);
+  if (rc == SLQ_OK) rc = launch_finish(p, batch, nullptr, p.dvec, p.sgn_work, status, stream);
+  if (rc != SLQ_OK) return rc;
+  return launch_accept(p, e, batch, d_s, p.s_work, d_logabs, d_sign, p.dvec, p.sgn_work, p.F_old, p.F_new, seed,
+                       step, chain0, d_accepted, d_logA, stream);
+}
+
+int slq_fit_effective(slq_plan* plan, const slq_eff* eff, int64_t n_samples, const int8_t* d_S,
+                      const double* d_logabs, double* d_theta, double* d_r2, hipStream_t stream) {
+  if (!plan || !eff || !d_S || !d_logabs || !d_theta || !d_r2) return efail(SLQ_ERR_ARG, "NULL argument");
+  Plan& p = plan->p;
+  const Eff& e = eff->e;
+  if (e.plan != &p) return efail(SLQ_ERR_ARG, "eff belongs to another plan");
+  if (n_samples < e.n_terms + 2) return efail(SLQ_ERR_ARG, "n_samples must be >= n_terms + 2");
+  SLQ_HIP(hipSetDevice(p.device));
+  double* F = nullptr;
+  if (hipMallocAsync((void**)&F, sizeof(double) * n_samples * e.n_terms, stream) != hipSuccess)
+    return efail(SLQ_ERR_DEVICE, "hipMallocAsync of the feature matrix failed");
+  int rc = launch_features(p, e, n_samples, d_S, F, stream);
+  if (rc == SLQ_OK) rc = launch_fit(p, e, n_samples, F, d_logabs, d_theta, d_r2, stream);
+  hipFreeAsync(F, stream);
+  return rc;
+}
+
+}  // extern "C"

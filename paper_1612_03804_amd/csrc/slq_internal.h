@@ -1,0 +1,211 @@
+// Internal declarations of libslq: the plan, the effective-model handle,
+// device helpers (Philox4x64-10, wavefront reductions) and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/slq.h"
+
+namespace slq {
+
+void set_error(const std::string& msg);
+
+#define SLQ_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::slq::set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+      return SLQ_ERR_DEVICE;                                                       \
+    }                                                                              \
+  } while (0)
+
+#define SLQ_LAUNCHED()                                                             \
+  do {                                                                             \
+    hipError_t e_ = hipGetLastError();                                             \
+    if (e_ != hipSuccess) {                                                        \
+      ::slq::set_error(std::string("kernel launch: ") + hipGetErrorString(e_));    \
+      return SLQ_ERR_DEVICE;                                                       \
+    }                                                                              \
+  } while (0)
+
+// ---------------------------------------------------------------- Philox ----
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 64x64
+// multiplies with the Weyl-sequence key schedule.
+struct u64x4 {
+  uint64_t v[4];
+};
+
+__device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  u64x4 o;
+  o.v[0] = c0;
+  o.v[1] = c1;
+  o.v[2] = c2;
+  o.v[3] = c3;
+  return o;
+}
+
+__device__ __forceinline__ double philox_uniform(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                                 uint64_t k0, uint64_t k1) {
+  return (double)(philox4x64_10(c0, c1, c2, c3, k0, k1).v[0] >> 11) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ uint32_t philox_below(uint32_t n, uint64_t c0, uint64_t c1, uint64_t c2,
+                                                 uint64_t c3, uint64_t k0, uint64_t k1) {
+  const uint64_t w = philox4x64_10(c0, c1, c2, c3, k0, k1).v[0] >> 32;
+  return (uint32_t)((w * (uint64_t)n) >> 32);
+}
+
+enum : uint64_t { TAG_LOCAL = 1, TAG_EFFECTIVE = 2, TAG_CUMULATIVE = 3 };
+
+// ------------------------------------------------------------ reductions ----
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ------------------------------------------------------------------ plan ----
+struct Plan {
+  slq_model m;
+  int n;          // sites N
+  int L;          // slices
+  int max_batch;
+  int device;
+  size_t bytes;
+  double* base;   // single allocation holding everything below
+  double* E;      // [N][N] exp(-dtau K)
+  double* Einv;   // [N][N] exp(+dtau K)
+  double* consts; // [0] exp(-dtau xi), [1] exp(+dtau xi), [2] exp(dtau mu), [3] exp(-dtau mu)
+  double* tabs;   // 1-D propagator tables, 4*(lx+ly)
+  // per-item N x N buffers
+  double *Xa, *Xb, *W, *U, *V, *Vt;
+  // per-item vectors
+  double *D, *invD, *Tblk;  // D, 1/D: [N]; compact-WY T blocks: [N/nb+1][nb][nb]
+  int32_t* perm;            // [N]
+  int32_t* ipiv;            // [N]
+  int32_t* nref;            // [1] reflectors with tau != 0 in the latest QR
+  int32_t* status;          // [max_batch] scratch status when caller passes NULL
+  int8_t* s_work;           // [max_batch][L][N] proposal fields
+  double* dvec;             // [max_batch] scratch doubles
+  double* dvec2;            // [max_batch] scratch doubles
+  int64_t* ivec;            // [max_batch] scratch counters
+  // local sweeps: delayed-update vectors per item
+  double *dX, *dY;          // [N][KD] and [KD][N]
+  double* dA;               // [KD]
+  // cumulative updates
+  double *F_old, *F_new;    // [max_batch][64] effective-action features
+  int8_t* sgn_work;         // [max_batch]
+  // optional event timing of the chain-product GEMM launches
+  bool prof = false;
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  size_t ev_used = 0;
+  double prof_flops = 0.0;
+};
+
+struct Eff {
+  Plan* plan;
+  int n_terms;
+  int n_colours;
+  int n_classes;
+  int32_t* d_terms;      // [n_terms][2]
+  double* d_theta;       // [1 + n_terms] (c0, lambda)
+  int32_t* d_col_sites;  // sites sorted by colour
+  int32_t* d_col_off;    // [n_colours + 1]
+  int max_class;         // largest colour class
+  int32_t* d_shell_off;  // shell offset table [6 + 1]
+  int32_t* d_shell_dxy;  // [total][2]
+};
+
+constexpr int QR_NB = 16;     // Householder / LU panel width
+constexpr int SWEEP_KD = 32;  // delayed local updates per flush
+
+// ------------------------------------------------------------- launchers ----
+int launch_kinetic(Plan& p, hipStream_t st);
+
+// C[b] = alpha * rowscale[b] o (op(A[b]) * diag(r_b) * op(B[b])) + beta * C[b]
+struct GemmArgs {
+  int M, N, K;
+  const double* A;
+  long lda, strideA;
+  const double* B;
+  long ldb, strideB;
+  double* C;
+  long ldc, strideC;
+  const int8_t* S;    // field: r_b[k] = consts[s > 0 ? 0 : 1] ^ (+1 or -1); null = no scaling
+  long strideS;
+  int slice;          // 0-based slice of S used for the scaling
+  int inv_scale;      // 0: r = exp(-dtau xi s), 1: r = exp(+dtau xi s)
+  const double* consts;
+  const double* rowscale;  // null = none
+  long strideRS;
+  double alpha, beta;
+  int a_upper;        // A is upper triangular: entries with k < m are taken as zero
+  int batch;
+};
+int launch_gemm(const GemmArgs& a, bool transA, bool transB, hipStream_t st);
+
+// Chain helpers
+int launch_first_slice(Plan& p, int batch, const int8_t* s, long strideS, int slice, double* X, hipStream_t st);
+int launch_set_identity(Plan& p, int batch, double* X, hipStream_t st);
+int launch_qr(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st);  // X -> W, U, D, invD, perm
+int launch_permute_rows(Plan& p, int batch, const double* V, double* Vt, hipStream_t st);
+int launch_finish(Plan& p, int batch, double* G, double* logabs, int8_t* sign, int32_t* status, hipStream_t st);
+int launch_check_spins(Plan& p, int batch, const int8_t* s, int32_t* status, hipStream_t st);
+
+int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, hipStream_t st);
+int check_batch(const Plan& p, long batch);
+int fill_f64(double* x, long n, double v, hipStream_t st);
+int fill_i32(int32_t* x, long n, int32_t v, hipStream_t st);
+int fill_i64(int64_t* x, long n, int64_t v, hipStream_t st);
+int copy_f64(const double* a, double* b, long n, hipStream_t st);
+int copy_i8(const int8_t* a, int8_t* b, long n, hipStream_t st);
+
+// Local sweeps
+int launch_flip_slice(Plan& p, int batch, int8_t* s, double* G, double* logabs, int8_t* sign, int slice,
+                      uint64_t seed, uint64_t sweep, uint64_t chain0, int64_t* accepts, hipStream_t st);
+int launch_drift(Plan& p, int batch, double* Gw, const double* Gf, double* drift, hipStream_t st);
+
+// Effective model
+int launch_eff_sweep(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, uint64_t seed, uint64_t step,
+                     uint64_t chain0, int64_t* accepts, double* dS, hipStream_t st);
+int launch_features(Plan& p, const Eff& e, long count, const int8_t* s, double* F, hipStream_t st);
+int launch_accept(Plan& p, const Eff& e, int batch, int8_t* s, const int8_t* sprop, double* logabs, int8_t* sign,
+                  const double* new_logabs, const int8_t* new_sign, const double* F_old, const double* F_new,
+                  uint64_t seed, uint64_t step, uint64_t chain0, int8_t* accepted, double* logA, hipStream_t st);
+int launch_fit(Plan& p, const Eff& e, long n, const double* F, const double* y, double* theta, double* r2,
+               hipStream_t st);
+
+}  // namespace slq
+
+struct slq_plan {
+  slq::Plan p;
+};
+struct slq_eff {
+  slq::Eff e;
+};

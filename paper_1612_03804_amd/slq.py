@@ -1,0 +1,298 @@
+"""ctypes binding of libslq (argument marshalling only).
+
+Every function forwards to the C entry point of the same name in
+include/slq.h; tensors are passed as raw device pointers together with the
+current torch stream.  The library must have been built
+(``python -m paper_1612_03804_amd.build``); loading fails loudly otherwise.
+There is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libslq.so")
+
+SLQ_OK, SLQ_ERR_ARG, SLQ_ERR_DEVICE, SLQ_ERR_WORKSPACE, SLQ_ERR_NUMERIC = 0, -1, -2, -3, -4
+SLQ_ST_BAD_SPIN, SLQ_ST_NONFINITE, SLQ_ST_SINGULAR = 1, 2, 4
+
+# every exported symbol of include/slq.h
+EXPORTS = (
+    "slq_version", "slq_last_error", "slq_plan_create", "slq_plan_destroy", "slq_plan_bytes", "slq_kinetic",
+    "slq_profile_enable", "slq_profile_read",
+    "slq_weight", "slq_green", "slq_udv", "slq_sweep_local", "slq_eff_create", "slq_eff_destroy",
+    "slq_eff_classes", "slq_eff_set_theta", "slq_eff_sweep", "slq_eff_features", "slq_cumulative_step",
+    "slq_fit_effective",
+)
+
+
+class SlqError(RuntimeError):
+    pass
+
+
+class slq_model(C.Structure):
+    _fields_ = [("lx", C.c_int32), ("ly", C.c_int32), ("n_slices", C.c_int32), ("n_stab", C.c_int32),
+                ("t", C.c_double), ("mu", C.c_double), ("dtau", C.c_double), ("xi", C.c_double)]
+
+    @classmethod
+    def of(cls, m) -> "slq_model":
+        return cls(m.lx, m.ly, m.n_slices, m.n_stab, m.t, m.mu, m.dtau, m.xi)
+
+
+_lib = None
+P = C.c_void_p
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libslq.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise SlqError(f"{path} is missing: build it with `python -m paper_1612_03804_amd.build`")
+    lib = C.CDLL(path)
+    i32, u64, i64, dbl = C.c_int32, C.c_uint64, C.c_int64, C.c_double
+    sig = {
+        "slq_version": ([], C.c_char_p),
+        "slq_last_error": ([], C.c_char_p),
+        "slq_plan_create": ([C.POINTER(slq_model), i32, C.POINTER(P)], C.c_int),
+        "slq_plan_destroy": ([P], C.c_int),
+        "slq_plan_bytes": ([P, C.POINTER(C.c_size_t)], C.c_int),
+        "slq_kinetic": ([P, i32, P, P], C.c_int),
+        "slq_profile_enable": ([P, i32], C.c_int),
+        "slq_profile_read": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int),
+        "slq_weight": ([P, i32, P, P, P, P, P], C.c_int),
+        "slq_green": ([P, i32, P, P, P, P, P, P], C.c_int),
+        "slq_udv": ([P, i32, P, i32, P, P, P, P, P], C.c_int),
+        "slq_sweep_local": ([P, i32, P, P, P, P, i32, u64, u64, u64, P, P, P, P], C.c_int),
+        "slq_eff_create": ([P, i32, P, P, dbl, C.POINTER(P)], C.c_int),
+        "slq_eff_destroy": ([P], C.c_int),
+        "slq_eff_classes": ([P, C.POINTER(i32)], C.c_int),
+        "slq_eff_set_theta": ([P, P, P], C.c_int),
+        "slq_eff_sweep": ([P, P, i32, P, i32, u64, u64, u64, P, P, P], C.c_int),
+        "slq_eff_features": ([P, P, i32, P, P, P], C.c_int),
+        "slq_cumulative_step": ([P, P, i32, P, P, P, i32, u64, u64, u64, P, P, P, P], C.c_int),
+        "slq_fit_effective": ([P, P, i64, P, P, P, P, P], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != SLQ_OK:
+        raise SlqError(f"libslq error {rc}: {load_library().slq_last_error().decode()}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise SlqError("libslq takes device tensors only")
+    if not t.is_contiguous():
+        raise SlqError("libslq takes contiguous tensors only")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, shape, name):
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape):
+        raise SlqError(f"{name}: expected {dtype} {tuple(shape)}, got {t.dtype} {tuple(t.shape)}")
+
+
+# ------------------------------------------------------------------ plan ----
+class Plan:
+    """Owns an slq_plan (device workspace for one model and max_batch fields)."""
+
+    def __init__(self, model, max_batch: int):
+        lib = load_library()
+        self.model = model
+        self.n = model.lx * model.ly
+        self.L = model.n_slices
+        self.max_batch = max_batch
+        self._m = slq_model.of(model)
+        h = C.c_void_p()
+        _check(lib.slq_plan_create(C.byref(self._m), max_batch, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().slq_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nbytes(self) -> int:
+        v = C.c_size_t()
+        _check(load_library().slq_plan_bytes(self.handle, C.byref(v)))
+        return v.value
+
+
+def slq_plan_create(model, max_batch: int) -> Plan:
+    return Plan(model, max_batch)
+
+
+def slq_plan_destroy(plan: Plan):
+    plan.close()
+
+
+def slq_kinetic(plan: Plan, inverse: bool, out, stream=None):
+    _need(out, torch.float64, (plan.n, plan.n), "out")
+    _check(load_library().slq_kinetic(plan.handle, int(bool(inverse)), _ptr(out), _stream(stream)))
+
+
+def slq_profile_enable(plan: Plan, enable: bool = True):
+    _check(load_library().slq_profile_enable(plan.handle, int(bool(enable))))
+
+
+def slq_profile_read(plan: Plan):
+    """(summed ms, launches, algorithmic flops) of the timed chain-product GEMMs."""
+    ms, n, fl = C.c_double(), C.c_int64(), C.c_double()
+    _check(load_library().slq_profile_read(plan.handle, C.byref(ms), C.byref(n), C.byref(fl)))
+    return ms.value, n.value, fl.value
+
+
+def slq_weight(plan: Plan, s, logabs, sign, status=None, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(logabs, torch.float64, (b,), "logabs")
+    _need(sign, torch.int8, (b,), "sign")
+    if status is not None:
+        _need(status, torch.int32, (b,), "status")
+    _check(load_library().slq_weight(plan.handle, b, _ptr(s), _ptr(logabs), _ptr(sign), _ptr(status),
+                                      _stream(stream)))
+
+
+def slq_green(plan: Plan, s, G, logabs, sign, status=None, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(G, torch.float64, (b, plan.n, plan.n), "G")
+    _need(logabs, torch.float64, (b,), "logabs")
+    _need(sign, torch.int8, (b,), "sign")
+    if status is not None:
+        _need(status, torch.int32, (b,), "status")
+    _check(load_library().slq_green(plan.handle, b, _ptr(s), _ptr(G), _ptr(logabs), _ptr(sign), _ptr(status),
+                                     _stream(stream)))
+
+
+def slq_udv(plan: Plan, s, slice0: int, U, D, V, status=None, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(U, torch.float64, (b, plan.n, plan.n), "U")
+    _need(D, torch.float64, (b, plan.n), "D")
+    _need(V, torch.float64, (b, plan.n, plan.n), "V")
+    _check(load_library().slq_udv(plan.handle, b, _ptr(s), int(slice0), _ptr(U), _ptr(D), _ptr(V), _ptr(status),
+                                   _stream(stream)))
+
+
+def slq_sweep_local(plan: Plan, s, G, logabs, sign, n_sweeps: int, seed: int, sweep0: int, chain0: int,
+                    accepts, drift, status=None, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(G, torch.float64, (b, plan.n, plan.n), "G")
+    _need(accepts, torch.int64, (b,), "accepts")
+    _need(drift, torch.float64, (b,), "drift")
+    _check(load_library().slq_sweep_local(plan.handle, b, _ptr(s), _ptr(G), _ptr(logabs), _ptr(sign),
+                                           int(n_sweeps), seed, sweep0, chain0, _ptr(accepts), _ptr(drift),
+                                           _ptr(status), _stream(stream)))
+
+
+# ------------------------------------------------------- effective model ----
+class Eff:
+    """Owns an slq_eff (terms, couplings and colour classes on the device)."""
+
+    def __init__(self, plan: Plan, terms, lam, c0: float = 0.0):
+        import numpy as np
+        lib = load_library()
+        self.plan = plan
+        self.terms = [tuple(int(v) for v in t) for t in terms]
+        t = np.ascontiguousarray(np.array(self.terms, dtype=np.int32).reshape(-1, 2))
+        lm = np.ascontiguousarray(np.asarray(lam, dtype=np.float64).reshape(-1))
+        if len(lm) != len(self.terms):
+            raise SlqError("lambda must have one entry per term")
+        h = C.c_void_p()
+        _check(lib.slq_eff_create(plan.handle, len(self.terms), t.ctypes.data_as(C.c_void_p),
+                                  lm.ctypes.data_as(C.c_void_p), float(c0), C.byref(h)))
+        self.handle = h
+        self.n_terms = len(self.terms)
+
+    @property
+    def n_classes(self) -> int:
+        v = C.c_int32()
+        _check(load_library().slq_eff_classes(self.handle, C.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().slq_eff_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def slq_eff_create(plan: Plan, terms, lam, c0: float = 0.0) -> Eff:
+    return Eff(plan, terms, lam, c0)
+
+
+def slq_eff_destroy(eff: Eff):
+    eff.close()
+
+
+def slq_eff_set_theta(eff: Eff, theta, stream=None):
+    _need(theta, torch.float64, (1 + eff.n_terms,), "theta")
+    _check(load_library().slq_eff_set_theta(eff.handle, _ptr(theta), _stream(stream)))
+
+
+def slq_eff_sweep(plan: Plan, eff: Eff, s, n_moves: int, seed: int, step: int, chain0: int,
+                  accepts=None, dS=None, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _check(load_library().slq_eff_sweep(plan.handle, eff.handle, b, _ptr(s), int(n_moves), seed, step, chain0,
+                                         _ptr(accepts), _ptr(dS), _stream(stream)))
+
+
+def slq_eff_features(plan: Plan, eff: Eff, s, F, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(F, torch.float64, (b, eff.n_terms), "F")
+    _check(load_library().slq_eff_features(plan.handle, eff.handle, b, _ptr(s), _ptr(F), _stream(stream)))
+
+
+def slq_cumulative_step(plan: Plan, eff: Eff, s, logabs, sign, n_moves: int, seed: int, step: int, chain0: int,
+                        accepted=None, logA=None, status=None, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(logabs, torch.float64, (b,), "logabs")
+    _need(sign, torch.int8, (b,), "sign")
+    _check(load_library().slq_cumulative_step(plan.handle, eff.handle, b, _ptr(s), _ptr(logabs), _ptr(sign),
+                                               int(n_moves), seed, step, chain0, _ptr(accepted), _ptr(logA),
+                                               _ptr(status), _stream(stream)))
+
+
+def slq_fit_effective(plan: Plan, eff: Eff, S, logabs, theta, r2, stream=None):
+    n = S.shape[0]
+    _need(S, torch.int8, (n, plan.L, plan.n), "S")
+    _need(logabs, torch.float64, (n,), "logabs")
+    _need(theta, torch.float64, (1 + eff.n_terms,), "theta")
+    _need(r2, torch.float64, (1,), "r2")
+    _check(load_library().slq_fit_effective(plan.handle, eff.handle, n, _ptr(S), _ptr(logabs), _ptr(theta),
+                                             _ptr(r2), _stream(stream)))
