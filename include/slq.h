@@ -59,12 +59,23 @@ enum {
   SLQ_ST_SINGULAR = 4     /* the final matrix M has a zero pivot (W_f = 0) */
 };
 
+/* Operand precision of the chain product X <- E diag(d_l) X.  The QR/UDV
+ * stabilisation, the final LU, log-det and G are FP64 in every mode; in the
+ * reduced modes E and X are rounded to the operand type at every GEMM, the
+ * matrix cores accumulate in FP32 and X is kept in FP32 between slices. */
+enum {
+  SLQ_PREC_FP64 = 0,
+  SLQ_PREC_FP32 = 1,
+  SLQ_PREC_BF16 = 2
+};
+
 typedef struct slq_model {
   int32_t lx, ly;      /* lattice extents, >= 1 each, N = lx*ly <= 2400 */
   int32_t n_slices;    /* L >= 1 */
   int32_t n_stab;      /* slices multiplied between QR stabilisations, >= 1 */
   double t, mu;        /* hopping and chemical potential */
   double dtau, xi;     /* slice width (> 0) and Ising-fermion coupling */
+  int32_t chain_prec;  /* SLQ_PREC_*: operand precision of the chain GEMMs */
 } slq_model;
 
 typedef struct slq_plan slq_plan;

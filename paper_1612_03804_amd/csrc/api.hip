@@ -83,6 +83,8 @@ static int check_model(const slq_model* m) {
   if (!(m->dtau > 0.0) || !std::isfinite(m->dtau)) return fail(SLQ_ERR_ARG, "dtau must be positive and finite");
   if (!std::isfinite(m->t) || !std::isfinite(m->mu) || !std::isfinite(m->xi))
     return fail(SLQ_ERR_ARG, "t, mu and xi must be finite");
+  if (m->chain_prec < SLQ_PREC_FP64 || m->chain_prec > SLQ_PREC_BF16)
+    return fail(SLQ_ERR_ARG, "chain_prec must be SLQ_PREC_FP64, SLQ_PREC_FP32 or SLQ_PREC_BF16");
   return SLQ_OK;
 }
 
@@ -93,8 +95,9 @@ int check_batch(const Plan& p, long batch) {
 }
 
 // One chain-product GEMM X <- E diag(d_l) X, bracketed by events when timing is on.
-static int timed_chain_gemm(Plan& p, const GemmArgs& g, hipStream_t st) {
-  if (!p.prof) return launch_gemm(g, false, false, st);
+template <typename F>
+static int timed_chain(Plan& p, double flops, hipStream_t st, F launch) {
+  if (!p.prof) return launch();
   if (p.ev_used + 2 > p.ev.size()) {
     for (int k = 0; k < 64; ++k) {
       hipEvent_t e;
@@ -105,10 +108,20 @@ static int timed_chain_gemm(Plan& p, const GemmArgs& g, hipStream_t st) {
   hipEvent_t a = p.ev[p.ev_used], b = p.ev[p.ev_used + 1];
   p.ev_used += 2;
   SLQ_HIP(hipEventRecord(a, st));
-  int rc = launch_gemm(g, false, false, st);
+  int rc = launch();
   SLQ_HIP(hipEventRecord(b, st));
-  p.prof_flops += 2.0 * (double)g.M * g.N * g.K * g.batch;
+  p.prof_flops += flops;
   return rc;
+}
+
+static int timed_chain_gemm(Plan& p, const GemmArgs& g, hipStream_t st) {
+  return timed_chain(p, 2.0 * (double)g.M * g.N * g.K * g.batch, st,
+                     [&]() { return launch_gemm(g, false, false, st); });
+}
+
+static int timed_chain_lp(Plan& p, const LpArgs& g, bool b_is_f64, hipStream_t st) {
+  return timed_chain(p, 2.0 * (double)g.M * g.N * g.K * g.batch, st,
+                     [&]() { return launch_gemm_lp(g, p.m.chain_prec, b_is_f64, st); });
 }
 
 // U D V of the cyclic chain B_{k(L)} ... B_{k(1)} with k(j) = (slice0 + j - 1) mod L + 1,
@@ -137,27 +150,68 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
   g.alpha = 1.0;
   g.beta = 0.0;
   g.batch = batch;
+  LpArgs h{};
+  h.M = N;
+  h.N = N;
+  h.K = N;
+  h.A = p.E32;
+  h.lda = N;
+  h.ldb = N;
+  h.strideB = NN;
+  h.ldc = N;
+  h.strideC = NN;
+  h.S = s;
+  h.strideS = strideS;
+  h.consts = p.consts;
+  h.batch = batch;
+  const bool lp = p.m.chain_prec != SLQ_PREC_FP64;
   for (int j0 = 0; j0 < L; j0 += ns) {
     const int jend = std::min(j0 + ns, L);
     double* cur = p.Xa;
     double* oth = p.Xb;
-    int j = j0;
-    if (j0 == 0) {
-      SLQ_TRY(launch_first_slice(p, batch, s, strideS, (slice0 + 0) % L, cur, st));
+    if (!lp) {
+      if (j0 == 0) {
+        SLQ_TRY(launch_first_slice(p, batch, s, strideS, (slice0 + 0) % L, cur, st));
+      } else {
+        g.B = p.U;
+        g.C = cur;
+        g.slice = (slice0 + j0) % L;
+        SLQ_TRY(timed_chain_gemm(p, g, st));
+      }
+      for (int j = j0 + 1; j < jend; ++j) {
+        g.B = cur;
+        g.C = oth;
+        g.slice = (slice0 + j) % L;
+        SLQ_TRY(timed_chain_gemm(p, g, st));
+        std::swap(cur, oth);
+      }
     } else {
-      g.B = p.U;
-      g.C = cur;
-      g.slice = (slice0 + j0) % L;
-      SLQ_TRY(timed_chain_gemm(p, g, st));
+      // FP32 / BF16 operands, X kept in FP32 (the FP64 buffers hold it), widened before the QR
+      float* c32 = (float*)p.Xa;
+      float* o32 = (float*)p.Xb;
+      if (j0 == 0) {
+        SLQ_TRY(launch_first_slice_f32(p, batch, s, strideS, (slice0 + 0) % L, c32, st));
+      } else {
+        h.B = p.U;
+        h.C = c32;
+        h.slice = (slice0 + j0) % L;
+        SLQ_TRY(timed_chain_lp(p, h, true, st));
+      }
+      for (int j = j0 + 1; j < jend; ++j) {
+        h.B = c32;
+        h.C = o32;
+        h.slice = (slice0 + j) % L;
+        SLQ_TRY(timed_chain_lp(p, h, false, st));
+        std::swap(c32, o32);
+      }
+      cur = (double*)o32;
+      SLQ_TRY(launch_widen(c32, cur, NN * batch, st));
     }
-    for (j = j0 + 1; j < jend; ++j) {
-      g.B = cur;
-      g.C = oth;
-      g.slice = (slice0 + j) % L;
-      SLQ_TRY(timed_chain_gemm(p, g, st));
-      std::swap(cur, oth);
+    if (N > 64) {
+      SLQ_TRY(launch_qr_blocked(p, batch, cur, status, st));
+    } else {
+      SLQ_TRY(launch_qr(p, batch, cur, status, st));
     }
-    SLQ_TRY(launch_qr(p, batch, cur, status, st));
     SLQ_TRY(launch_permute_rows(p, batch, p.V, p.Vt, st));
     GemmArgs v{};
     v.M = N;
@@ -231,6 +285,7 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
     off += (bytes + 255) / 256 * 256;
     return o;
   };
+  const size_t oE32 = take(4 * NN);
   const size_t oE = take(8 * NN), oEi = take(8 * NN), oTab = take(8 * (2 * (model->lx + model->ly) + 8)),
                oC = take(8 * 8);
   const size_t oXa = take(8 * NN * B), oXb = take(8 * NN * B), oW = take(8 * NN * B), oU = take(8 * NN * B),
@@ -251,6 +306,7 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   p.E = (double*)(c + oE);
   p.Einv = (double*)(c + oEi);
   p.tabs = (double*)(c + oTab);
+  p.E32 = (float*)(c + oE32);
   p.consts = (double*)(c + oC);
   p.Xa = (double*)(c + oXa);
   p.Xb = (double*)(c + oXb);
@@ -276,6 +332,7 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   p.F_new = (double*)(c + oFn);
   p.sgn_work = (int8_t*)(c + oSg);
   int rc = launch_kinetic(p, 0);
+  if (rc == SLQ_OK) rc = launch_narrow(p.E, p.E32, NN, 0);
   if (rc == SLQ_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(SLQ_ERR_DEVICE, "kinetic build failed");
   if (rc != SLQ_OK) {
     hipFree(base);

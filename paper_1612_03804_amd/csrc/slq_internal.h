@@ -103,6 +103,7 @@ struct Plan {
   double* Einv;   // [N][N] exp(+dtau K)
   double* consts; // [0] exp(-dtau xi), [1] exp(+dtau xi), [2] exp(dtau mu), [3] exp(-dtau mu)
   double* tabs;   // 1-D propagator tables, 4*(lx+ly)
+  float* E32;     // [N][N] E in FP32 (reduced-precision chains)
   // per-item N x N buffers
   double *Xa, *Xb, *W, *U, *V, *Vt;
   // per-item vectors
@@ -170,10 +171,34 @@ struct GemmArgs {
 };
 int launch_gemm(const GemmArgs& a, bool transA, bool transB, hipStream_t st);
 
+// Reduced-precision chain GEMM: C(f32)[b] = A(f32, shared) diag(d_slice) B[b] (f32 or f64)
+struct LpArgs {
+  int M, N, K;
+  const float* A;
+  long lda;
+  const void* B;
+  long ldb, strideB;
+  float* C;
+  long ldc, strideC;
+  const int8_t* S;
+  long strideS;
+  int slice;
+  const double* consts;
+  int batch;
+};
+int launch_gemm_lp(const LpArgs& a, int prec, bool b_is_f64, hipStream_t st);
+int launch_first_slice_f32(Plan& p, int batch, const int8_t* s, long strideS, int slice, float* X, hipStream_t st);
+int launch_widen(const float* a, double* b, long n, hipStream_t st);
+int launch_narrow(const double* a, float* b, long n, hipStream_t st);
+
 // Chain helpers
 int launch_first_slice(Plan& p, int batch, const int8_t* s, long strideS, int slice, double* X, hipStream_t st);
 int launch_set_identity(Plan& p, int batch, double* X, hipStream_t st);
-int launch_qr(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st);  // X -> W, U, D, invD, perm
+// X -> W (R above the diagonal), U (Q), D, invD, perm, nref.  launch_qr keeps
+// one workgroup per field for the whole factorisation (small N);
+// launch_qr_blocked factors panels in LDS and updates with MFMA GEMMs.
+int launch_qr(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st);
+int launch_qr_blocked(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st);
 int launch_permute_rows(Plan& p, int batch, const double* V, double* Vt, hipStream_t st);
 int launch_finish(Plan& p, int batch, double* G, double* logabs, int8_t* sign, int32_t* status, hipStream_t st);
 int launch_check_spins(Plan& p, int batch, const int8_t* s, int32_t* status, hipStream_t st);

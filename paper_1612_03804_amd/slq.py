@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libslq.so")
 
 SLQ_OK, SLQ_ERR_ARG, SLQ_ERR_DEVICE, SLQ_ERR_WORKSPACE, SLQ_ERR_NUMERIC = 0, -1, -2, -3, -4
 SLQ_ST_BAD_SPIN, SLQ_ST_NONFINITE, SLQ_ST_SINGULAR = 1, 2, 4
+SLQ_PREC_FP64, SLQ_PREC_FP32, SLQ_PREC_BF16 = 0, 1, 2
 
 # every exported symbol of include/slq.h
 EXPORTS = (
@@ -35,11 +36,12 @@ class SlqError(RuntimeError):
 
 class slq_model(C.Structure):
     _fields_ = [("lx", C.c_int32), ("ly", C.c_int32), ("n_slices", C.c_int32), ("n_stab", C.c_int32),
-                ("t", C.c_double), ("mu", C.c_double), ("dtau", C.c_double), ("xi", C.c_double)]
+                ("t", C.c_double), ("mu", C.c_double), ("dtau", C.c_double), ("xi", C.c_double),
+                ("chain_prec", C.c_int32)]
 
     @classmethod
-    def of(cls, m) -> "slq_model":
-        return cls(m.lx, m.ly, m.n_slices, m.n_stab, m.t, m.mu, m.dtau, m.xi)
+    def of(cls, m, chain_prec: int = 0) -> "slq_model":
+        return cls(m.lx, m.ly, m.n_slices, m.n_stab, m.t, m.mu, m.dtau, m.xi, int(chain_prec))
 
 
 _lib = None
@@ -114,13 +116,14 @@ def _need(t, dtype, shape, name):
 class Plan:
     """Owns an slq_plan (device workspace for one model and max_batch fields)."""
 
-    def __init__(self, model, max_batch: int):
+    def __init__(self, model, max_batch: int, chain_prec: int = 0):
         lib = load_library()
         self.model = model
         self.n = model.lx * model.ly
         self.L = model.n_slices
         self.max_batch = max_batch
-        self._m = slq_model.of(model)
+        self.chain_prec = int(chain_prec)
+        self._m = slq_model.of(model, chain_prec)
         h = C.c_void_p()
         _check(lib.slq_plan_create(C.byref(self._m), max_batch, C.byref(h)))
         self.handle = h
@@ -143,8 +146,8 @@ class Plan:
         return v.value
 
 
-def slq_plan_create(model, max_batch: int) -> Plan:
-    return Plan(model, max_batch)
+def slq_plan_create(model, max_batch: int, chain_prec: int = 0) -> Plan:
+    return Plan(model, max_batch, chain_prec)
 
 
 def slq_plan_destroy(plan: Plan):
