@@ -58,6 +58,79 @@ def cpu_baseline(model, terms, theta, fields, logabs, signs, steps, seed):
                       f"and one exact weight each), {dt:.1f} s"}
 
 
+def ess_rates(slq, plan, eff, s, logabs, sign, status, seed, n_moves, steps, dqmc_chains, sweeps, burn):
+    """Effective independent samples per second of the total magnetisation:
+    cumulative updates (all chains of the plan) against local DQMC sweeps
+    (the first `dqmc_chains` chains, restarted from the same fields)."""
+    import torch
+    from paper_1612_03804_amd.analysis import tau_int_chains
+    dev = s.device
+    B = s.shape[0]
+    s_dq = s[:dqmc_chains].clone()
+    M = torch.empty((steps, B), dtype=torch.int64, device=dev)
+    acc = torch.empty(B, dtype=torch.int8, device=dev)
+    logA = torch.empty(B, dtype=torch.float64, device=dev)
+    for k in range(burn):
+        slq.slq_cumulative_step(plan, eff, s, logabs, sign, n_moves, seed, 10_000 + k, 0, acc, logA, status)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        slq.slq_cumulative_step(plan, eff, s, logabs, sign, n_moves, seed, 20_000 + k, 0, acc, logA, status)
+        slq.slq_magnetization(plan, s, M[k])
+    torch.cuda.synchronize()
+    t_sl = time.perf_counter() - t0
+    tau_sl = tau_int_chains(M.cpu().numpy().T)
+    n = dqmc_chains
+    G = torch.empty((n, plan.n, plan.n), dtype=torch.float64, device=dev)
+    la = torch.empty(n, dtype=torch.float64, device=dev)
+    sg = torch.empty(n, dtype=torch.int8, device=dev)
+    st = torch.empty(n, dtype=torch.int32, device=dev)
+    slq.slq_green(plan, s_dq, G, la, sg, st)
+    a64 = torch.empty(n, dtype=torch.int64, device=dev)
+    drift = torch.empty(n, dtype=torch.float64, device=dev)
+    Md = torch.empty((sweeps, n), dtype=torch.int64, device=dev)
+    slq.slq_sweep_local(plan, s_dq, G, la, sg, burn, seed, 0, 0, a64, drift, st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(sweeps):
+        slq.slq_sweep_local(plan, s_dq, G, la, sg, 1, seed, 1000 + k, 0, a64, drift, st)
+        slq.slq_magnetization(plan, s_dq, Md[k])
+    torch.cuda.synchronize()
+    t_dq = time.perf_counter() - t0
+    tau_dq = tau_int_chains(Md.cpu().numpy().T)
+    ess_sl = B * steps / (2 * tau_sl) / t_sl
+    ess_dq = n * sweeps / (2 * tau_dq) / t_dq
+    return {"sldqmc": {"chains": B, "steps": steps, "tau_int_steps": tau_sl, "ess_per_s": ess_sl,
+                       "steps_per_s": B * steps / t_sl},
+            "dqmc_fp64": {"chains": n, "sweeps": sweeps, "tau_int_sweeps": tau_dq, "ess_per_s": ess_dq,
+                          "sweeps_per_s": n * sweeps / t_dq},
+            "burn_in": burn, "ess_ratio": ess_sl / ess_dq}
+
+
+def group_rate(slq, dev, reps: int = 5):
+    """Exact weights of 64 chains of uneven size (Lx = Ly in {8..24}, L in
+    {40..100}) per second, one graph launch per evaluation."""
+    import torch
+    from slq_inputs import uneven_models, iid_field
+    models = uneven_models(64, 4000)
+    grp = slq.Group(models)
+    s = torch.from_numpy(grp.pack([iid_field(m, 4100 + c) for c, m in enumerate(models)])).to(dev)
+    la = torch.empty(64, dtype=torch.float64, device=dev)
+    sg = torch.empty(64, dtype=torch.int8, device=dev)
+    slq.slq_group_weight(grp, s, la, sg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        slq.slq_group_weight(grp, s, la, sg)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    flops = sum(2.0 * m.n_sites ** 3 * (m.n_slices - 1) for m in models)
+    info = grp.describe()
+    grp.close()
+    return {"evals_per_s": 64 / dt, "ms_per_launch": dt * 1e3, "chain_tflops_effective": flops / dt / 1e12,
+            "batches": len(info["batches"]), "tuned": info["tuned"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +140,11 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-details", action="store_true")
+    ap.add_argument("--ess", action="store_true", help="also measure effective samples/s of both samplers")
+    ap.add_argument("--ess-steps", type=int, default=60)
+    ap.add_argument("--ess-sweeps", type=int, default=40)
+    ap.add_argument("--ess-dqmc-chains", type=int, default=64)
+    ap.add_argument("--ess-burn", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note.",
@@ -169,6 +247,10 @@ def main():
         details["dqmc_chains"] = nb
         details["dqmc_local_acceptance"] = float(acc.sum().item()) / (nb * model.n_sites * model.n_slices)
         details["dqmc_max_drift"] = float(drift.max().item())
+        details["group_64_uneven"] = group_rate(slq, dev)
+    if args.ess:
+        details["ess"] = ess_rates(slq, plan, eff, s, logabs, sign, status, seed, n_moves, args.ess_steps,
+                                   args.ess_dqmc_chains, args.ess_sweeps, args.ess_burn)
     out["details"] = details
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(model, terms, theta_h, fields, la0, sg0, args.cpu_steps, seed)

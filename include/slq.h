@@ -144,6 +144,48 @@ int slq_udv(slq_plan* plan, int32_t batch, const int8_t* d_s, int32_t slice0,
             double* d_U, double* d_D, double* d_V, int32_t* d_status, hipStream_t stream);
 
 /*
+ * slq_magnetization - d_M[b] = sum_{i,l} s_{i,l} (int64) of each field: the
+ * total magnetisation whose autocorrelation C(t) over sweeps or cumulative
+ * updates defines the autocorrelation time (Fig. 1 caption; tau_L in
+ * "Basics of DQMC").  d_s int8 [batch][L][N].
+ */
+int slq_magnetization(slq_plan* plan, int32_t batch, const int8_t* d_s, int64_t* d_M, hipStream_t stream);
+
+/*
+ * Groups of independent chains of uneven size.  slq_group_create takes one
+ * model per chain (N_c and L_c may all differ); chains with identical models
+ * share an internal plan and are evaluated as one batch.  At creation the
+ * tile shape of the FP64 chain GEMM is chosen for every distinct N by timing
+ * the candidate shapes on the device (the choice then applies to every plan
+ * of the process).  Synchronous; free with slq_group_destroy.
+ * Errors: SLQ_ERR_ARG (a model fails the checks of slq_plan_create),
+ * SLQ_ERR_DEVICE.
+ */
+typedef struct slq_group slq_group;
+int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out);
+int slq_group_destroy(slq_group* group);
+/* Packed layouts (host arrays of n_chains + 1 entries): chain c's field is the
+ * int8 [L_c][N_c] block at byte offset s_off[c] of d_s, its G the FP64
+ * [N_c][N_c] block at element offset g_off[c] of d_G; the last entries are
+ * the totals.  g_off may be NULL. */
+int slq_group_layout(const slq_group* group, int64_t* s_off, int64_t* g_off);
+/* JSON text describing the batches and the tuned tile shapes. */
+int slq_group_describe(const slq_group* group, char* buf, size_t len);
+/*
+ * slq_group_weight / slq_group_green - Eq. 1's exact weight (and G) of every
+ * chain: d_logabs, d_sign, d_status [n_chains], d_G packed as above.  The
+ * whole evaluation (gathers, the stabilised chains, QRs and LU of every
+ * batch, scatters) is recorded once as a HIP graph on the group's own stream
+ * for a given set of pointers and replayed as one launch afterwards; it is
+ * ordered after prior work on `stream`, and later work on `stream` waits for
+ * it.  Calls on one group must not overlap in time.
+ */
+int slq_group_weight(slq_group* group, const int8_t* d_s, double* d_logabs, int8_t* d_sign,
+                     int32_t* d_status, hipStream_t stream);
+int slq_group_green(slq_group* group, const int8_t* d_s, double* d_G, double* d_logabs,
+                    int8_t* d_sign, int32_t* d_status, hipStream_t stream);
+
+/*
  * slq_sweep_local - n_sweeps local-update DQMC sweeps ("Basics of DQMC") on
  * `batch` independent chains, in place.  For each slice l = 1..L and site
  * i = 0..N-1 in ascending order the flip s_{i,l} -> -s_{i,l} has ratio
@@ -212,6 +254,49 @@ int slq_eff_sweep(slq_plan* plan, const slq_eff* eff, int32_t batch, int8_t* d_s
 /* slq_eff_features - d_F FP64 [batch][n_terms] = F_k(s_b) (exact half-integers). */
 int slq_eff_features(slq_plan* plan, const slq_eff* eff, int32_t batch,
                      const int8_t* d_s, double* d_F, hipStream_t stream);
+
+/*
+ * Learned effective action (the "..." of Eq. 2: interactions beyond the pair
+ * couplings).  A small convolutional network on the field viewed as
+ * [L][ly][lx], periodic in all three axes:
+ *   a1[c] = b1[c] + sum_k W1[c][k] s(x + o(k)),         h1 = tanh(a1),  c = 0..7
+ *   a2[c] = b2[c] + sum_{c',k} W2[c][c'][k] h1[c'](x + o(k)),  h2 = tanh(a2)
+ *   S_net = b3 + sum_c w3[c] sum_x h2[c](x)
+ * with k = 0..26 and o(k) = (k/9 - 1, (k/3)%3 - 1, k%3 - 1) along (time, y, x).
+ * Parameters: SLQ_NET_PARAMS FP64 values W1[8][27], b1[8], W2[8][8][27],
+ * b2[8], w3[8], b3 (caller-owned device memory).  The learned action is
+ * S_theta = S_lin + S_net; arithmetic in FP32 (net_prec = SLQ_PREC_FP32) or
+ * FP64.  All reductions have a fixed order (deterministic results).
+ */
+#define SLQ_NET_PARAMS 1969
+
+/* d_S[b] = S_net(s_b). */
+int slq_net_forward(slq_plan* plan, int32_t net_prec, int32_t batch, const int8_t* d_s,
+                    const double* d_params, double* d_S, hipStream_t stream);
+/* Gradient of the loss (1/B) sum_b (S_net(s_b) - r_b)^2, r_b = d_y[b] - S_lin(s_b),
+ * S_lin from the linear model of `eff` (its current c0 and lambda): the network
+ * is trained on the residual of the linear fit.  d_grad [SLQ_NET_PARAMS];
+ * d_loss [1] (may be NULL).  1 <= batch <= max_batch. */
+int slq_net_gradient(slq_plan* plan, const slq_eff* eff, int32_t net_prec, int32_t batch,
+                     const int8_t* d_s, const double* d_y, const double* d_params,
+                     double* d_grad, double* d_loss, hipStream_t stream);
+/* One Adam step (Kingma & Ba, with bias correction) of n parameters; t >= 1. */
+int slq_net_adam(int32_t n, double* d_params, const double* d_grad, double* d_m, double* d_v,
+                 int64_t t, double lr, double beta1, double beta2, double eps, hipStream_t stream);
+/*
+ * slq_eff_set_net - attach a copy of the network parameters d_params to `eff`
+ * (or detach with d_params = NULL: the linear model is the fallback).  While
+ * attached, slq_eff_sweep and slq_cumulative_step use S_lin + S_net: the move
+ * classes are one slice and one colour of the greedy colouring of the dl = 0
+ * couplings together with all pairs within spatial Chebyshev distance 4 (a
+ * flip changes h2 within distance 2, so the neighbourhoods touched by the
+ * sites of a class are disjoint), one class drawn uniformly per move as
+ * before; Eq. 4 uses S_net(s') - S_net(s) from full forward passes.  Needs
+ * lx, ly, L >= 5.  The colouring is built on the first attach (synchronous).
+ */
+int slq_eff_set_net(slq_eff* eff, const double* d_params, int32_t net_prec, hipStream_t stream);
+/* Number of move classes while a network is attached. */
+int slq_eff_net_classes(const slq_eff* eff, int32_t* n_classes);
 
 /*
  * slq_cumulative_step - one cumulative update (steps iii-iv, Eq. 4) of each

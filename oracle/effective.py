@@ -119,9 +119,12 @@ def flip_delta(model, terms, lam, s, i: int, l: int) -> float:
     return -2.0 * float(s[l - 1, i]) * tot
 
 
-def spatial_colouring(model, terms):
+def spatial_colouring(model, terms, net_range: int = 0):
     """Greedy colouring of the sites, ascending index, smallest free colour,
-    on the graph linking i to every spatial partner of the dl = 0 terms."""
+    on the graph linking i to every spatial partner of the dl = 0 terms and,
+    when net_range > 0, to every site within that periodic Chebyshev distance
+    (the reach of a flip through the learned action's two 3^3 convolutions is
+    2, so sites closer than 5 interact through it)."""
     n = model.n_sites
     nbr = [set() for _ in range(n)]
     for term in terms:
@@ -129,6 +132,14 @@ def spatial_colouring(model, terms):
             continue
         for i in range(n):
             for j, _ in partners(model, term, i, 1):
+                if j != i:
+                    nbr[i].add(j)
+                    nbr[j].add(i)
+    for i in range(n):
+        x, y = i % model.lx, i // model.lx
+        for dy in range(-net_range, net_range + 1):
+            for dx in range(-net_range, net_range + 1):
+                j = (x + dx) % model.lx + model.lx * ((y + dy) % model.ly)
                 if j != i:
                     nbr[i].add(j)
                     nbr[j].add(i)
@@ -142,22 +153,27 @@ def spatial_colouring(model, terms):
     return col
 
 
-def colour_classes(model, terms):
+def colour_classes(model, terms, net_range: int = 0):
     """Class index c_s + n_colours * (l - 1) lists the sites i with colour c_s
     at slice l; returns the list of (l, [sites])."""
-    col = spatial_colouring(model, terms)
+    col = spatial_colouring(model, terms, net_range)
     nc = max(col) + 1
     return [(l, [i for i in range(model.n_sites) if col[i] == c])
             for l in range(1, model.n_slices + 1) for c in range(nc)]
 
 
-def effective_move(model, terms, lam, s, classes, *, seed, step, move, chain=0):
-    """One colour-class move in place; returns (#accepted, sum of accepted dS)."""
+def effective_move(model, terms, lam, s, classes, *, seed, step, move, chain=0, net_params=None):
+    """One colour-class move in place; returns (#accepted, sum of accepted dS).
+    With net_params the action is S_lin + S_net and each flip's change of
+    S_net comes from two full forward passes (oracle.net.flip_delta)."""
     key = (seed, TAG_EFFECTIVE)
     cls = below(len(classes), (0, move, step, chain), key)
     l, sites = classes[cls]
     hsum = np.tensordot(np.asarray(lam, dtype=np.float64), local_fields(model, terms, s), axes=1)
     ds = [-2.0 * float(s[l - 1, i]) * float(hsum[l - 1, i]) for i in sites]   # pre-move field
+    if net_params is not None:
+        from . import net
+        ds = [d + net.flip_delta(net_params, model, s, i, l) for d, i in zip(ds, sites)]
     acc, tot = 0, 0.0
     for i, d in zip(sites, ds):
         u = uniform((1 + (l - 1) * model.n_sites + i, move, step, chain), key)
@@ -168,24 +184,30 @@ def effective_move(model, terms, lam, s, classes, *, seed, step, move, chain=0):
     return acc, tot
 
 
-def effective_sweep(model, terms, lam, s, n_moves, *, seed, step, chain=0, classes=None):
+def effective_sweep(model, terms, lam, s, n_moves, *, seed, step, chain=0, classes=None, net_params=None):
     """n_moves colour-class moves in place; returns (#accepted, sum dS)."""
-    classes = classes or colour_classes(model, terms)
+    classes = classes or colour_classes(model, terms, 4 if net_params is not None else 0)
     acc, tot = 0, 0.0
     for m in range(n_moves):
-        a, d = effective_move(model, terms, lam, s, classes, seed=seed, step=step, move=m, chain=chain)
+        a, d = effective_move(model, terms, lam, s, classes, seed=seed, step=step, move=m, chain=chain,
+                              net_params=net_params)
         acc += a
         tot += d
     return acc, tot
 
 
 def cumulative_step(model, terms, c0, lam, s, logabs, sign, n_moves, weight_fn, *,
-                    seed, step, chain=0, classes=None):
+                    seed, step, chain=0, classes=None, net_params=None):
     """One cumulative update (Eq. 4).  Returns (s, logabs, sign, accepted, logA)
-    with s replaced by the proposal when accepted.  weight_fn(s) -> (log|W|, sign)."""
+    with s replaced by the proposal when accepted.  weight_fn(s) -> (log|W|, sign).
+    With net_params the effective action is S_lin + S_net."""
     prop = s.copy()
-    effective_sweep(model, terms, lam, prop, n_moves, seed=seed, step=step, chain=chain, classes=classes)
+    effective_sweep(model, terms, lam, prop, n_moves, seed=seed, step=step, chain=chain, classes=classes,
+                    net_params=net_params)
     ds = float(np.dot(lam, features(model, terms, prop) - features(model, terms, s)))
+    if net_params is not None:
+        from . import net
+        ds += net.forward(net_params, model, prop)[0] - net.forward(net_params, model, s)[0]
     new_logabs, new_sign = weight_fn(prop)
     log_a = (new_logabs - logabs) - ds
     u = uniform((0, 0, step, chain), (seed, TAG_CUMULATIVE))

@@ -34,6 +34,19 @@ __global__ void k_copy_i8(const int8_t* __restrict__ a, int8_t* __restrict__ b, 
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) b[i] = a[i];
 }
 
+// M[b] = sum of the spins of field b (fixed-order integer reduction).
+__global__ __launch_bounds__(256) void k_magnetization(long per, const int8_t* __restrict__ s, int64_t* M) {
+  __shared__ long long red[4];
+  const int8_t* sb = s + (long)blockIdx.x * per;
+  long long acc = 0;
+  for (long i = threadIdx.x; i < per; i += 256) acc += sb[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) M[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 static unsigned grid_for(long n) { return (unsigned)std::max<long>(1, std::min<long>((n + 255) / 256, 2048)); }
 
 int fill_f64(double* x, long n, double v, hipStream_t st) {
@@ -87,6 +100,8 @@ static int check_model(const slq_model* m) {
     return fail(SLQ_ERR_ARG, "chain_prec must be SLQ_PREC_FP64, SLQ_PREC_FP32 or SLQ_PREC_BF16");
   return SLQ_OK;
 }
+
+int check_model_public(const slq_model* m) { return check_model(m); }
 
 int check_batch(const Plan& p, long batch) {
   if (batch < 0) return fail(SLQ_ERR_ARG, "batch must be >= 0");
@@ -343,6 +358,17 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   return SLQ_OK;
 }
 
+int slq_magnetization(slq_plan* plan, int32_t batch, const int8_t* d_s, int64_t* d_M, hipStream_t stream) {
+  if (!plan || !d_s || !d_M) return fail(SLQ_ERR_ARG, "NULL argument");
+  Plan& p = plan->p;
+  SLQ_TRY(check_batch(p, batch));
+  if (batch == 0) return SLQ_OK;
+  SLQ_HIP(hipSetDevice(p.device));
+  k_magnetization<<<batch, 256, 0, stream>>>((long)p.L * p.n, d_s, d_M);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+
 int slq_profile_enable(slq_plan* plan, int32_t enable) {
   if (!plan) return fail(SLQ_ERR_ARG, "plan is NULL");
   plan->p.prof = enable != 0;
@@ -375,6 +401,7 @@ int slq_plan_destroy(slq_plan* plan) {
   hipSetDevice(plan->p.device);
   hipDeviceSynchronize();
   for (hipEvent_t e : plan->p.ev) hipEventDestroy(e);
+  release_net(plan->p);
   hipFree(plan->p.base);
   delete plan;
   return SLQ_OK;

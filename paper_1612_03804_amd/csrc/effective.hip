@@ -35,18 +35,7 @@ static const int kShellDxy[25][2] = {
     {2, 1},  {2, -1}, {-2, 1}, {-2, -1}, {1, 2}, {1, -2}, {-1, 2}, {-1, -2},  // 4
     {2, 2},  {2, -2}, {-2, 2}, {-2, -2}};                // 5
 
-struct EffDev {
-  int lx, ly, L, N;
-  int n_terms, n_colours, n_classes;
-  const int32_t* terms;      // [K][2]
-  const double* theta;       // [1 + K]
-  const int32_t* col_sites;  // [N]
-  const int32_t* col_off;    // [n_colours + 1]
-  const int32_t* shell_off;  // [7]
-  const int32_t* shell_dxy;  // [25][2]
-};
-
-static EffDev dev_view(const Plan& p, const Eff& e) {
+EffDev eff_dev_view(const Plan& p, const Eff& e) {
   EffDev d;
   d.lx = p.m.lx;
   d.ly = p.m.ly;
@@ -62,25 +51,6 @@ static EffDev dev_view(const Plan& p, const Eff& e) {
   d.shell_off = e.d_shell_off;
   d.shell_dxy = e.d_shell_dxy;
   return d;
-}
-
-// h_k((i, l)) for one term, l 0-based, s the field of one chain [L][N]
-__device__ __forceinline__ int local_field(const EffDev& d, const int8_t* __restrict__ s, int k, int i, int l) {
-  const int r = d.terms[2 * k], dl = d.terms[2 * k + 1];
-  const int x = i % d.lx, y = i / d.lx;
-  int h = 0;
-  const int lp = (l + dl) % d.L, lm = (l - dl + d.L) % d.L;
-  for (int o = d.shell_off[r]; o < d.shell_off[r + 1]; ++o) {
-    const int xx = ((x + d.shell_dxy[2 * o]) % d.lx + d.lx) % d.lx;
-    const int yy = ((y + d.shell_dxy[2 * o + 1]) % d.ly + d.ly) % d.ly;
-    const int j = xx + d.lx * yy;
-    if (dl == 0) {
-      h += s[(long)l * d.N + j];
-    } else {
-      h += s[(long)lp * d.N + j] + s[(long)lm * d.N + j];
-    }
-  }
-  return h;
 }
 
 // ------------------------------------------------------------ moves ----
@@ -101,7 +71,7 @@ __global__ __launch_bounds__(256) void k_eff_sweep(EffDev d, int8_t* s_all, int 
     for (int t = beg + threadIdx.x; t < end; t += blockDim.x) {
       const int i = d.col_sites[t];
       double hs = 0.0;
-      for (int k = 0; k < d.n_terms; ++k) hs += d.theta[1 + k] * (double)local_field(d, s, k, i, l);
+      for (int k = 0; k < d.n_terms; ++k) hs += d.theta[1 + k] * (double)local_field_dev(d, s, k, i, l);
       const double sx = (double)s[(long)l * d.N + i];
       const double dS = -2.0 * sx * hs;
       const double u = philox_uniform((uint64_t)(1 + (long)l * d.N + i), (uint64_t)mv, step, chain, seed,
@@ -132,7 +102,8 @@ __global__ __launch_bounds__(256) void k_eff_sweep(EffDev d, int8_t* s_all, int 
 int launch_eff_sweep(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, uint64_t seed, uint64_t step,
                      uint64_t chain0, int64_t* accepts, double* dS, hipStream_t st) {
   if (batch <= 0) return SLQ_OK;
-  k_eff_sweep<<<batch, 256, 0, st>>>(dev_view(p, e), s, n_moves, seed, step, chain0, accepts, dS);
+  if (e.net_on) return launch_eff_sweep_net(p, e, batch, s, n_moves, seed, step, chain0, accepts, dS, st);
+  k_eff_sweep<<<batch, 256, 0, st>>>(eff_dev_view(p, e), s, n_moves, seed, step, chain0, accepts, dS);
   SLQ_LAUNCHED();
   return SLQ_OK;
 }
@@ -150,7 +121,7 @@ __global__ __launch_bounds__(256) void k_features(EffDev d, const int8_t* s_all,
     long long part = 0;
     for (long x = threadIdx.x; x < total; x += blockDim.x) {
       const int l = (int)(x / d.N), i = (int)(x % d.N);
-      part += (long long)s[x] * local_field(d, s, k, i, l);
+      part += (long long)s[x] * local_field_dev(d, s, k, i, l);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
@@ -162,7 +133,7 @@ __global__ __launch_bounds__(256) void k_features(EffDev d, const int8_t* s_all,
 
 int launch_features(Plan& p, const Eff& e, long count, const int8_t* s, double* F, hipStream_t st) {
   if (count <= 0) return SLQ_OK;
-  k_features<<<(unsigned)count, 256, 0, st>>>(dev_view(p, e), s, F);
+  k_features<<<(unsigned)count, 256, 0, st>>>(eff_dev_view(p, e), s, F);
   SLQ_LAUNCHED();
   return SLQ_OK;
 }
@@ -171,14 +142,16 @@ int launch_features(Plan& p, const Eff& e, long count, const int8_t* s, double* 
 // Eq. 4: logA = [ln|W(s')| - ln|W(s)|] - [S_eff(s') - S_eff(s)]
 __global__ __launch_bounds__(256) void k_accept(EffDev d, int8_t* s_all, const int8_t* sp_all, double* logabs,
                                                 int8_t* sign, const double* new_logabs, const int8_t* new_sign,
-                                                const double* F_old, const double* F_new, uint64_t seed,
-                                                uint64_t step, uint64_t chain0, int8_t* accepted, double* logA) {
+                                                const double* F_old, const double* F_new, const double* Sn_old,
+                                                const double* Sn_new, uint64_t seed, uint64_t step, uint64_t chain0,
+                                                int8_t* accepted, double* logA) {
   __shared__ int take;
   const int b = blockIdx.x;
   if (threadIdx.x == 0) {
     double dS = 0.0;
     for (int k = 0; k < d.n_terms; ++k)
       dS += d.theta[1 + k] * (F_new[(long)b * d.n_terms + k] - F_old[(long)b * d.n_terms + k]);
+    if (Sn_old) dS += Sn_new[b] - Sn_old[b];  // learned part of the action
     const double la = (new_logabs[b] - logabs[b]) - dS;
     const double u = philox_uniform(0, 0, step, chain0 + b, seed, TAG_CUMULATIVE);
     const double lu = (u == 0.0) ? -INFINITY : log(u);
@@ -200,10 +173,11 @@ __global__ __launch_bounds__(256) void k_accept(EffDev d, int8_t* s_all, const i
 
 int launch_accept(Plan& p, const Eff& e, int batch, int8_t* s, const int8_t* sprop, double* logabs, int8_t* sign,
                   const double* new_logabs, const int8_t* new_sign, const double* F_old, const double* F_new,
-                  uint64_t seed, uint64_t step, uint64_t chain0, int8_t* accepted, double* logA, hipStream_t st) {
+                  const double* Sn_old, const double* Sn_new, uint64_t seed, uint64_t step, uint64_t chain0,
+                  int8_t* accepted, double* logA, hipStream_t st) {
   if (batch <= 0) return SLQ_OK;
-  k_accept<<<batch, 256, 0, st>>>(dev_view(p, e), s, sprop, logabs, sign, new_logabs, new_sign, F_old, F_new, seed,
-                                  step, chain0, accepted, logA);
+  k_accept<<<batch, 256, 0, st>>>(eff_dev_view(p, e), s, sprop, logabs, sign, new_logabs, new_sign, F_old, F_new,
+                                  Sn_old, Sn_new, seed, step, chain0, accepted, logA);
   SLQ_LAUNCHED();
   return SLQ_OK;
 }
@@ -397,6 +371,7 @@ int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const 
   Eff& e = h->e;
   e.plan = &p;
   e.n_terms = n_terms;
+  e.h_terms.assign(terms, terms + 2 * n_terms);
   e.n_colours = nc;
   e.n_classes = nc * L;
   e.max_class = maxc;
@@ -436,7 +411,88 @@ int slq_eff_destroy(slq_eff* eff) {
   hipSetDevice(eff->e.plan->device);
   hipDeviceSynchronize();
   hipFree(eff->e.d_terms);
+  if (eff->e.d_net) hipFree(eff->e.d_net);
   delete eff;
+  return SLQ_OK;
+}
+
+int slq_eff_set_net(slq_eff* eff, const double* d_params, int32_t net_prec, hipStream_t stream) {
+  if (!eff) return efail(SLQ_ERR_ARG, "eff is NULL");
+  Eff& e = eff->e;
+  Plan& p = *e.plan;
+  if (!d_params) {
+    e.net_on = false;
+    return SLQ_OK;
+  }
+  if (net_prec != SLQ_PREC_FP64 && net_prec != SLQ_PREC_FP32)
+    return efail(SLQ_ERR_ARG, "net_prec must be SLQ_PREC_FP64 or SLQ_PREC_FP32");
+  if (p.m.lx < 5 || p.m.ly < 5 || p.L < 5)
+    return efail(SLQ_ERR_ARG, "moves with the learned action need lx, ly and L >= 5");
+  SLQ_HIP(hipSetDevice(p.device));
+  if (!e.d_net) {
+    // colouring of the graph of dl = 0 couplings plus spatial Chebyshev distance <= 4
+    const int lx = p.m.lx, ly = p.m.ly, N = p.n;
+    std::vector<std::set<int>> nbr(N);
+    for (int k = 0; k < e.n_terms; ++k) {
+      const int r = e.h_terms[2 * k], dl = e.h_terms[2 * k + 1];
+      if (dl != 0) continue;
+      for (int i = 0; i < N; ++i) {
+        const int x = i % lx, y = i / lx;
+        for (int o = kShellOff[r]; o < kShellOff[r + 1]; ++o) {
+          const int j = ((x + kShellDxy[o][0]) % lx + lx) % lx + lx * (((y + kShellDxy[o][1]) % ly + ly) % ly);
+          if (j != i) nbr[i].insert(j);
+        }
+      }
+    }
+    for (int i = 0; i < N; ++i) {
+      const int x = i % lx, y = i / lx;
+      for (int dy = -4; dy <= 4; ++dy)
+        for (int dx = -4; dx <= 4; ++dx) {
+          const int j = ((x + dx) % lx + lx) % lx + lx * (((y + dy) % ly + ly) % ly);
+          if (j != i) nbr[i].insert(j);
+        }
+    }
+    std::vector<int> col(N, -1);
+    int nc = 0;
+    for (int i = 0; i < N; ++i) {
+      std::set<int> used;
+      for (int j : nbr[i])
+        if (col[j] >= 0) used.insert(col[j]);
+      int c = 0;
+      while (used.count(c)) ++c;
+      col[i] = c;
+      nc = std::max(nc, c + 1);
+    }
+    std::vector<int32_t> sites, off(nc + 1, 0);
+    for (int c = 0; c < nc; ++c) {
+      off[c] = (int32_t)sites.size();
+      for (int i = 0; i < N; ++i)
+        if (col[i] == c) sites.push_back(i);
+    }
+    off[nc] = (int32_t)sites.size();
+    const size_t b_prm = 8 * ((SLQ_NET_PARAMS + 31) / 32 * 32), b_sites = 4 * N, b_off = 4 * (nc + 1);
+    char* base = nullptr;
+    if (hipMalloc((void**)&base, b_prm + b_sites + b_off + 64) != hipSuccess)
+      return efail(SLQ_ERR_DEVICE, "hipMalloc failed");
+    e.d_net = (double*)base;
+    e.d_ncol_sites = (int32_t*)(base + b_prm);
+    e.d_ncol_off = (int32_t*)(base + b_prm + b_sites);
+    e.n_ncolours = nc;
+    if (hipMemcpy(e.d_ncol_sites, sites.data(), b_sites, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(e.d_ncol_off, off.data(), b_off, hipMemcpyHostToDevice) != hipSuccess)
+      return efail(SLQ_ERR_DEVICE, "hipMemcpy failed");
+  }
+  int rc = copy_f64(d_params, e.d_net, SLQ_NET_PARAMS, stream);
+  if (rc != SLQ_OK) return rc;
+  e.net_prec = net_prec;
+  e.net_on = true;
+  return SLQ_OK;
+}
+
+int slq_eff_net_classes(const slq_eff* eff, int32_t* n_classes) {
+  if (!eff || !n_classes) return efail(SLQ_ERR_ARG, "NULL argument");
+  if (!eff->e.d_net) return efail(SLQ_ERR_ARG, "no network attached");
+  *n_classes = eff->e.n_ncolours * eff->e.plan->L;
   return SLQ_OK;
 }
 
@@ -492,10 +548,13 @@ int slq_cumulative_step(slq_plan* plan, const slq_eff* eff, int32_t batch, int8_
   if ((rc = launch_features(p, e, batch, d_s, p.F_old, stream)) != SLQ_OK) return rc;
   if ((rc = launch_features(p, e, batch, p.s_work, p.F_new, stream)) != SLQ_OK) return rc;
   if ((rc = launch_check_spins(p, batch, d_s, status, stream)) != SLQ_OK) return rc;
+  double *sn_old = nullptr, *sn_new = nullptr;
+  if (e.net_on && (rc = net_pair(p, e, batch, d_s, p.s_work, &sn_old, &sn_new, stream)) != SLQ_OK) return rc;
   rc = run_chain(p, batch, p.s_work, 0, status, stream);
   if (rc == SLQ_OK) rc = launch_finish(p, batch, nullptr, p.dvec, p.sgn_work, status, stream);
   if (rc != SLQ_OK) return rc;
-  return launch_accept(p, e, batch, d_s, p.s_work, d_logabs, d_sign, p.dvec, p.sgn_work, p.F_old, p.F_new, seed,
+  return launch_accept(p, e, batch, d_s, p.s_work, d_logabs, d_sign, p.dvec, p.sgn_work, p.F_old, p.F_new, sn_old,
+                       sn_new, seed,
                        step, chain0, d_accepted, d_logA, stream);
 }
 

@@ -18,6 +18,8 @@
 // field's tiles are dispatched to one XCD, column panel by column panel), so
 // the operand panels of a field are fetched into one L2 only.
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "slq_internal.h"
 
@@ -205,23 +207,64 @@ static int run(const GemmArgs& a, bool ta, bool tb, hipStream_t st) {
   return SLQ_OK;
 }
 
-// Tile choice: thin panels get 32 x 64 tiles; otherwise the largest square
-// tile that divides both M and N, else 64 x 64 with ragged edges.
-int launch_gemm(const GemmArgs& a, bool ta, bool tb, hipStream_t st) {
+// Tile configurations of the FP64 GEMM (index = GemmCfg).
+int launch_gemm_cfg(const GemmArgs& a, bool ta, bool tb, int cfg, hipStream_t st) {
   if (a.batch <= 0 || a.M <= 0 || a.N <= 0) return SLQ_OK;
-  auto divides = [&](int t) { return a.M % t == 0 && a.N % t == 0; };
-  if (a.M <= 16 && a.N <= 16) return run<1, 1, 1, 1, 16>(a, ta, tb, st);
-  if (a.M <= 32) return run<2, 1, 1, 4, 16>(a, ta, tb, st);
-  // K is staged 4-8 deep: the small LDS footprint keeps several workgroups
-  // resident per CU, which hides the memory latency better than deeper stages
-  // (400 x 400 chain, 80 x 80 tiles: 16 deep 21.5, 8 deep 28.1, 4 deep
-  // 31.7 TFLOP/s).
-  if (a.M >= 128 && divides(128)) return run<4, 4, 2, 2, 8>(a, ta, tb, st);
-  if (a.M >= 96 && divides(96)) return run<3, 3, 2, 2, 8>(a, ta, tb, st);
-  if (a.M >= 80 && divides(80)) return run<5, 1, 1, 5, 4>(a, ta, tb, st);
-  if (a.M >= 64 && divides(64)) return run<2, 2, 2, 2, 8>(a, ta, tb, st);
-  if (a.M >= 48 && divides(48)) return run<3, 1, 1, 3, 8>(a, ta, tb, st);
-  return run<2, 2, 2, 2, 8>(a, ta, tb, st);
+  switch (cfg) {
+    case GEMM_16: return run<1, 1, 1, 1, 16>(a, ta, tb, st);
+    case GEMM_32x64: return run<2, 1, 1, 4, 16>(a, ta, tb, st);
+    case GEMM_128: return run<4, 4, 2, 2, 8>(a, ta, tb, st);
+    case GEMM_96: return run<3, 3, 2, 2, 8>(a, ta, tb, st);
+    case GEMM_80_K4: return run<5, 1, 1, 5, 4>(a, ta, tb, st);
+    case GEMM_80_K8: return run<5, 1, 1, 5, 8>(a, ta, tb, st);
+    case GEMM_160x80: return run<5, 1, 2, 5, 8>(a, ta, tb, st);
+    case GEMM_64: return run<2, 2, 2, 2, 8>(a, ta, tb, st);
+    case GEMM_48: return run<3, 1, 1, 3, 8>(a, ta, tb, st);
+    default:
+      set_error("unknown GEMM tile configuration");
+      return SLQ_ERR_ARG;
+  }
+}
+
+// Tile shapes picked by the autotuner for square N x N x N products (the
+// chain), keyed by N; shared by every plan of the process.
+static std::mutex g_tune_mu;
+static std::map<int, int> g_tuned;
+
+void set_tuned_gemm(int n, int cfg) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[n] = cfg;
+}
+
+int tuned_gemm(int n) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(n);
+  return it == g_tuned.end() ? -1 : it->second;
+}
+
+// Default tile choice: thin panels get 32 x 64 tiles; otherwise the largest
+// square tile that divides both M and N, else 64 x 64 with ragged edges.
+// K is staged 4-8 deep: the small LDS footprint keeps several workgroups
+// resident per CU, which hides the memory latency better than deeper stages
+// (400 x 400 chain, 80 x 80 tiles: 16 deep 21.5, 8 deep 28.1, 4 deep
+// 31.7 TFLOP/s).
+int default_gemm(int M, int N) {
+  auto divides = [&](int t) { return M % t == 0 && N % t == 0; };
+  if (M <= 16 && N <= 16) return GEMM_16;
+  if (M <= 32) return GEMM_32x64;
+  if (M >= 128 && divides(128)) return GEMM_128;
+  if (M >= 96 && divides(96)) return GEMM_96;
+  if (M >= 80 && divides(80)) return GEMM_80_K4;
+  if (M >= 64 && divides(64)) return GEMM_64;
+  if (M >= 48 && divides(48)) return GEMM_48;
+  return GEMM_64;
+}
+
+int launch_gemm(const GemmArgs& a, bool ta, bool tb, hipStream_t st) {
+  int cfg = -1;
+  if (a.M == a.N && a.N == a.K && !ta && !tb) cfg = tuned_gemm(a.M);
+  if (cfg < 0) cfg = default_gemm(a.M, a.N);
+  return launch_gemm_cfg(a, ta, tb, cfg, st);
 }
 
 }  // namespace slq

@@ -1,0 +1,401 @@
+// Groups of independent chains of uneven size (N_c, L_c): one graph-captured
+// launch evaluates the exact weight (Eq. 1; and optionally G) of every chain.
+//
+// Chains with identical models share an internal plan and run as one batch;
+// the fields are gathered from the caller's packed layout into the batch,
+// evaluated (stabilised chain, QR, LU) and the results scattered back.  The
+// whole sequence is recorded once as a HIP graph on the group's own stream
+// (per set of caller pointers) and replayed as a single launch; the caller's
+// stream is joined with events.  At creation the chain-GEMM tile shape of
+// every distinct N is picked by timing the candidate tiles on the device.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "slq_internal.h"
+
+namespace slq {
+
+struct SubPlan {
+  slq_plan* plan = nullptr;
+  int nb = 0;
+  int32_t* d_ids = nullptr;   // [nb] chain index of each batch position
+  int64_t* d_soff = nullptr;  // [nb] field offset (bytes) in the caller's packed layout
+  int64_t* d_goff = nullptr;  // [nb] G offset (doubles)
+};
+
+struct Group {
+  int n = 0;
+  int device = 0;
+  std::vector<slq_model> models;
+  std::vector<int64_t> s_off, g_off;
+  std::vector<SubPlan> subs;
+  std::vector<int> tuned_n, tuned_cfg;
+  std::vector<double> tuned_tflops;
+  void* dmem = nullptr;
+  hipStream_t gs = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+int check_model_public(const slq_model* m);
+
+__global__ void k_gather(const int8_t* __restrict__ src, const int64_t* __restrict__ soff, long per,
+                         int8_t* __restrict__ dst) {
+  const int pos = blockIdx.y;
+  const int8_t* s = src + soff[pos];
+  int8_t* d = dst + (long)pos * per;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
+}
+
+__global__ void k_scatter(int nb, const int32_t* __restrict__ ids, const double* __restrict__ la,
+                          const int8_t* __restrict__ sg, const int32_t* __restrict__ st, double* __restrict__ out_la,
+                          int8_t* __restrict__ out_sg, int32_t* __restrict__ out_st) {
+  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= nb) return;
+  const int c = ids[pos];
+  out_la[c] = la[pos];
+  out_sg[c] = sg[pos];
+  if (out_st) out_st[c] = st[pos];
+}
+
+__global__ void k_scatter_g(long NN, const int64_t* __restrict__ goff, const double* __restrict__ G,
+                            double* __restrict__ out) {
+  const int pos = blockIdx.y;
+  const double* s = G + (long)pos * NN;
+  double* d = out + goff[pos];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < NN; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
+}
+
+static bool same_model(const slq_model& a, const slq_model& b) {
+  return a.lx == b.lx && a.ly == b.ly && a.n_slices == b.n_slices && a.n_stab == b.n_stab && a.t == b.t &&
+         a.mu == b.mu && a.dtau == b.dtau && a.xi == b.xi && a.chain_prec == b.chain_prec;
+}
+
+// Time every candidate tile shape of the FP64 chain GEMM for one N on the
+// sub-plan's own buffers and keep the fastest for the process.
+static int autotune(Group& g, SubPlan& sp) {
+  Plan& p = sp.plan->p;
+  const int N = p.n;
+  if (p.m.chain_prec != SLQ_PREC_FP64 || tuned_gemm(N) >= 0) return SLQ_OK;
+  std::vector<int> cands;
+  if (N <= 32) {
+    cands = {GEMM_16, GEMM_32x64, GEMM_64};
+  } else {
+    cands = {GEMM_128, GEMM_96, GEMM_80_K4, GEMM_80_K8, GEMM_160x80, GEMM_64, GEMM_48};
+  }
+  const long NN = (long)N * N;
+  int rc = launch_set_identity(p, sp.nb, p.Xa, g.gs);
+  if (rc != SLQ_OK) return rc;
+  rc = fill_i32((int32_t*)p.s_work, (long)sp.nb * p.L * N / 4, 0x01010101, g.gs);
+  if (rc != SLQ_OK) return rc;
+  GemmArgs a{};
+  a.M = N;
+  a.N = N;
+  a.K = N;
+  a.A = p.E;
+  a.lda = N;
+  a.B = p.Xa;
+  a.ldb = N;
+  a.strideB = NN;
+  a.C = p.Xb;
+  a.ldc = N;
+  a.strideC = NN;
+  a.S = p.s_work;
+  a.strideS = (long)p.L * N;
+  a.consts = p.consts;
+  a.alpha = 1.0;
+  a.batch = sp.nb;
+  hipEvent_t e0, e1;
+  SLQ_HIP(hipEventCreate(&e0));
+  SLQ_HIP(hipEventCreate(&e1));
+  int best = default_gemm(N, N);
+  float best_ms = 1e30f;
+  for (int cfg : cands) {
+    if ((rc = launch_gemm_cfg(a, false, false, cfg, g.gs)) != SLQ_OK) break;
+    SLQ_HIP(hipEventRecord(e0, g.gs));
+    for (int r = 0; r < 3 && rc == SLQ_OK; ++r) rc = launch_gemm_cfg(a, false, false, cfg, g.gs);
+    SLQ_HIP(hipEventRecord(e1, g.gs));
+    SLQ_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    SLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (rc == SLQ_OK && ms < best_ms) {
+      best_ms = ms;
+      best = cfg;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != SLQ_OK) return rc;
+  set_tuned_gemm(N, best);
+  g.tuned_n.push_back(N);
+  g.tuned_cfg.push_back(best);
+  g.tuned_tflops.push_back(2.0 * (double)N * N * N * sp.nb * 3 / (best_ms * 1e-3) / 1e12);
+  return SLQ_OK;
+}
+
+static int enqueue(Group& g, const int8_t* d_s, double* d_G, double* d_logabs, int8_t* d_sign, int32_t* d_status) {
+  hipStream_t st = g.gs;
+  for (SubPlan& sp : g.subs) {
+    Plan& p = sp.plan->p;
+    const long per = (long)p.L * p.n;
+    dim3 grid((unsigned)std::max<long>(1, std::min<long>((per + 255) / 256, 256)), sp.nb);
+    k_gather<<<grid, 256, 0, st>>>(d_s, sp.d_soff, per, p.s_work);
+    SLQ_LAUNCHED();
+    int rc = fill_i32(p.status, sp.nb, 0, st);
+    if (rc == SLQ_OK) rc = launch_check_spins(p, sp.nb, p.s_work, p.status, st);
+    if (rc == SLQ_OK) rc = run_chain(p, sp.nb, p.s_work, 0, p.status, st);
+    if (rc == SLQ_OK) rc = launch_finish(p, sp.nb, d_G ? p.Xa : nullptr, p.dvec, p.sgn_work, p.status, st);
+    if (rc != SLQ_OK) return rc;
+    k_scatter<<<(sp.nb + 63) / 64, 64, 0, st>>>(sp.nb, sp.d_ids, p.dvec, p.sgn_work, p.status, d_logabs, d_sign,
+                                                 d_status);
+    SLQ_LAUNCHED();
+    if (d_G) {
+      const long NN = (long)p.n * p.n;
+      dim3 gg((unsigned)std::max<long>(1, std::min<long>((NN + 255) / 256, 256)), sp.nb);
+      k_scatter_g<<<gg, 256, 0, st>>>(NN, sp.d_goff, p.Xa, d_G);
+      SLQ_LAUNCHED();
+    }
+  }
+  return SLQ_OK;
+}
+
+static int group_eval(Group& g, const int8_t* d_s, double* d_G, double* d_logabs, int8_t* d_sign, int32_t* d_status,
+                      hipStream_t stream) {
+  SLQ_HIP(hipSetDevice(g.device));
+  SLQ_HIP(hipEventRecord(g.ev_in, stream));
+  SLQ_HIP(hipStreamWaitEvent(g.gs, g.ev_in, 0));
+  const void* key[5] = {d_s, d_G, d_logabs, d_sign, d_status};
+  if (!g.exec || memcmp(key, g.key, sizeof(key)) != 0) {
+    if (g.exec) {
+      hipGraphExecDestroy(g.exec);
+      hipGraphDestroy(g.graph);
+      g.exec = nullptr;
+      g.graph = nullptr;
+    }
+    // one eager pass (sets kernel attributes), then record the graph
+    int rc = enqueue(g, d_s, d_G, d_logabs, d_sign, d_status);
+    if (rc != SLQ_OK) return rc;
+    SLQ_HIP(hipStreamBeginCapture(g.gs, hipStreamCaptureModeThreadLocal));
+    rc = enqueue(g, d_s, d_G, d_logabs, d_sign, d_status);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(g.gs, &graph);
+    if (rc != SLQ_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) {
+      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      return SLQ_ERR_DEVICE;
+    }
+    g.graph = graph;
+    SLQ_HIP(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    memcpy(g.key, key, sizeof(key));
+  }
+  SLQ_HIP(hipGraphLaunch(g.exec, g.gs));
+  SLQ_HIP(hipEventRecord(g.ev_out, g.gs));
+  SLQ_HIP(hipStreamWaitEvent(stream, g.ev_out, 0));
+  return SLQ_OK;
+}
+
+static void release(Group& g) {
+  hipSetDevice(g.device);
+  if (g.gs) hipStreamSynchronize(g.gs);
+  if (g.exec) hipGraphExecDestroy(g.exec);
+  if (g.graph) hipGraphDestroy(g.graph);
+  for (SubPlan& sp : g.subs) slq_plan_destroy(sp.plan);
+  if (g.dmem) hipFree(g.dmem);
+  if (g.ev_in) hipEventDestroy(g.ev_in);
+  if (g.ev_out) hipEventDestroy(g.ev_out);
+  if (g.gs) hipStreamDestroy(g.gs);
+  g = Group();
+}
+
+}  // namespace slq
+
+struct slq_group {
+  slq::Group g;
+};
+
+using namespace slq;
+
+extern "C" {
+
+int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out) {
+  if (!models || !out || n_chains < 1) {
+    set_error("models, out and n_chains >= 1 are required");
+    return SLQ_ERR_ARG;
+  }
+  *out = nullptr;
+  for (int c = 0; c < n_chains; ++c) {
+    int rc = check_model_public(&models[c]);
+    if (rc != SLQ_OK) return rc;
+  }
+  slq_group* h = new (std::nothrow) slq_group();
+  if (!h) {
+    set_error("host allocation failed");
+    return SLQ_ERR_DEVICE;
+  }
+  Group& g = h->g;
+  g.n = n_chains;
+  g.models.assign(models, models + n_chains);
+  if (hipGetDevice(&g.device) != hipSuccess) {
+    delete h;
+    set_error("no HIP device");
+    return SLQ_ERR_DEVICE;
+  }
+  g.s_off.resize(n_chains + 1);
+  g.g_off.resize(n_chains + 1);
+  g.s_off[0] = 0;
+  g.g_off[0] = 0;
+  for (int c = 0; c < n_chains; ++c) {
+    const long N = (long)models[c].lx * models[c].ly;
+    g.s_off[c + 1] = g.s_off[c] + (long)models[c].n_slices * N;
+    g.g_off[c + 1] = g.g_off[c] + N * N;
+  }
+  // sub-plans in order of first appearance
+  std::vector<std::vector<int>> members;
+  std::vector<int> rep;
+  for (int c = 0; c < n_chains; ++c) {
+    int k = -1;
+    for (size_t q = 0; q < rep.size(); ++q)
+      if (same_model(models[rep[q]], models[c])) k = (int)q;
+    if (k < 0) {
+      rep.push_back(c);
+      members.emplace_back();
+      k = (int)rep.size() - 1;
+    }
+    members[k].push_back(c);
+  }
+  size_t bytes = 0;
+  for (auto& mset : members) bytes += mset.size() * (4 + 8 + 8) + 64;
+  if (hipMalloc(&g.dmem, bytes) != hipSuccess) {
+    delete h;
+    set_error("hipMalloc failed");
+    return SLQ_ERR_DEVICE;
+  }
+  char* dp = (char*)g.dmem;
+  int rc = SLQ_OK;
+  for (size_t q = 0; q < members.size() && rc == SLQ_OK; ++q) {
+    SubPlan sp;
+    sp.nb = (int)members[q].size();
+    rc = slq_plan_create(&models[rep[q]], sp.nb, &sp.plan);
+    if (rc != SLQ_OK) break;
+    std::vector<int32_t> ids(members[q].begin(), members[q].end());
+    std::vector<int64_t> so(sp.nb), go(sp.nb);
+    for (int i = 0; i < sp.nb; ++i) {
+      so[i] = g.s_off[ids[i]];
+      go[i] = g.g_off[ids[i]];
+    }
+    sp.d_soff = (int64_t*)dp;
+    dp += 8 * sp.nb;
+    sp.d_goff = (int64_t*)dp;
+    dp += 8 * sp.nb;
+    sp.d_ids = (int32_t*)dp;
+    dp += 4 * sp.nb + (64 - (4 * sp.nb) % 64) % 64;
+    if (hipMemcpy(sp.d_soff, so.data(), 8 * sp.nb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(sp.d_goff, go.data(), 8 * sp.nb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(sp.d_ids, ids.data(), 4 * sp.nb, hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("hipMemcpy failed");
+      rc = SLQ_ERR_DEVICE;
+    }
+    g.subs.push_back(sp);
+  }
+  if (rc == SLQ_OK && (hipStreamCreateWithFlags(&g.gs, hipStreamNonBlocking) != hipSuccess ||
+                       hipEventCreateWithFlags(&g.ev_in, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming) != hipSuccess)) {
+    set_error("stream/event creation failed");
+    rc = SLQ_ERR_DEVICE;
+  }
+  // autotune the chain GEMM once per distinct N, on the largest batch of that N
+  for (size_t q = 0; q < g.subs.size() && rc == SLQ_OK; ++q) {
+    size_t pick = q;
+    for (size_t r = 0; r < g.subs.size(); ++r)
+      if (g.subs[r].plan->p.n == g.subs[q].plan->p.n && g.subs[r].nb > g.subs[pick].nb) pick = r;
+    rc = autotune(g, g.subs[pick]);
+  }
+  if (rc == SLQ_OK && hipStreamSynchronize(g.gs) != hipSuccess) {
+    set_error("autotuning failed");
+    rc = SLQ_ERR_DEVICE;
+  }
+  if (rc != SLQ_OK) {
+    release(h->g);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return SLQ_OK;
+}
+
+int slq_group_destroy(slq_group* grp) {
+  if (!grp) return SLQ_OK;
+  release(grp->g);
+  delete grp;
+  return SLQ_OK;
+}
+
+int slq_group_layout(const slq_group* grp, int64_t* s_off, int64_t* g_off) {
+  if (!grp || !s_off) {
+    set_error("NULL argument");
+    return SLQ_ERR_ARG;
+  }
+  const Group& g = grp->g;
+  for (int c = 0; c <= g.n; ++c) {
+    s_off[c] = g.s_off[c];
+    if (g_off) g_off[c] = g.g_off[c];
+  }
+  return SLQ_OK;
+}
+
+int slq_group_describe(const slq_group* grp, char* buf, size_t len) {
+  if (!grp || !buf || len == 0) {
+    set_error("NULL argument");
+    return SLQ_ERR_ARG;
+  }
+  const Group& g = grp->g;
+  std::string s = "{\"chains\": " + std::to_string(g.n) + ", \"batches\": [";
+  for (size_t q = 0; q < g.subs.size(); ++q) {
+    const Plan& p = g.subs[q].plan->p;
+    s += (q ? ", " : "") + std::string("{\"N\": ") + std::to_string(p.n) + ", \"L\": " + std::to_string(p.L) +
+         ", \"chains\": " + std::to_string(g.subs[q].nb) + "}";
+  }
+  s += "], \"tuned\": [";
+  for (size_t q = 0; q < g.tuned_n.size(); ++q) {
+    char tmp[128];
+    snprintf(tmp, sizeof(tmp), "%s{\"N\": %d, \"cfg\": %d, \"tflops\": %.3f}", q ? ", " : "", g.tuned_n[q],
+             g.tuned_cfg[q], g.tuned_tflops[q]);
+    s += tmp;
+  }
+  s += "]}";
+  if (s.size() + 1 > len) {
+    set_error("buffer too small");
+    return SLQ_ERR_ARG;
+  }
+  memcpy(buf, s.c_str(), s.size() + 1);
+  return SLQ_OK;
+}
+
+int slq_group_weight(slq_group* grp, const int8_t* d_s, double* d_logabs, int8_t* d_sign, int32_t* d_status,
+                     hipStream_t stream) {
+  if (!grp || !d_s || !d_logabs || !d_sign) {
+    set_error("NULL argument");
+    return SLQ_ERR_ARG;
+  }
+  return group_eval(grp->g, d_s, nullptr, d_logabs, d_sign, d_status, stream);
+}
+
+int slq_group_green(slq_group* grp, const int8_t* d_s, double* d_G, double* d_logabs, int8_t* d_sign,
+                    int32_t* d_status, hipStream_t stream) {
+  if (!grp || !d_s || !d_G || !d_logabs || !d_sign) {
+    set_error("NULL argument");
+    return SLQ_ERR_ARG;
+  }
+  return group_eval(grp->g, d_s, d_G, d_logabs, d_sign, d_status, stream);
+}
+
+}  // extern "C"

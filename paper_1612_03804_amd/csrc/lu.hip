@@ -323,10 +323,10 @@ int launch_finish(Plan& p, int batch, double* G, double* logabs, int8_t* sign, i
   const int nb = p.n <= 1024 ? 16 : 8;
   const size_t lds = finish_lds(p.n, nb);
   if (nb == 16) {
-    hipFuncSetAttribute((const void*)k_finish<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    allow_max_lds((const void*)k_finish<16>);
     k_finish<16><<<batch, FN_THREADS, lds, st>>>(a);
   } else {
-    hipFuncSetAttribute((const void*)k_finish<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    allow_max_lds((const void*)k_finish<8>);
     k_finish<8><<<batch, FN_THREADS, lds, st>>>(a);
   }
   SLQ_LAUNCHED();

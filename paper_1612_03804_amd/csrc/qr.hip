@@ -340,10 +340,10 @@ int launch_qr(Plan& p, int batch, const double* X, int32_t* status, hipStream_t 
   const int nb = qr_panel_width(p.n);
   const size_t lds = qr_lds(p.n, nb);
   if (nb == 16) {
-    hipFuncSetAttribute((const void*)k_qr<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    allow_max_lds((const void*)k_qr<16>);
     k_qr<16><<<batch, QR_THREADS, lds, st>>>(a);
   } else {
-    hipFuncSetAttribute((const void*)k_qr<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    allow_max_lds((const void*)k_qr<8>);
     k_qr<8><<<batch, QR_THREADS, lds, st>>>(a);
   }
   SLQ_LAUNCHED();

@@ -265,7 +265,7 @@ static int run_blocked(Plan& p, int batch, const double* X, int32_t* status, hip
   double* Ybuf = p.dX;  // [b][N][NB] (local-sweep scratch is idle here)
   double* Wt = p.dY;    // [b][NB][N]
   const size_t lpp = sizeof(double) * N + sizeof(int) * N;
-  hipFuncSetAttribute((const void*)k_prepivot, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lpp);
+  allow_max_lds((const void*)k_prepivot);
   k_prepivot<<<batch, PQ_THREADS, lpp, st>>>(N, X, p.W, p.D, p.perm, status);
   SLQ_LAUNCHED();
   k_zero_i32<<<(batch + 255) / 256, 256, 0, st>>>(p.nref, batch);
@@ -275,7 +275,7 @@ static int run_blocked(Plan& p, int batch, const double* X, int32_t* status, hip
     const int j0 = pi * NB, nbw = std::min(NB, N - j0), m = N - j0, nt = N - j0 - nbw;
     PanelArgs a{N, j0, nbw, p.W, Vbuf, Zbuf, Ybuf, p.D, p.invD, p.nref, status};
     const size_t lds = sizeof(double) * ((size_t)NB * (m + 1) + 2 * NB * NB + 2 * NB + PQ_WAVES);
-    hipFuncSetAttribute((const void*)k_panel<NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    allow_max_lds((const void*)k_panel<NB>);
     k_panel<NB><<<batch, PQ_THREADS, lds, st>>>(a);
     SLQ_LAUNCHED();
     if (nt <= 0) continue;

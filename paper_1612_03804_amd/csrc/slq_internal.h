@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -31,6 +32,21 @@ void set_error(const std::string& msg);
       return SLQ_ERR_DEVICE;                                                       \
     }                                                                              \
   } while (0)
+
+// Raise a kernel's dynamic-LDS limit to the 160 KiB of a gfx950 CU, once per
+// kernel and process (so no attribute call happens while a graph is recorded).
+inline void allow_max_lds(const void* fn) {
+  static std::mutex mu;
+  static std::vector<const void*> done;
+  std::lock_guard<std::mutex> lk(mu);
+  for (const void* f : done)
+    if (f == fn) return;
+  hipFuncAttributes attr;
+  if (hipFuncGetAttributes(&attr, fn) == hipSuccess)
+    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)attr.sharedSizeBytes);
+  (void)hipGetLastError();  // a refused attribute must not surface as the next launch's error
+  done.push_back(fn);
+}
 
 // ---------------------------------------------------------------- Philox ----
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 64x64
@@ -127,6 +143,8 @@ struct Plan {
   std::vector<hipEvent_t> ev;  // start/stop pairs
   size_t ev_used = 0;
   double prof_flops = 0.0;
+  // learned-action workspace, allocated on first use
+  void* net_state = nullptr;
 };
 
 struct Eff {
@@ -141,7 +159,47 @@ struct Eff {
   int max_class;         // largest colour class
   int32_t* d_shell_off;  // shell offset table [6 + 1]
   int32_t* d_shell_dxy;  // [total][2]
+  std::vector<int32_t> h_terms;  // host copy of the terms
+  // learned action (optional)
+  bool net_on = false;
+  int net_prec = 0;
+  double* d_net = nullptr;          // [1969] parameters (owned copy)
+  int32_t* d_ncol_sites = nullptr;  // colouring that also separates the network's range
+  int32_t* d_ncol_off = nullptr;
+  int n_ncolours = 0;
 };
+
+// Device view of an effective model.
+struct EffDev {
+  int lx, ly, L, N;
+  int n_terms, n_colours, n_classes;
+  const int32_t* terms;      // [K][2]
+  const double* theta;       // [1 + K]
+  const int32_t* col_sites;  // [N]
+  const int32_t* col_off;    // [n_colours + 1]
+  const int32_t* shell_off;  // [7]
+  const int32_t* shell_dxy;  // [25][2]
+};
+EffDev eff_dev_view(const Plan& p, const Eff& e);
+
+// h_k((i, l)) of term k at site i, slice l (0-based) of one field s [L][N]
+__device__ __forceinline__ int local_field_dev(const EffDev& d, const int8_t* __restrict__ s, int k, int i, int l) {
+  const int r = d.terms[2 * k], dl = d.terms[2 * k + 1];
+  const int x = i % d.lx, y = i / d.lx;
+  int h = 0;
+  const int lp = (l + dl) % d.L, lm = (l - dl + d.L) % d.L;
+  for (int o = d.shell_off[r]; o < d.shell_off[r + 1]; ++o) {
+    const int xx = ((x + d.shell_dxy[2 * o]) % d.lx + d.lx) % d.lx;
+    const int yy = ((y + d.shell_dxy[2 * o + 1]) % d.ly + d.ly) % d.ly;
+    const int j = xx + d.lx * yy;
+    if (dl == 0) {
+      h += s[(long)l * d.N + j];
+    } else {
+      h += s[(long)lp * d.N + j] + s[(long)lm * d.N + j];
+    }
+  }
+  return h;
+}
 
 constexpr int QR_NB = 16;     // Householder / LU panel width
 constexpr int SWEEP_KD = 32;  // delayed local updates per flush
@@ -170,6 +228,23 @@ struct GemmArgs {
   int batch;
 };
 int launch_gemm(const GemmArgs& a, bool transA, bool transB, hipStream_t st);
+// Tile configurations (TM x TN, K stage depth) of the FP64 GEMM.
+enum GemmCfg {
+  GEMM_16 = 0,     // 16 x 16, 1 wavefront
+  GEMM_32x64,      // 32 x 64, 4 wavefronts (thin panels)
+  GEMM_128,        // 128 x 128, K 8
+  GEMM_96,         // 96 x 96, K 8
+  GEMM_80_K4,      // 80 x 80, 5 wavefronts, K 4
+  GEMM_80_K8,      // 80 x 80, 5 wavefronts, K 8
+  GEMM_160x80,     // 160 x 80, 10 wavefronts, K 8
+  GEMM_64,         // 64 x 64, K 8
+  GEMM_48,         // 48 x 48, 3 wavefronts, K 8
+  GEMM_NCFG
+};
+int launch_gemm_cfg(const GemmArgs& a, bool transA, bool transB, int cfg, hipStream_t st);
+int default_gemm(int M, int N);
+void set_tuned_gemm(int n, int cfg);
+int tuned_gemm(int n);
 
 // Reduced-precision chain GEMM: C(f32)[b] = A(f32, shared) diag(d_slice) B[b] (f32 or f64)
 struct LpArgs {
@@ -222,9 +297,18 @@ int launch_eff_sweep(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, u
 int launch_features(Plan& p, const Eff& e, long count, const int8_t* s, double* F, hipStream_t st);
 int launch_accept(Plan& p, const Eff& e, int batch, int8_t* s, const int8_t* sprop, double* logabs, int8_t* sign,
                   const double* new_logabs, const int8_t* new_sign, const double* F_old, const double* F_new,
-                  uint64_t seed, uint64_t step, uint64_t chain0, int8_t* accepted, double* logA, hipStream_t st);
+                  const double* Sn_old, const double* Sn_new, uint64_t seed, uint64_t step, uint64_t chain0,
+                  int8_t* accepted, double* logA, hipStream_t st);
 int launch_fit(Plan& p, const Eff& e, long n, const double* F, const double* y, double* theta, double* r2,
                hipStream_t st);
+
+// Learned action
+int net_forward(Plan& p, int prec, int batch, const int8_t* s, const double* prm, double* S, hipStream_t st);
+int launch_eff_sweep_net(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, uint64_t seed, uint64_t step,
+                         uint64_t chain0, int64_t* accepts, double* dS, hipStream_t st);
+int net_pair(Plan& p, const Eff& e, int batch, const int8_t* s_old, const int8_t* s_new, double** old_out,
+             double** new_out, hipStream_t st);
+void release_net(Plan& p);
 
 }  // namespace slq
 

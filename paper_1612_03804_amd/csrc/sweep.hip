@@ -138,7 +138,7 @@ int launch_flip_slice(Plan& p, int batch, int8_t* s, double* G, double* logabs, 
   f.sweep = sweep;
   f.chain0 = chain0;
   const size_t lds = sizeof(double) * ((size_t)p.n + SWEEP_KD + 4);
-  hipFuncSetAttribute((const void*)k_flip_slice, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  allow_max_lds((const void*)k_flip_slice);
   k_flip_slice<<<batch, FL_THREADS, lds, st>>>(f);
   SLQ_LAUNCHED();
   return SLQ_OK;

@@ -26,8 +26,11 @@ EXPORTS = (
     "slq_profile_enable", "slq_profile_read",
     "slq_weight", "slq_green", "slq_udv", "slq_sweep_local", "slq_eff_create", "slq_eff_destroy",
     "slq_eff_classes", "slq_eff_set_theta", "slq_eff_sweep", "slq_eff_features", "slq_cumulative_step",
-    "slq_fit_effective",
+    "slq_fit_effective", "slq_group_create", "slq_group_destroy", "slq_group_layout", "slq_group_describe",
+    "slq_group_weight", "slq_group_green", "slq_magnetization", "slq_net_forward", "slq_net_gradient",
+    "slq_net_adam", "slq_eff_set_net", "slq_eff_net_classes",
 )
+SLQ_NET_PARAMS = 1969
 
 
 class SlqError(RuntimeError):
@@ -78,6 +81,18 @@ def load_library(path: str = LIB_PATH):
         "slq_eff_features": ([P, P, i32, P, P, P], C.c_int),
         "slq_cumulative_step": ([P, P, i32, P, P, P, i32, u64, u64, u64, P, P, P, P], C.c_int),
         "slq_fit_effective": ([P, P, i64, P, P, P, P, P], C.c_int),
+        "slq_group_create": ([P, i32, C.POINTER(P)], C.c_int),
+        "slq_group_destroy": ([P], C.c_int),
+        "slq_group_layout": ([P, P, P], C.c_int),
+        "slq_group_describe": ([P, C.c_char_p, C.c_size_t], C.c_int),
+        "slq_group_weight": ([P, P, P, P, P, P], C.c_int),
+        "slq_group_green": ([P, P, P, P, P, P, P], C.c_int),
+        "slq_magnetization": ([P, i32, P, P, P], C.c_int),
+        "slq_net_forward": ([P, i32, i32, P, P, P, P], C.c_int),
+        "slq_net_gradient": ([P, P, i32, i32, P, P, P, P, P, P], C.c_int),
+        "slq_net_adam": ([i32, P, P, P, P, i64, dbl, dbl, dbl, dbl, P], C.c_int),
+        "slq_eff_set_net": ([P, P, i32, P], C.c_int),
+        "slq_eff_net_classes": ([P, C.POINTER(i32)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -157,6 +172,13 @@ def slq_plan_destroy(plan: Plan):
 def slq_kinetic(plan: Plan, inverse: bool, out, stream=None):
     _need(out, torch.float64, (plan.n, plan.n), "out")
     _check(load_library().slq_kinetic(plan.handle, int(bool(inverse)), _ptr(out), _stream(stream)))
+
+
+def slq_magnetization(plan: Plan, s, M, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(M, torch.int64, (b,), "M")
+    _check(load_library().slq_magnetization(plan.handle, b, _ptr(s), _ptr(M), _stream(stream)))
 
 
 def slq_profile_enable(plan: Plan, enable: bool = True):
@@ -299,3 +321,104 @@ def slq_fit_effective(plan: Plan, eff: Eff, S, logabs, theta, r2, stream=None):
     _need(r2, torch.float64, (1,), "r2")
     _check(load_library().slq_fit_effective(plan.handle, eff.handle, n, _ptr(S), _ptr(logabs), _ptr(theta),
                                              _ptr(r2), _stream(stream)))
+
+
+# ------------------------------------------------------------------ group ----
+class Group:
+    """Owns an slq_group: chains of uneven (N, L), one graph launch per evaluation."""
+
+    def __init__(self, models, chain_prec: int = 0):
+        import numpy as np
+        lib = load_library()
+        self.models = list(models)
+        arr = (slq_model * len(self.models))(*[slq_model.of(m, chain_prec) for m in self.models])
+        h = C.c_void_p()
+        _check(lib.slq_group_create(arr, len(self.models), C.byref(h)))
+        self.handle = h
+        n = len(self.models)
+        so = np.zeros(n + 1, dtype=np.int64)
+        go = np.zeros(n + 1, dtype=np.int64)
+        _check(lib.slq_group_layout(h, so.ctypes.data_as(C.c_void_p), go.ctypes.data_as(C.c_void_p)))
+        self.s_off, self.g_off = so, go
+
+    def describe(self) -> dict:
+        import json
+        buf = C.create_string_buffer(1 << 16)
+        _check(load_library().slq_group_describe(self.handle, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def pack(self, fields):
+        """Pack per-chain int8 [L_c][N_c] arrays into the group's layout (host)."""
+        import numpy as np
+        out = np.empty(int(self.s_off[-1]), dtype=np.int8)
+        for c, f in enumerate(fields):
+            out[self.s_off[c]:self.s_off[c + 1]] = np.asarray(f, dtype=np.int8).reshape(-1)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().slq_group_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def slq_group_weight(group: Group, s, logabs, sign, status=None, stream=None):
+    n = len(group.models)
+    _need(s, torch.int8, (int(group.s_off[-1]),), "s")
+    _need(logabs, torch.float64, (n,), "logabs")
+    _need(sign, torch.int8, (n,), "sign")
+    _check(load_library().slq_group_weight(group.handle, _ptr(s), _ptr(logabs), _ptr(sign), _ptr(status),
+                                            _stream(stream)))
+
+
+def slq_group_green(group: Group, s, G, logabs, sign, status=None, stream=None):
+    n = len(group.models)
+    _need(s, torch.int8, (int(group.s_off[-1]),), "s")
+    _need(G, torch.float64, (int(group.g_off[-1]),), "G")
+    _need(logabs, torch.float64, (n,), "logabs")
+    _need(sign, torch.int8, (n,), "sign")
+    _check(load_library().slq_group_green(group.handle, _ptr(s), _ptr(G), _ptr(logabs), _ptr(sign), _ptr(status),
+                                           _stream(stream)))
+
+
+# -------------------------------------------------------- learned action ----
+def slq_net_forward(plan: Plan, net_prec: int, s, params, S, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(params, torch.float64, (SLQ_NET_PARAMS,), "params")
+    _need(S, torch.float64, (b,), "S")
+    _check(load_library().slq_net_forward(plan.handle, int(net_prec), b, _ptr(s), _ptr(params), _ptr(S),
+                                           _stream(stream)))
+
+
+def slq_net_gradient(plan: Plan, eff: Eff, net_prec: int, s, y, params, grad, loss=None, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(y, torch.float64, (b,), "y")
+    _need(params, torch.float64, (SLQ_NET_PARAMS,), "params")
+    _need(grad, torch.float64, (SLQ_NET_PARAMS,), "grad")
+    _check(load_library().slq_net_gradient(plan.handle, eff.handle, int(net_prec), b, _ptr(s), _ptr(y),
+                                            _ptr(params), _ptr(grad), _ptr(loss), _stream(stream)))
+
+
+def slq_net_adam(params, grad, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    n = params.numel()
+    _check(load_library().slq_net_adam(n, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t), float(lr),
+                                        float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def slq_eff_set_net(eff: Eff, params, net_prec: int = SLQ_PREC_FP32, stream=None):
+    if params is not None:
+        _need(params, torch.float64, (SLQ_NET_PARAMS,), "params")
+    _check(load_library().slq_eff_set_net(eff.handle, _ptr(params), int(net_prec), _stream(stream)))
+
+
+def slq_eff_net_classes(eff: Eff) -> int:
+    v = C.c_int32()
+    _check(load_library().slq_eff_net_classes(eff.handle, C.byref(v)))
+    return v.value

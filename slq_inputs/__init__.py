@@ -120,3 +120,17 @@ def default_terms(n_slices: int) -> list[tuple[int, int]]:
     """Coupling terms (spatial shell r, time separation dl) of the effective
     action: 2 spatial, L/2 temporal and 4 space-time terms (16 at L=20)."""
     return [(1, 0), (2, 0)] + [(0, dl) for dl in range(1, n_slices // 2 + 1)] + [(1, 1), (1, 2), (2, 1), (2, 2)]
+
+
+NET_PARAMS = 8 * 27 + 8 + 8 * 8 * 27 + 8 + 8 + 1
+
+
+def net_init(key: int, scale: float = 1.0) -> np.ndarray:
+    """Seeded initial parameters of the learned action's network (1969 FP64
+    values in the order W1, b1, W2, b2, w3, b3): normal weights with fan-in
+    scaling, zero biases, small readout weights."""
+    g = rng(key)
+    w1 = g.normal(scale=scale / np.sqrt(27.0), size=8 * 27)
+    w2 = g.normal(scale=scale / np.sqrt(8 * 27.0), size=8 * 8 * 27)
+    w3 = g.normal(scale=0.01, size=8)
+    return np.concatenate([w1, np.zeros(8), w2, np.zeros(8), w3, [0.0]])

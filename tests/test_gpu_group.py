@@ -1,0 +1,67 @@
+"""Groups of chains of uneven size evaluated by one graph launch: parity with
+the oracle per chain, and graph replays (with eager work and synchronisation
+in between) that reproduce the first result exactly."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import stable
+from slq_inputs import uneven_models, iid_field
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def slq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1612_03804_amd import slq as mod
+    mod.load_library()
+    return mod
+
+
+def test_uneven_group_parity_and_replays(slq):
+    from tests.gpu_util import dev, host
+    models = uneven_models(64, 4000)
+    fields = [iid_field(m, 4100 + c) for c, m in enumerate(models)]
+    grp = slq.Group(models)
+    info = grp.describe()
+    assert info["chains"] == 64 and sum(b["chains"] for b in info["batches"]) == 64
+    assert {t["N"] for t in info["tuned"]} == {b["N"] for b in info["batches"]}
+    s = dev(grp.pack(fields))
+    G = torch.empty(int(grp.g_off[-1]), dtype=torch.float64, device="cuda")
+    la = torch.empty(64, dtype=torch.float64, device="cuda")
+    sg = torch.empty(64, dtype=torch.int8, device="cuda")
+    st = torch.empty(64, dtype=torch.int32, device="cuda")
+    slq.slq_group_green(grp, s, G, la, sg, st)
+    G0, la0, sg0, st0 = host(G), host(la), host(sg), host(st)
+    assert np.all(st0 == 0)
+    # oracle on a subset covering every lattice size
+    seen = set()
+    for c, m in enumerate(models):
+        if (m.lx, m.n_slices) in seen and c % 9:
+            continue
+        seen.add((m.lx, m.n_slices))
+        ref_la, ref_sg, ref_G = stable.green(m, fields[c])
+        Gc = G0[grp.g_off[c]:grp.g_off[c + 1]].reshape(m.n_sites, m.n_sites)
+        assert sg0[c] == ref_sg and abs(la0[c] - ref_la) < 1e-12 * abs(ref_la), c
+        assert np.max(np.abs(Gc - ref_G)) < 1e-10, c
+    # replays of the recorded graph, with eager library work in between
+    plan = slq.Plan(models[0], 1)
+    one = dev(fields[0][None])
+    la1 = torch.empty(1, dtype=torch.float64, device="cuda")
+    sg1 = torch.empty(1, dtype=torch.int8, device="cuda")
+    for rep in range(3):
+        la.fill_(0.0)
+        G.fill_(0.0)
+        slq.slq_weight(plan, one, la1, sg1)
+        torch.cuda.synchronize()
+        slq.slq_group_green(grp, s, G, la, sg, st)
+        assert np.array_equal(host(la), la0) and np.array_equal(host(G), G0), rep
+        assert abs(host(la1)[0] - la0[0]) < 1e-12 * abs(la0[0])
+    # weight only through a second graph
+    la2 = torch.empty(64, dtype=torch.float64, device="cuda")
+    slq.slq_group_weight(grp, s, la2, sg, st)
+    assert np.array_equal(host(la2), la0)
+    plan.close()
+    grp.close()

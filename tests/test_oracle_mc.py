@@ -248,3 +248,18 @@ def test_tau_int_ar1(rho):
         x[t] = rho * x[t - 1] + noise[t]
     exact = (1 + rho) / (2 * (1 - rho))
     assert abs(autocorr.tau_int(x) - exact) < 0.06 * exact + 0.02
+
+
+# ------------------------------------------- package analysis vs oracle ----
+def test_package_tau_int_matches_ar1_and_oracle():
+    from paper_1612_03804_amd.analysis import tau_int_chains
+    g = np.random.default_rng(8)
+    rho, chains, T = 0.7, 64, 4000
+    x = np.empty((chains, T))
+    x[:, 0] = g.normal(size=chains) / np.sqrt(1 - rho * rho)
+    noise = g.normal(size=(chains, T))
+    for t in range(1, T):
+        x[:, t] = rho * x[:, t - 1] + noise[:, t]
+    exact = (1 + rho) / (2 * (1 - rho))
+    assert abs(tau_int_chains(x) - exact) < 0.05 * exact
+    assert abs(tau_int_chains(x[0]) - autocorr.tau_int(x[0])) < 0.1 * exact
