@@ -58,53 +58,94 @@ def cpu_baseline(model, terms, theta, fields, logabs, signs, steps, seed):
                       f"and one exact weight each), {dt:.1f} s"}
 
 
-def ess_rates(slq, plan, eff, s, logabs, sign, status, seed, n_moves, steps, dqmc_chains, sweeps, burn):
-    """Effective independent samples per second of the total magnetisation:
-    cumulative updates (all chains of the plan) against local DQMC sweeps
-    (the first `dqmc_chains` chains, restarted from the same fields)."""
+def ess_rates(slq, plan, model, terms, seed, steps, n_dq, sweeps, burn):
+    """Effective independent samples per second of the total magnetisation,
+    following the self-learning procedure: (i) local DQMC sweeps on n_dq
+    chains, timed, whose configurations and exact weights form the training
+    set; (ii) the effective model fitted to them; (iii)+(iv) cumulative updates
+    on all chains of the plan, started from the DQMC configurations, for a few
+    numbers of effective moves per update."""
+    import numpy as np
     import torch
     from paper_1612_03804_amd.analysis import tau_int_chains
-    dev = s.device
-    B = s.shape[0]
-    s_dq = s[:dqmc_chains].clone()
-    M = torch.empty((steps, B), dtype=torch.int64, device=dev)
-    acc = torch.empty(B, dtype=torch.int8, device=dev)
-    logA = torch.empty(B, dtype=torch.float64, device=dev)
-    for k in range(burn):
-        slq.slq_cumulative_step(plan, eff, s, logabs, sign, n_moves, seed, 10_000 + k, 0, acc, logA, status)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        slq.slq_cumulative_step(plan, eff, s, logabs, sign, n_moves, seed, 20_000 + k, 0, acc, logA, status)
-        slq.slq_magnetization(plan, s, M[k])
-    torch.cuda.synchronize()
-    t_sl = time.perf_counter() - t0
-    tau_sl = tau_int_chains(M.cpu().numpy().T)
-    n = dqmc_chains
-    G = torch.empty((n, plan.n, plan.n), dtype=torch.float64, device=dev)
-    la = torch.empty(n, dtype=torch.float64, device=dev)
-    sg = torch.empty(n, dtype=torch.int8, device=dev)
-    st = torch.empty(n, dtype=torch.int32, device=dev)
+    from slq_inputs import iid_fields
+    dev = torch.device("cuda")
+    B, L, N, n = plan.max_batch, model.n_slices, model.n_sites, n_dq
+    f64, i8, i32, i64 = torch.float64, torch.int8, torch.int32, torch.int64
+    s_dq = torch.from_numpy(iid_fields(model, n, 3000)).to(dev)
+    G = torch.empty((n, N, N), dtype=f64, device=dev)
+    la = torch.empty(n, dtype=f64, device=dev)
+    sg = torch.empty(n, dtype=i8, device=dev)
+    st = torch.empty(n, dtype=i32, device=dev)
+    a64 = torch.empty(n, dtype=i64, device=dev)
+    drift = torch.empty(n, dtype=f64, device=dev)
     slq.slq_green(plan, s_dq, G, la, sg, st)
-    a64 = torch.empty(n, dtype=torch.int64, device=dev)
-    drift = torch.empty(n, dtype=torch.float64, device=dev)
-    Md = torch.empty((sweeps, n), dtype=torch.int64, device=dev)
     slq.slq_sweep_local(plan, s_dq, G, la, sg, burn, seed, 0, 0, a64, drift, st)
+    train_s = torch.empty((sweeps, n, L, N), dtype=i8, device=dev)
+    train_la = torch.empty((sweeps, n), dtype=f64, device=dev)
+    Md = torch.empty((sweeps, n), dtype=i64, device=dev)
+    acc_dq = torch.zeros(n, dtype=i64, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(sweeps):
         slq.slq_sweep_local(plan, s_dq, G, la, sg, 1, seed, 1000 + k, 0, a64, drift, st)
         slq.slq_magnetization(plan, s_dq, Md[k])
+        train_s[k].copy_(s_dq)
+        train_la[k].copy_(la)
+        acc_dq += a64
     torch.cuda.synchronize()
     t_dq = time.perf_counter() - t0
     tau_dq = tau_int_chains(Md.cpu().numpy().T)
-    ess_sl = B * steps / (2 * tau_sl) / t_sl
     ess_dq = n * sweeps / (2 * tau_dq) / t_dq
-    return {"sldqmc": {"chains": B, "steps": steps, "tau_int_steps": tau_sl, "ess_per_s": ess_sl,
-                       "steps_per_s": B * steps / t_sl},
-            "dqmc_fp64": {"chains": n, "sweeps": sweeps, "tau_int_sweeps": tau_dq, "ess_per_s": ess_dq,
-                          "sweeps_per_s": n * sweeps / t_dq},
-            "burn_in": burn, "ess_ratio": ess_sl / ess_dq}
+
+    # (ii) fit on the DQMC configurations
+    eff = slq.Eff(plan, terms, np.zeros(len(terms)))
+    theta = torch.empty(1 + len(terms), dtype=f64, device=dev)
+    r2 = torch.empty(1, dtype=f64, device=dev)
+    slq.slq_fit_effective(plan, eff, train_s.view(-1, L, N), train_la.view(-1), theta, r2)
+    slq.slq_eff_set_theta(eff, theta)
+
+    # (iii)+(iv) cumulative updates from the DQMC end configurations
+    start = s_dq.repeat((B + n - 1) // n, 1, 1)[:B].contiguous()
+    runs = []
+    for n_moves in (max(1, eff.n_classes // 4), eff.n_classes, 4 * eff.n_classes):
+        s = start.clone()
+        logabs = torch.empty(B, dtype=f64, device=dev)
+        sign = torch.empty(B, dtype=i8, device=dev)
+        status = torch.empty(B, dtype=i32, device=dev)
+        slq.slq_weight(plan, s, logabs, sign, status)
+        acc = torch.empty((steps, B), dtype=i8, device=dev)
+        logA = torch.empty((steps, B), dtype=f64, device=dev)
+        M = torch.empty((steps, B), dtype=i64, device=dev)
+        for k in range(burn):
+            slq.slq_cumulative_step(plan, eff, s, logabs, sign, n_moves, seed, 10_000 + k, 0, acc[0], logA[0],
+                                    status)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            slq.slq_cumulative_step(plan, eff, s, logabs, sign, n_moves, seed, 20_000 + k, 0, acc[k], logA[k],
+                                    status)
+            slq.slq_magnetization(plan, s, M[k])
+        torch.cuda.synchronize()
+        t_sl = time.perf_counter() - t0
+        rate = float(acc.float().mean().item())
+        la_h = logA.cpu().numpy()
+        run = {"effective_moves": n_moves, "acceptance": rate, "logA_mean": float(la_h.mean()),
+               "logA_std": float(la_h.std()), "steps_per_s": B * steps / t_sl}
+        if rate > 0:   # a chain that never moves has no autocorrelation time
+            tau_sl = tau_int_chains(M.cpu().numpy().T)
+            run.update(tau_int_steps=tau_sl, ess_per_s=B * steps / (2 * tau_sl) / t_sl)
+        else:
+            run.update(tau_int_steps=None, ess_per_s=0.0)
+        runs.append(run)
+    eff.close()
+    best = max(runs, key=lambda r: r["ess_per_s"])
+    return {"dqmc_fp64": {"chains": n, "sweeps": sweeps, "tau_int_sweeps": tau_dq, "ess_per_s": ess_dq,
+                          "sweeps_per_s": n * sweeps / t_dq,
+                          "local_acceptance": float(acc_dq.sum().item()) / (n * sweeps * N * L)},
+            "fit": {"samples": n * sweeps, "terms": len(terms), "r2": float(r2.item())},
+            "sldqmc": {"chains": B, "steps": steps, "runs": runs},
+            "burn_in": burn, "ess_ratio": best["ess_per_s"] / ess_dq}
 
 
 def group_rate(slq, dev, reps: int = 5):
@@ -239,6 +280,11 @@ def main():
         nb = min(B, 64)
         acc = torch.empty(nb, dtype=torch.int64, device=dev)
         drift = torch.empty(nb, dtype=torch.float64, device=dev)
+        G2 = G[:nb].clone()
+        la2, sg2, st2 = logabs[:nb].clone(), sign[:nb].clone(), status[:nb].clone()
+        s2 = s[:nb].clone()
+        slq.slq_sweep_local(plan, s2, G2, la2, sg2, 1, seed, 0, 0, acc, drift, st2)  # allocates the stack
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         slq.slq_sweep_local(plan, s[:nb], G[:nb], logabs[:nb], sign[:nb], 1, seed, 0, 0, acc, drift, status[:nb])
         torch.cuda.synchronize()
@@ -249,8 +295,8 @@ def main():
         details["dqmc_max_drift"] = float(drift.max().item())
         details["group_64_uneven"] = group_rate(slq, dev)
     if args.ess:
-        details["ess"] = ess_rates(slq, plan, eff, s, logabs, sign, status, seed, n_moves, args.ess_steps,
-                                   args.ess_dqmc_chains, args.ess_sweeps, args.ess_burn)
+        details["ess"] = ess_rates(slq, plan, model, terms, seed, args.ess_steps, args.ess_dqmc_chains,
+                                   args.ess_sweeps, args.ess_burn)
     out["details"] = details
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(model, terms, theta_h, fields, la0, sg0, args.cpu_steps, seed)

@@ -193,8 +193,15 @@ int slq_group_green(slq_group* group, const int8_t* d_s, double* d_G, double* d_
  * Green's function whose cyclic chain ends at B_l; it is accepted iff
  * u < |R| (Metropolis on |W_f|) and G is updated by Sherman-Morrison
  * G -= (delta/R)(e_i - G[:,i]) G[i,:] (applied in delayed blocks).  After
- * each slice G <- B_l G B_l^{-1}; when l % n_stab == 0 G is recomputed from
- * the stabilised chain and the wrap drift max|G_wrapped - G_fresh| recorded.
+ * each slice G <- B_l G B_l^{-1}; when l % n_stab == 0 G is recomputed and
+ * the wrap drift max|G_wrapped - G_fresh| recorded.  The recomputation merges
+ * the stabilised product B_l...B_1 (extended block by block as the sweep
+ * moves up) with a stabilised B_L...B_{l+1} (built for every boundary when
+ * the sweep starts), so a sweep costs O(L N^3) rather than O(L^2 N^3 / n_stab).
+ * The first call with a given batch allocates that stack of partial products,
+ * (floor((L-1)/n_stab) + 1) * batch * (2N^2 + N) doubles, kept until the plan
+ * is destroyed (SLQ_ERR_DEVICE if it cannot); products are FP64 whatever the
+ * plan's chain precision.
  * u: key (seed, 1), counter (i, l-1, sweep0 + k, chain0 + b) for sweep k.
  * In/out: d_s [batch][L][N]; d_G [batch][N][N] must hold G of the incoming
  * fields (from slq_green) and holds G of the outgoing ones; d_logabs and
@@ -217,9 +224,12 @@ int slq_sweep_local(slq_plan* plan, int32_t batch, int8_t* d_s, double* d_G,
  * with time taken modulo L.  Shell r holds the lattice offsets of the r-th
  * smallest squared length (0: (0,0); 1: (+-1,0),(0,+-1); 2: (+-1,+-1);
  * 3: (+-2,0),(0,+-2); 4: (+-2,+-1),(+-1,+-2); 5: (+-2,+-2)).
+ * The term (r,dl) = (0,0) is the one-body term (a uniform field, the first
+ * of the terms Eq. 2 leaves as "..."): h = 1 and F = sum_x s_x; a single
+ * determinant has no s -> -s symmetry, so it is the leading term of ln|W_f|.
  * lambda_k = -beta J_k and c0 = -beta E_0, so S_eff approximates ln|W_f|
- * (Eq. 3).  A term needs 0 <= r <= 5, 0 <= dl <= L/2, (r,dl) != (0,0) and no
- * site may be its own partner.
+ * (Eq. 3).  A term needs 0 <= r <= 5, 0 <= dl <= L/2 and no site may be its
+ * own partner.
  * Effective moves (step iii) act on colour classes: one class is one time
  * slice and one colour of the greedy colouring (ascending site index,
  * smallest free colour) of the graph of dl = 0 couplings; class index =

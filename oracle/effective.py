@@ -8,9 +8,13 @@ separation dl >= 0.  The partner multiset of x = (i, l) is
     P_k(x) = {(i + delta, l + sigma dl mod L) : delta in shell r, sigma = +-1}  (dl > 0)
     P_k(x) = {(i + delta, l)                 : delta in shell r}              (dl = 0)
 
-h_k(x) = sum_{y in P_k(x)} s_y and F_k(s) = 1/2 sum_x s_x h_k(x).  The effective
-log-weight is S_eff = c0 + sum_k lambda_k F_k with lambda_k = -beta J_k and
-c0 = -beta E_0 (Eq. 3 fits it to ln omega).  Flipping x changes it by
+h_k(x) = sum_{y in P_k(x)} s_y and F_k(s) = 1/2 sum_x s_x h_k(x).  The term
+(0, 0) is the one-body term of the expansion (a uniform field on the
+auxiliary spins, the first of the terms Eq. (2) leaves as "..."): h(x) = 1 and
+F = sum_x s_x.  A single-determinant weight has no s -> -s symmetry, so this
+term carries most of the variance of ln omega.  The effective log-weight is
+S_eff = c0 + sum_k lambda_k F_k with lambda_k = -beta J_k and c0 = -beta E_0
+(Eq. 3 fits it to ln omega).  Flipping x changes it by
 dS = -2 s_x sum_k lambda_k h_k(x) whenever x is not its own partner.
 
 Effective moves (step iii): one move picks a colour class uniformly at random
@@ -51,8 +55,11 @@ def shell_offsets(r: int, max_shell: int = 8):
 
 
 def partners(model, term, i: int, l: int):
-    """Partner multiset P_k((i, l)) as a list of (site, slice) with slice 1-based."""
+    """Partner multiset P_k((i, l)) as a list of (site, slice) with slice 1-based
+    (empty for the one-body term)."""
     r, dl = term
+    if r == 0 and dl == 0:
+        return []
     lx, ly, L = model.lx, model.ly, model.n_slices
     x, y = i % lx, i // lx
     out = []
@@ -67,10 +74,10 @@ def partners(model, term, i: int, l: int):
 
 
 def check_terms(model, terms):
-    """A term is usable when 0 <= dl <= L/2, (r, dl) != (0, 0) and no site is its
-    own partner (which small tori can cause, e.g. (+-2, 0) on Lx = 2)."""
+    """A term is usable when 0 <= dl <= L/2 and no site is its own partner
+    (which small tori can cause, e.g. (+-2, 0) on Lx = 2)."""
     for r, dl in terms:
-        if dl < 0 or dl > model.n_slices // 2 or (r == 0 and dl == 0):
+        if dl < 0 or dl > model.n_slices // 2:
             raise ValueError(f"unusable term {(r, dl)}")
         if (0, 1) in partners(model, (r, dl), 0, 1):
             raise ValueError(f"term {(r, dl)} makes a site its own partner")
@@ -83,6 +90,9 @@ def local_fields(model, terms, s):
     s3 = np.asarray(s, dtype=np.float64).reshape(L, ly, lx)
     h = np.zeros((len(terms), L, ly, lx))
     for k, (r, dl) in enumerate(terms):
+        if r == 0 and dl == 0:
+            h[k] = 1.0
+            continue
         for dx, dy in shell_offsets(r):
             for sg in ((0,) if dl == 0 else (1, -1)):
                 h[k] += np.roll(s3, shift=(-sg * dl, -dy, -dx), axis=(0, 1, 2))
@@ -96,14 +106,19 @@ def local_fields_bruteforce(model, terms, s):
     for k, term in enumerate(terms):
         for l in range(1, L + 1):
             for i in range(n):
-                h[k, l - 1, i] = sum(int(s[ll - 1, j]) for j, ll in partners(model, term, i, l))
+                if term == (0, 0):
+                    h[k, l - 1, i] = 1
+                else:
+                    h[k, l - 1, i] = sum(int(s[ll - 1, j]) for j, ll in partners(model, term, i, l))
     return h
 
 
 def features(model, terms, s) -> np.ndarray:
-    """F_k(s) = 1/2 sum_x s_x h_k(x) (exact half-integers in FP64)."""
+    """F_k(s) = 1/2 sum_x s_x h_k(x), and sum_x s_x for the one-body term
+    (exact half-integers in FP64)."""
     h = local_fields(model, terms, s)
-    return 0.5 * np.einsum("li,kli->k", s.astype(np.float64), h)
+    half = np.array([1.0 if tuple(t) == (0, 0) else 0.5 for t in terms])
+    return half * np.einsum("li,kli->k", s.astype(np.float64), h)
 
 
 def action(model, terms, c0, lam, s) -> float:
@@ -115,7 +130,10 @@ def flip_delta(model, terms, lam, s, i: int, l: int) -> float:
     """dS for flipping (i, l): -2 s_x sum_k lambda_k h_k(x)."""
     tot = 0.0
     for k, term in enumerate(terms):
-        tot += lam[k] * sum(int(s[ll - 1, j]) for j, ll in partners(model, term, i, l))
+        if tuple(term) == (0, 0):
+            tot += lam[k]
+        else:
+            tot += lam[k] * sum(int(s[ll - 1, j]) for j, ll in partners(model, term, i, l))
     return -2.0 * float(s[l - 1, i]) * tot
 
 

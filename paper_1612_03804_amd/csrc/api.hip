@@ -80,12 +80,6 @@ int copy_i8(const int8_t* a, int8_t* b, long n, hipStream_t st) {
   return SLQ_OK;
 }
 
-#define SLQ_TRY(x)              \
-  do {                          \
-    int rc_ = (x);              \
-    if (rc_ != SLQ_OK) return rc_; \
-  } while (0)
-
 static int check_model(const slq_model* m) {
   if (!m) return fail(SLQ_ERR_ARG, "model is NULL");
   if (m->lx < 1 || m->ly < 1) return fail(SLQ_ERR_ARG, "lx and ly must be >= 1");
@@ -165,6 +159,7 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
   g.alpha = 1.0;
   g.beta = 0.0;
   g.batch = batch;
+  g.cfg = p.gemm_cfg;
   LpArgs h{};
   h.M = N;
   h.N = N;
@@ -402,6 +397,7 @@ int slq_plan_destroy(slq_plan* plan) {
   hipDeviceSynchronize();
   for (hipEvent_t e : plan->p.ev) hipEventDestroy(e);
   release_net(plan->p);
+  release_stack(plan->p);
   hipFree(plan->p.base);
   delete plan;
   return SLQ_OK;
@@ -461,8 +457,6 @@ int slq_sweep_local(slq_plan* plan, int32_t batch, int8_t* d_s, double* d_G, dou
   if (n_sweeps < 0) return fail(SLQ_ERR_ARG, "n_sweeps must be >= 0");
   if (!d_s || !d_G || !d_logabs || !d_sign) return fail(SLQ_ERR_ARG, "NULL device pointer");
   SLQ_HIP(hipSetDevice(p.device));
-  const int N = p.n, L = p.L;
-  const long NN = (long)N * N;
   int32_t* status = d_status ? d_status : p.status;
   int64_t* acc = d_accepts ? d_accepts : p.ivec;
   double* drift = d_drift ? d_drift : p.dvec2;
@@ -470,47 +464,7 @@ int slq_sweep_local(slq_plan* plan, int32_t batch, int8_t* d_s, double* d_G, dou
   SLQ_TRY(launch_check_spins(p, batch, d_s, status, st));
   SLQ_TRY(fill_i64(acc, batch, 0, st));
   SLQ_TRY(fill_f64(drift, batch, 0.0, st));
-  GemmArgs w1{};
-  w1.M = N;
-  w1.N = N;
-  w1.K = N;
-  w1.A = p.E;
-  w1.lda = N;
-  w1.strideA = 0;
-  w1.B = d_G;
-  w1.ldb = N;
-  w1.strideB = NN;
-  w1.C = p.Xa;
-  w1.ldc = N;
-  w1.strideC = NN;
-  w1.S = d_s;
-  w1.strideS = (long)L * N;
-  w1.inv_scale = 0;
-  w1.consts = p.consts;
-  w1.alpha = 1.0;
-  w1.batch = batch;
-  GemmArgs w2 = w1;  // G <- T diag(1/d_l) E^{-1}
-  w2.A = p.Xa;
-  w2.strideA = NN;
-  w2.B = p.Einv;
-  w2.strideB = 0;
-  w2.C = d_G;
-  w2.inv_scale = 1;
-  for (int k = 0; k < n_sweeps; ++k) {
-    for (int l = 1; l <= L; ++l) {
-      SLQ_TRY(launch_flip_slice(p, batch, d_s, d_G, d_logabs, d_sign, l - 1, seed, sweep0 + k, chain0, acc, st));
-      w1.slice = l - 1;
-      w2.slice = l - 1;
-      SLQ_TRY(launch_gemm(w1, false, false, st));
-      SLQ_TRY(launch_gemm(w2, false, false, st));
-      if (l % p.m.n_stab == 0) {
-        SLQ_TRY(run_chain(p, batch, d_s, l % L, status, st));
-        SLQ_TRY(launch_finish(p, batch, p.Xa, p.dvec, p.sgn_work, status, st));
-        SLQ_TRY(launch_drift(p, batch, d_G, p.Xa, drift, st));
-      }
-    }
-  }
-  return SLQ_OK;
+  return sweep_stacked(p, batch, d_s, d_G, d_logabs, d_sign, n_sweeps, seed, sweep0, chain0, acc, drift, status, st);
 }
 
 }  // extern "C"

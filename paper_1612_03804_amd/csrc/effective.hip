@@ -109,7 +109,8 @@ int launch_eff_sweep(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, u
 }
 
 // --------------------------------------------------------- features ----
-// F[b][k] = 1/2 sum_x s_x h_k(x); integer sums, exact.
+// F[b][k] = 1/2 sum_x s_x h_k(x), sum_x s_x for the one-body term; integer
+// sums, exact.
 __global__ __launch_bounds__(256) void k_features(EffDev d, const int8_t* s_all, double* F) {
   __shared__ long long acc[MAX_TERMS];
   const long b = blockIdx.x;
@@ -128,7 +129,10 @@ __global__ __launch_bounds__(256) void k_features(EffDev d, const int8_t* s_all,
     if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long*)&acc[k], (unsigned long long)part);
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < d.n_terms; k += blockDim.x) F[b * d.n_terms + k] = 0.5 * (double)acc[k];
+  for (int k = threadIdx.x; k < d.n_terms; k += blockDim.x) {
+    const bool one_body = d.terms[2 * k] == 0 && d.terms[2 * k + 1] == 0;
+    F[b * d.n_terms + k] = (one_body ? 1.0 : 0.5) * (double)acc[k];
+  }
 }
 
 int launch_features(Plan& p, const Eff& e, long count, const int8_t* s, double* F, hipStream_t st) {
@@ -317,8 +321,8 @@ int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const 
   std::vector<std::set<int>> nbr(N);
   for (int k = 0; k < n_terms; ++k) {
     const int r = terms[2 * k], dl = terms[2 * k + 1];
-    if (r < 0 || r > MAX_SHELL || dl < 0 || dl > L / 2 || (r == 0 && dl == 0))
-      return efail(SLQ_ERR_ARG, "unusable term (r, dl)");
+    if (r < 0 || r > MAX_SHELL || dl < 0 || dl > L / 2) return efail(SLQ_ERR_ARG, "unusable term (r, dl)");
+    if (r == 0 && dl == 0) continue;  // one-body term: no partners
     if (dl == 0) {
       for (int o = kShellOff[r]; o < kShellOff[r + 1]; ++o) {
         const int dx = ((kShellDxy[o][0] % lx) + lx) % lx, dy = ((kShellDxy[o][1] % ly) + ly) % ly;

@@ -40,7 +40,7 @@ __device__ __forceinline__ int acc_col(int lane, int r) { return lane & 15; }
 // and the wrap; a separate symbol so that profiles separate it).
 template <int WM, int WN, int GM, int GN, int TK, bool TA, bool TB, int MODE>
 __global__ __launch_bounds__(64 * GM * GN) void k_gemm(GemmArgs g, int ntm, int ntn) {
-  constexpr bool AUP = MODE == 1, FS = MODE == 2;
+  constexpr bool AUP = MODE == 1, FS = MODE == 2, FSO = MODE == 3;
   constexpr int TM = 16 * WM * GM, TN = 16 * WN * GN, NT = 64 * GM * GN;
   constexpr int APT = (TM * TK + NT - 1) / NT, BPT = (TK * TN + NT - 1) / NT;
   constexpr int PADM = TM + 2, PADN = TN + 2;
@@ -61,9 +61,9 @@ __global__ __launch_bounds__(64 * GM * GN) void k_gemm(GemmArgs g, int ntm, int 
 
   const double* A = g.A + (long)b * g.strideA;
   const double* B = g.B + (long)b * g.strideB;
-  const int8_t* S = FS ? g.S + (long)b * g.strideS + (long)g.slice * g.K : nullptr;
+  const int8_t* S = (FS || FSO) ? g.S + (long)b * g.strideS + (long)g.slice * g.K : nullptr;
   double rpos = 0.0, rneg = 0.0;
-  if (FS) {
+  if (FS || FSO) {
     rpos = g.consts[g.inv_scale ? 1 : 0];  // s = +1
     rneg = g.consts[g.inv_scale ? 0 : 1];  // s = -1
   }
@@ -169,6 +169,7 @@ __global__ __launch_bounds__(64 * GM * GN) void k_gemm(GemmArgs g, int ntm, int 
         if (gm < g.M && gn < g.N) {
           double v = g.alpha * acc[i][jj][r];
           if (RS) v *= RS[gm];
+          if (FSO) v *= (S[gm] > 0) ? rpos : rneg;
           const long o = (long)gm * g.ldc + gn;
           C[o] = (g.beta != 0.0) ? v + g.beta * C[o] : v;
         }
@@ -192,6 +193,12 @@ static int run(const GemmArgs& a, bool ta, bool tb, hipStream_t st) {
   }
   if (a.a_upper) {
     k_gemm<WM, WN, GM, GN, TK, false, false, 1><<<grid, block, 0, st>>>(a, ntm, ntn);
+  } else if (a.S && a.s_out) {
+    if (a.M != a.K) {
+      set_error("output-row field scaling needs M == K");
+      return SLQ_ERR_ARG;
+    }
+    k_gemm<WM, WN, GM, GN, TK, false, false, 3><<<grid, block, 0, st>>>(a, ntm, ntn);
   } else if (a.S) {
     k_gemm<WM, WN, GM, GN, TK, false, false, 2><<<grid, block, 0, st>>>(a, ntm, ntn);
   } else if (!ta && !tb) {
@@ -226,22 +233,6 @@ int launch_gemm_cfg(const GemmArgs& a, bool ta, bool tb, int cfg, hipStream_t st
   }
 }
 
-// Tile shapes picked by the autotuner for square N x N x N products (the
-// chain), keyed by N; shared by every plan of the process.
-static std::mutex g_tune_mu;
-static std::map<int, int> g_tuned;
-
-void set_tuned_gemm(int n, int cfg) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuned[n] = cfg;
-}
-
-int tuned_gemm(int n) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tuned.find(n);
-  return it == g_tuned.end() ? -1 : it->second;
-}
-
 // Default tile choice: thin panels get 32 x 64 tiles; otherwise the largest
 // square tile that divides both M and N, else 64 x 64 with ragged edges.
 // K is staged 4-8 deep: the small LDS footprint keeps several workgroups
@@ -262,7 +253,7 @@ int default_gemm(int M, int N) {
 
 int launch_gemm(const GemmArgs& a, bool ta, bool tb, hipStream_t st) {
   int cfg = -1;
-  if (a.M == a.N && a.N == a.K && !ta && !tb) cfg = tuned_gemm(a.M);
+  if (a.cfg >= 0) cfg = a.cfg;
   if (cfg < 0) cfg = default_gemm(a.M, a.N);
   return launch_gemm_cfg(a, ta, tb, cfg, st);
 }

@@ -77,12 +77,12 @@ static bool same_model(const slq_model& a, const slq_model& b) {
          a.mu == b.mu && a.dtau == b.dtau && a.xi == b.xi && a.chain_prec == b.chain_prec;
 }
 
-// Time every candidate tile shape of the FP64 chain GEMM for one N on the
-// sub-plan's own buffers and keep the fastest for the process.
+// Time every candidate tile shape of the FP64 chain GEMM on the sub-plan's
+// own buffers and batch size, and keep the fastest for that sub-plan.
 static int autotune(Group& g, SubPlan& sp) {
   Plan& p = sp.plan->p;
   const int N = p.n;
-  if (p.m.chain_prec != SLQ_PREC_FP64 || tuned_gemm(N) >= 0) return SLQ_OK;
+  if (p.m.chain_prec != SLQ_PREC_FP64 || p.gemm_cfg >= 0) return SLQ_OK;
   std::vector<int> cands;
   if (N <= 32) {
     cands = {GEMM_16, GEMM_32x64, GEMM_64};
@@ -132,7 +132,7 @@ static int autotune(Group& g, SubPlan& sp) {
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc != SLQ_OK) return rc;
-  set_tuned_gemm(N, best);
+  p.gemm_cfg = best;
   g.tuned_n.push_back(N);
   g.tuned_cfg.push_back(best);
   g.tuned_tflops.push_back(2.0 * (double)N * N * N * sp.nb * 3 / (best_ms * 1e-3) / 1e12);

@@ -307,13 +307,14 @@ static size_t finish_lds(int N, int nb) {
   return panel + sizeof(double) * FN_WAVES + sizeof(int) * (FN_WAVES + 2);
 }
 
-int launch_finish(Plan& p, int batch, double* G, double* logabs, int8_t* sign, int32_t* status, hipStream_t st) {
+int launch_finish(Plan& p, int batch, const UdvRef& f, double* G, double* logabs, int8_t* sign, int32_t* status,
+                  hipStream_t st) {
   FinishArgs a;
   a.N = p.n;
-  a.U = p.U;
-  a.D = p.D;
-  a.V = p.V;
-  a.nref = p.nref;
+  a.U = f.U;
+  a.D = f.D;
+  a.V = f.V;
+  a.nref = f.nref;
   a.W = p.W;
   a.ipiv = p.ipiv;
   a.G = G;

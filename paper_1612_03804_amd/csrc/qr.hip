@@ -325,17 +325,17 @@ static size_t qr_lds(int N, int nb) {
 
 int qr_panel_width(int N) { return N <= 1024 ? 16 : 8; }
 
-int launch_qr(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st) {
+int launch_qr(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st) {
   QrArgs a;
   a.N = p.n;
   a.X = X;
   a.W = p.W;
-  a.U = p.U;
-  a.D = p.D;
+  a.U = o.U;
+  a.D = o.D;
   a.invD = p.invD;
   a.perm = p.perm;
   a.Tblk = p.Tblk;
-  a.nref = p.nref;
+  a.nref = o.nref;
   a.status = status;
   const int nb = qr_panel_width(p.n);
   const size_t lds = qr_lds(p.n, nb);

@@ -256,7 +256,7 @@ __global__ void k_zero_i32(int32_t* x, int n) {
 }
 
 template <int NB>
-static int run_blocked(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st) {
+static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st) {
   const int N = p.n;
   const long NN = (long)N * N;
   // scratch: Vbuf = Xb-or-Xa not holding X (both are free once W is written), Y, Wt
@@ -266,14 +266,14 @@ static int run_blocked(Plan& p, int batch, const double* X, int32_t* status, hip
   double* Wt = p.dY;    // [b][NB][N]
   const size_t lpp = sizeof(double) * N + sizeof(int) * N;
   allow_max_lds((const void*)k_prepivot);
-  k_prepivot<<<batch, PQ_THREADS, lpp, st>>>(N, X, p.W, p.D, p.perm, status);
+  k_prepivot<<<batch, PQ_THREADS, lpp, st>>>(N, X, p.W, o.D, p.perm, status);
   SLQ_LAUNCHED();
-  k_zero_i32<<<(batch + 255) / 256, 256, 0, st>>>(p.nref, batch);
+  k_zero_i32<<<(batch + 255) / 256, 256, 0, st>>>(o.nref, batch);
   SLQ_LAUNCHED();
   const int npanel = (N + NB - 1) / NB;
   for (int pi = 0; pi < npanel; ++pi) {
     const int j0 = pi * NB, nbw = std::min(NB, N - j0), m = N - j0, nt = N - j0 - nbw;
-    PanelArgs a{N, j0, nbw, p.W, Vbuf, Zbuf, Ybuf, p.D, p.invD, p.nref, status};
+    PanelArgs a{N, j0, nbw, p.W, Vbuf, Zbuf, Ybuf, o.D, p.invD, o.nref, status};
     const size_t lds = sizeof(double) * ((size_t)NB * (m + 1) + 2 * NB * NB + 2 * NB + PQ_WAVES);
     allow_max_lds((const void*)k_panel<NB>);
     k_panel<NB><<<batch, PQ_THREADS, lds, st>>>(a);
@@ -316,7 +316,7 @@ static int run_blocked(Plan& p, int batch, const double* X, int32_t* status, hip
     if (rc != SLQ_OK) return rc;
   }
   // explicit Q, backwards: U[j0:, j0:] -= Z (V^T U[j0:, j0:])
-  int rc = launch_set_identity(p, batch, p.U, st);
+  int rc = launch_set_identity(p, batch, o.U, st);
   if (rc != SLQ_OK) return rc;
   for (int pi = npanel - 1; pi >= 0; --pi) {
     const int j0 = pi * NB, nbw = std::min(NB, N - j0), m = N - j0;
@@ -327,7 +327,7 @@ static int run_blocked(Plan& p, int batch, const double* X, int32_t* status, hip
     g1.A = Vbuf + (long)j0 * N + j0;
     g1.lda = N;
     g1.strideA = NN;
-    g1.B = p.U + (long)j0 * N + j0;
+    g1.B = o.U + (long)j0 * N + j0;
     g1.ldb = N;
     g1.strideB = NN;
     g1.C = Wt;
@@ -347,7 +347,7 @@ static int run_blocked(Plan& p, int batch, const double* X, int32_t* status, hip
     g2.B = Wt;
     g2.ldb = N;
     g2.strideB = (long)NB * N;
-    g2.C = p.U + (long)j0 * N + j0;
+    g2.C = o.U + (long)j0 * N + j0;
     g2.ldc = N;
     g2.strideC = NN;
     g2.alpha = -1.0;
@@ -361,11 +361,11 @@ static int run_blocked(Plan& p, int batch, const double* X, int32_t* status, hip
 
 int qr_blocked_width(int N) { return N <= 448 ? 32 : (N <= 1100 ? 16 : 8); }
 
-int launch_qr_blocked(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st) {
+int launch_qr_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st) {
   switch (qr_blocked_width(p.n)) {
-    case 32: return run_blocked<32>(p, batch, X, status, st);
-    case 16: return run_blocked<16>(p, batch, X, status, st);
-    default: return run_blocked<8>(p, batch, X, status, st);
+    case 32: return run_blocked<32>(p, batch, X, o, status, st);
+    case 16: return run_blocked<16>(p, batch, X, o, status, st);
+    default: return run_blocked<8>(p, batch, X, o, status, st);
   }
 }
 

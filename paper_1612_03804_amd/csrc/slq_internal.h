@@ -33,6 +33,13 @@ void set_error(const std::string& msg);
     }                                                                              \
   } while (0)
 
+// Return the status of a library call from the enclosing function unless OK.
+#define SLQ_TRY(x)                 \
+  do {                             \
+    int rc_ = (x);                 \
+    if (rc_ != SLQ_OK) return rc_; \
+  } while (0)
+
 // Raise a kernel's dynamic-LDS limit to the 160 KiB of a gfx950 CU, once per
 // kernel and process (so no attribute call happens while a graph is recorded).
 inline void allow_max_lds(const void* fn) {
@@ -145,6 +152,12 @@ struct Plan {
   double prof_flops = 0.0;
   // learned-action workspace, allocated on first use
   void* net_state = nullptr;
+  // tile configuration of the FP64 chain GEMM chosen by the autotuner (-1: default)
+  int gemm_cfg = -1;
+  // stabilised partial products kept by local sweeps, allocated on first use
+  // for stack_batch fields (see sweep_stacked)
+  double* stack = nullptr;
+  int stack_batch = 0;
 };
 
 struct Eff {
@@ -182,9 +195,11 @@ struct EffDev {
 };
 EffDev eff_dev_view(const Plan& p, const Eff& e);
 
-// h_k((i, l)) of term k at site i, slice l (0-based) of one field s [L][N]
+// h_k((i, l)) of term k at site i, slice l (0-based) of one field s [L][N];
+// 1 for the one-body term (0, 0)
 __device__ __forceinline__ int local_field_dev(const EffDev& d, const int8_t* __restrict__ s, int k, int i, int l) {
   const int r = d.terms[2 * k], dl = d.terms[2 * k + 1];
+  if (r == 0 && dl == 0) return 1;
   const int x = i % d.lx, y = i / d.lx;
   int h = 0;
   const int lp = (l + dl) % d.L, lm = (l - dl + d.L) % d.L;
@@ -225,6 +240,8 @@ struct GemmArgs {
   long strideRS;
   double alpha, beta;
   int a_upper;        // A is upper triangular: entries with k < m are taken as zero
+  int s_out;          // apply the field factor to the rows of C instead of the rows of op(B)
+  int cfg = -1;       // tile configuration (GemmCfg), -1 = default choice
   int batch;
 };
 int launch_gemm(const GemmArgs& a, bool transA, bool transB, hipStream_t st);
@@ -243,8 +260,6 @@ enum GemmCfg {
 };
 int launch_gemm_cfg(const GemmArgs& a, bool transA, bool transB, int cfg, hipStream_t st);
 int default_gemm(int M, int N);
-void set_tuned_gemm(int n, int cfg);
-int tuned_gemm(int n);
 
 // Reduced-precision chain GEMM: C(f32)[b] = A(f32, shared) diag(d_slice) B[b] (f32 or f64)
 struct LpArgs {
@@ -269,13 +284,39 @@ int launch_narrow(const double* a, float* b, long n, hipStream_t st);
 // Chain helpers
 int launch_first_slice(Plan& p, int batch, const int8_t* s, long strideS, int slice, double* X, hipStream_t st);
 int launch_set_identity(Plan& p, int batch, double* X, hipStream_t st);
-// X -> W (R above the diagonal), U (Q), D, invD, perm, nref.  launch_qr keeps
-// one workgroup per field for the whole factorisation (small N);
-// launch_qr_blocked factors panels in LDS and updates with MFMA GEMMs.
-int launch_qr(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st);
-int launch_qr_blocked(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st);
+// A stabilised factorisation U D V of [batch] fields, N x N / N / N x N per
+// field packed densely, plus the Householder count whose parity is det U.
+struct UdvRef {
+  double* U;
+  double* D;
+  double* V;
+  int32_t* nref;
+};
+inline UdvRef plan_udv(Plan& p) { return UdvRef{p.U, p.D, p.V, p.nref}; }
+
+// QR of X diag(o.D) with column pre-pivoting.  Reads o.D, then overwrites it
+// with |diag R|; writes Q to o.U, the reflection count to o.nref, R above the
+// diagonal to W, and invD, perm.  launch_qr keeps one workgroup per field for
+// the whole factorisation (small N); launch_qr_blocked factors panels in LDS
+// and updates with MFMA GEMMs (it uses Xa or Xb, whichever does not hold X,
+// and Vt, dX, dY as scratch).
+int launch_qr(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st);
+int launch_qr_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st);
+inline int launch_qr(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st) {
+  return launch_qr(p, batch, X, plan_udv(p), status, st);
+}
+inline int launch_qr_blocked(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st) {
+  return launch_qr_blocked(p, batch, X, plan_udv(p), status, st);
+}
 int launch_permute_rows(Plan& p, int batch, const double* V, double* Vt, hipStream_t st);
-int launch_finish(Plan& p, int batch, double* G, double* logabs, int8_t* sign, int32_t* status, hipStream_t st);
+// log|det(1 + U D V)|, its sign and optionally G = (1 + U D V)^{-1}; W and ipiv
+// are scratch.
+int launch_finish(Plan& p, int batch, const UdvRef& f, double* G, double* logabs, int8_t* sign, int32_t* status,
+                  hipStream_t st);
+inline int launch_finish(Plan& p, int batch, double* G, double* logabs, int8_t* sign, int32_t* status,
+                         hipStream_t st) {
+  return launch_finish(p, batch, plan_udv(p), G, logabs, sign, status, st);
+}
 int launch_check_spins(Plan& p, int batch, const int8_t* s, int32_t* status, hipStream_t st);
 
 int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, hipStream_t st);
@@ -290,6 +331,10 @@ int copy_i8(const int8_t* a, int8_t* b, long n, hipStream_t st);
 int launch_flip_slice(Plan& p, int batch, int8_t* s, double* G, double* logabs, int8_t* sign, int slice,
                       uint64_t seed, uint64_t sweep, uint64_t chain0, int64_t* accepts, hipStream_t st);
 int launch_drift(Plan& p, int batch, double* Gw, const double* Gf, double* drift, hipStream_t st);
+int sweep_stacked(Plan& p, int batch, int8_t* s, double* G, double* logabs, int8_t* sign, int n_sweeps,
+                  uint64_t seed, uint64_t sweep0, uint64_t chain0, int64_t* accepts, double* drift,
+                  int32_t* status, hipStream_t st);
+void release_stack(Plan& p);
 
 // Effective model
 int launch_eff_sweep(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, uint64_t seed, uint64_t step,

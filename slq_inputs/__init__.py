@@ -117,9 +117,11 @@ def uneven_models(count: int = 64, key: int = 4000, base: Model | None = None) -
 
 
 def default_terms(n_slices: int) -> list[tuple[int, int]]:
-    """Coupling terms (spatial shell r, time separation dl) of the effective
-    action: 2 spatial, L/2 temporal and 4 space-time terms (16 at L=20)."""
-    return [(1, 0), (2, 0)] + [(0, dl) for dl in range(1, n_slices // 2 + 1)] + [(1, 1), (1, 2), (2, 1), (2, 2)]
+    """Terms (spatial shell r, time separation dl) of the effective action: the
+    one-body term (0, 0), then 2 spatial, L/2 temporal and 4 space-time
+    couplings (1 + 16 at L=20)."""
+    return ([(0, 0), (1, 0), (2, 0)] + [(0, dl) for dl in range(1, n_slices // 2 + 1)]
+            + [(1, 1), (1, 2), (2, 1), (2, 2)])
 
 
 NET_PARAMS = 8 * 27 + 8 + 8 * 8 * 27 + 8 + 8 + 1

@@ -71,7 +71,19 @@ def test_shells():
 
 
 def test_default_terms_count():
-    assert len(default_terms(20)) == 16          # 2 spatial + 10 temporal + 4 space-time
+    assert len(default_terms(20)) == 17          # one-body + 2 spatial + 10 temporal + 4 space-time
+
+
+def test_one_body_term_is_the_magnetisation():
+    """F of the term (0, 0) is sum_x s_x, its local field is 1 and a flip of x
+    changes it by -2 s_x, independently of every other site."""
+    m = Model(3, 4, 6, xi=1.0)
+    s = iid_field(m, 23)
+    f = effective.features(m, [(0, 0), (1, 0)], s)
+    assert f[0] == int(s.astype(np.int64).sum())
+    assert np.array_equal(effective.local_fields(m, [(0, 0)], s)[0], np.ones((6, 12)))
+    assert effective.flip_delta(m, [(0, 0)], [0.3], s, 4, 2) == -2.0 * 0.3 * s[1, 4]
+    assert effective.partners(m, (0, 0), 4, 2) == []
 
 
 def test_local_fields_vectorised_equals_partner_lists():
@@ -127,9 +139,9 @@ def _states(m):
 def test_cumulative_update_detailed_balance_exact():
     """Exact transition matrix on the 2x2, L=2 space (256 states)."""
     m = Model(2, 2, 2, t=1.0, mu=-0.3, dtau=0.4, xi=1.2, n_stab=1)
-    terms = [(1, 0), (2, 0), (0, 1), (1, 1)]
+    terms = [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1)]
     effective.check_terms(m, terms)
-    lam = np.array([0.15, -0.05, 0.3, 0.02])
+    lam = np.array([-0.2, 0.15, -0.05, 0.3, 0.02])
     states = _states(m)
     ns = len(states)
     w = np.array([stable.weight(m, s)[0] for s in states])
