@@ -59,14 +59,21 @@ enum {
   SLQ_ST_SINGULAR = 4     /* the final matrix M has a zero pivot (W_f = 0) */
 };
 
-/* Operand precision of the chain product X <- E diag(d_l) X.  The QR/UDV
- * stabilisation, the final LU, log-det and G are FP64 in every mode; in the
- * reduced modes E and X are rounded to the operand type at every GEMM, the
- * matrix cores accumulate in FP32 and X is kept in FP32 between slices. */
+/* How the chain product X <- E diag(d_l) X is formed.  The QR/UDV
+ * stabilisation, the final LU, log-det and G are FP64 in every mode.
+ * SLQ_PREC_FP64: FP64, using that E = e^{dtau mu} Cx (x) Cy is a Kronecker
+ *   product of two circulants on the periodic lattice (lattice lines along x,
+ *   then along y: 2N^2 (lx+ly) flops per slice and field instead of 2N^3;
+ *   lattices with lx or ly > 64 fall back to the dense FP64 product).
+ * SLQ_PREC_FP64_DENSE: FP64 dense GEMMs with E on the matrix cores.
+ * SLQ_PREC_FP32 / SLQ_PREC_BF16: dense GEMMs with E and X rounded to the
+ *   operand type at every GEMM, FP32 accumulation on the matrix cores, X kept
+ *   in FP32 between slices. */
 enum {
   SLQ_PREC_FP64 = 0,
   SLQ_PREC_FP32 = 1,
-  SLQ_PREC_BF16 = 2
+  SLQ_PREC_BF16 = 2,
+  SLQ_PREC_FP64_DENSE = 3
 };
 
 typedef struct slq_model {

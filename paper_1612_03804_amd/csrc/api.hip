@@ -90,8 +90,8 @@ static int check_model(const slq_model* m) {
   if (!(m->dtau > 0.0) || !std::isfinite(m->dtau)) return fail(SLQ_ERR_ARG, "dtau must be positive and finite");
   if (!std::isfinite(m->t) || !std::isfinite(m->mu) || !std::isfinite(m->xi))
     return fail(SLQ_ERR_ARG, "t, mu and xi must be finite");
-  if (m->chain_prec < SLQ_PREC_FP64 || m->chain_prec > SLQ_PREC_BF16)
-    return fail(SLQ_ERR_ARG, "chain_prec must be SLQ_PREC_FP64, SLQ_PREC_FP32 or SLQ_PREC_BF16");
+  if (m->chain_prec < SLQ_PREC_FP64 || m->chain_prec > SLQ_PREC_FP64_DENSE)
+    return fail(SLQ_ERR_ARG, "chain_prec must be SLQ_PREC_FP64, SLQ_PREC_FP32, SLQ_PREC_BF16 or SLQ_PREC_FP64_DENSE");
   return SLQ_OK;
 }
 
@@ -103,7 +103,7 @@ int check_batch(const Plan& p, long batch) {
   return SLQ_OK;
 }
 
-// One chain-product GEMM X <- E diag(d_l) X, bracketed by events when timing is on.
+// One chain-product launch (a block of X <- E diag(d_l) X), bracketed by events when timing is on.
 template <typename F>
 static int timed_chain(Plan& p, double flops, hipStream_t st, F launch) {
   if (!p.prof) return launch();
@@ -126,6 +126,11 @@ static int timed_chain(Plan& p, double flops, hipStream_t st, F launch) {
 static int timed_chain_gemm(Plan& p, const GemmArgs& g, hipStream_t st) {
   return timed_chain(p, 2.0 * (double)g.M * g.N * g.K * g.batch, st,
                      [&]() { return launch_gemm(g, false, false, st); });
+}
+
+static int timed_chain_kron(Plan& p, const KronArgs& k, hipStream_t st) {
+  const double flops = 2.0 * (double)p.n * p.n * (p.m.lx + p.m.ly) * k.count * k.batch;
+  return timed_chain(p, flops, st, [&]() { return launch_kron(p, k, st); });
 }
 
 static int timed_chain_lp(Plan& p, const LpArgs& g, bool b_is_f64, hipStream_t st) {
@@ -174,12 +179,26 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
   h.strideS = strideS;
   h.consts = p.consts;
   h.batch = batch;
-  const bool lp = p.m.chain_prec != SLQ_PREC_FP64;
+  const bool lp = p.m.chain_prec == SLQ_PREC_FP32 || p.m.chain_prec == SLQ_PREC_BF16;
+  const bool kron = p.m.chain_prec == SLQ_PREC_FP64 && p.kron_P > 0;
   for (int j0 = 0; j0 < L; j0 += ns) {
     const int jend = std::min(j0 + ns, L);
     double* cur = p.Xa;
     double* oth = p.Xb;
-    if (!lp) {
+    if (kron) {
+      KronArgs k{};
+      k.in = j0 == 0 ? nullptr : p.U;
+      k.strideIn = NN;
+      k.out = cur;
+      k.strideOut = NN;
+      k.s = s;
+      k.slice0 = (slice0 + j0) % L;
+      k.count = jend - j0;
+      k.step = 1;
+      k.scale = 1;
+      k.batch = batch;
+      SLQ_TRY(timed_chain_kron(p, k, st));
+    } else if (!lp) {
       if (j0 == 0) {
         SLQ_TRY(launch_first_slice(p, batch, s, strideS, (slice0 + 0) % L, cur, st));
       } else {
@@ -300,11 +319,11 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
                oC = take(8 * 8);
   const size_t oXa = take(8 * NN * B), oXb = take(8 * NN * B), oW = take(8 * NN * B), oU = take(8 * NN * B),
                oV = take(8 * NN * B), oVt = take(8 * NN * B);
-  const size_t oD = take(8 * N * B), oID = take(8 * N * B), oT = take(8 * (N + 16) * 16 * B);
+  const size_t oD = take(8 * N * B), oID = take(8 * N * B), oT = take(8 * (N + 32) * 32 * B);
   const size_t oPerm = take(4 * N * B), oPiv = take(4 * N * B), oNref = take(4 * B), oSt = take(4 * B);
   const size_t oSw = take((size_t)p.L * N * B), oDv = take(8 * B), oDv2 = take(8 * B), oIv = take(8 * B);
   const size_t oX = take(8 * N * SWEEP_KD * B), oY = take(8 * N * SWEEP_KD * B), oA = take(8 * SWEEP_KD * B);
-  const size_t oFo = take(8 * 64 * B), oFn = take(8 * 64 * B), oSg = take(B);
+  const size_t oFo = take(8 * 64 * B), oFn = take(8 * 64 * B), oSg = take(B), oKw = take(8 * 8 * 64);
   p.bytes = off;
   void* base = nullptr;
   if (hipMalloc(&base, off) != hipSuccess) {
@@ -341,7 +360,10 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   p.F_old = (double*)(c + oFo);
   p.F_new = (double*)(c + oFn);
   p.sgn_work = (int8_t*)(c + oSg);
+  p.kron_w = (double*)(c + oKw);
+  p.kron_P = kron_line_size(model->lx, model->ly);
   int rc = launch_kinetic(p, 0);
+  if (rc == SLQ_OK) rc = launch_kron_windows(p, 0);
   if (rc == SLQ_OK) rc = launch_narrow(p.E, p.E32, NN, 0);
   if (rc == SLQ_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(SLQ_ERR_DEVICE, "kinetic build failed");
   if (rc != SLQ_OK) {

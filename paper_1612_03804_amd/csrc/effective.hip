@@ -50,6 +50,8 @@ EffDev eff_dev_view(const Plan& p, const Eff& e) {
   d.col_off = e.d_col_off;
   d.shell_off = e.d_shell_off;
   d.shell_dxy = e.d_shell_dxy;
+  d.n_pairs = e.n_pairs;
+  d.pairs = e.d_pairs;
   return d;
 }
 
@@ -99,11 +101,120 @@ __global__ __launch_bounds__(256) void k_eff_sweep(EffDev d, int8_t* s_all, int 
   }
 }
 
+// The same moves with the field, the couplings and the flattened partner
+// list in LDS.  Four lanes share a site, each summing every fourth partner;
+// a quad reduction joins them and the first lane draws and flips.
+constexpr int EFF_THREADS = 512;
+
+__device__ __forceinline__ int wrap2(int v, int n) {  // v in [-2n, 3n)
+  if (v < 0) v += n;
+  if (v < 0) v += n;
+  if (v >= n) v -= n;
+  if (v >= n) v -= n;
+  return v;
+}
+
+__global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t* s_all, int n_moves, uint64_t seed,
+                                                                uint64_t step, uint64_t chain0, int64_t* accepts,
+                                                                double* dS_out) {
+  extern __shared__ double sm[];
+  __shared__ double redd[EFF_THREADS / 64];
+  __shared__ long long redi[EFF_THREADS / 64];
+  __shared__ double one_body;
+  const int np = d.n_pairs, N = d.N, L = d.L, lx = d.lx, ly = d.ly;
+  double* lam = sm;                            // [np]
+  int32_t* pr = (int32_t*)(lam + np);          // [np]
+  int8_t* f = (int8_t*)(pr + np);              // [L][N]
+  const int b = blockIdx.x, tid = threadIdx.x;
+  int8_t* s = s_all + (long)b * L * N;
+  const uint64_t chain = chain0 + b;
+  for (int p = tid; p < np; p += EFF_THREADS) {
+    const int32_t e = d.pairs[p];
+    pr[p] = e;
+    lam[p] = d.theta[1 + (e >> 20)];
+  }
+  if (tid == 0) {
+    double h = 0.0;
+    for (int k = 0; k < d.n_terms; ++k)
+      if (d.terms[2 * k] == 0 && d.terms[2 * k + 1] == 0) h += d.theta[1 + k];
+    one_body = h;
+  }
+  for (long i = tid; i < (long)L * N; i += EFF_THREADS) f[i] = s[i];
+  __syncthreads();
+  const int sub = tid & 3, slot = tid >> 2, nslot = EFF_THREADS / 4;
+  const double h1 = one_body;
+  long long acc = 0;
+  double dsum = 0.0;
+  for (int mv = 0; mv < n_moves; ++mv) {
+    const uint32_t cls = philox_below((uint32_t)d.n_classes, 0, (uint64_t)mv, step, chain, seed, TAG_EFFECTIVE);
+    const int colour = (int)(cls % d.n_colours);
+    const int l = (int)(cls / d.n_colours);  // 0-based slice
+    const int beg = d.col_off[colour], end = d.col_off[colour + 1];
+    for (int t = beg + slot; t < end; t += nslot) {  // the four lanes of a quad share t
+      const int i = d.col_sites[t];
+      const int x = i % lx, y = i / lx;
+      double hs = 0.0;
+      for (int p = sub; p < np; p += 4) {
+        const int32_t e = pr[p];
+        const int xx = wrap2(x + (e & 15) - 4, lx);
+        const int yy = wrap2(y + ((e >> 4) & 15) - 4, ly);
+        int ll = l + ((e >> 8) & 4095) - 2048;
+        if (ll < 0) ll += L;
+        if (ll >= L) ll -= L;
+        hs += lam[p] * (double)f[ll * N + xx + lx * yy];
+      }
+      hs += dpp_move<DPP_QUAD_XOR1>(hs);
+      hs += dpp_move<DPP_QUAD_XOR2>(hs);
+      if (sub == 0) {
+        const int8_t sv = f[l * N + i];
+        const double dS = -2.0 * (double)sv * (h1 + hs);
+        const double u = philox_uniform((uint64_t)(1 + (long)l * N + i), (uint64_t)mv, step, chain, seed,
+                                        TAG_EFFECTIVE);
+        if (u < exp(dS)) {
+          f[l * N + i] = (int8_t)(-sv);
+          ++acc;
+          dsum += dS;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (long i = tid; i < (long)L * N; i += EFF_THREADS) s[i] = f[i];
+  dsum = wave_sum(dsum);
+  const double a2 = wave_sum((double)acc);  // exact: counts stay far below 2^53
+  if ((tid & 63) == 0) {
+    redd[tid >> 6] = dsum;
+    redi[tid >> 6] = (long long)a2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    long long at = 0;
+    double ds = 0.0;
+    for (int w = 0; w < EFF_THREADS / 64; ++w) {
+      at += redi[w];
+      ds += redd[w];
+    }
+    if (accepts) accepts[b] = at;
+    if (dS_out) dS_out[b] = ds;
+  }
+}
+
+static size_t eff_lds_bytes(const Plan& p, const Eff& e) {
+  return (size_t)e.n_pairs * (sizeof(double) + sizeof(int32_t)) + (size_t)p.L * p.n;
+}
+
 int launch_eff_sweep(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, uint64_t seed, uint64_t step,
                      uint64_t chain0, int64_t* accepts, double* dS, hipStream_t st) {
   if (batch <= 0) return SLQ_OK;
   if (e.net_on) return launch_eff_sweep_net(p, e, batch, s, n_moves, seed, step, chain0, accepts, dS, st);
-  k_eff_sweep<<<batch, 256, 0, st>>>(eff_dev_view(p, e), s, n_moves, seed, step, chain0, accepts, dS);
+  const size_t lds = eff_lds_bytes(p, e);
+  if (e.d_pairs && lds <= 150 * 1024 && p.L <= 4094) {
+    allow_max_lds((const void*)k_eff_sweep_lds);
+    k_eff_sweep_lds<<<batch, EFF_THREADS, lds, st>>>(eff_dev_view(p, e), s, n_moves, seed, step, chain0, accepts,
+                                                     dS);
+  } else {
+    k_eff_sweep<<<batch, 256, 0, st>>>(eff_dev_view(p, e), s, n_moves, seed, step, chain0, accepts, dS);
+  }
   SLQ_LAUNCHED();
   return SLQ_OK;
 }
@@ -135,9 +246,85 @@ __global__ __launch_bounds__(256) void k_features(EffDev d, const int8_t* s_all,
   }
 }
 
+// The same features from per-site bit strings of the field along imaginary
+// time: with bit l of B_i set when s_{i,l} = -1,
+//     sum_l s_{i,l} s_{j,l+t} = L - 2 popcount(B_i xor B_j rotated by t),
+// and, the shells being symmetric under delta -> -delta,
+//     F_(r,dl) = sum_{delta in shell r} sum_{i,l} s_{i,l} s_{i+delta, l+dl}   (dl > 0),
+//     F_(r,0)  = 1/2 of the same sum with dl = 0,   F_(0,0) = sum_{i,l} s_{i,l}.
+// Each site keeps B twice over (2L bits) so a rotation is a shifted read.
+constexpr int FEAT_THREADS = 512;
+
+__device__ __forceinline__ uint64_t bits_window(const uint64_t* D, int t, int w) {  // bits t + 64 w ...
+  const int q = (t >> 6) + w, r = t & 63;
+  return r == 0 ? D[q] : (D[q] >> r) | (D[q + 1] << (64 - r));
+}
+
+__global__ __launch_bounds__(FEAT_THREADS) void k_features_bits(EffDev d, const int8_t* s_all, double* F) {
+  extern __shared__ uint64_t bits[];  // [N][W2]
+  __shared__ double part[FEAT_THREADS / 64][MAX_TERMS];
+  const int N = d.N, L = d.L, lx = d.lx, ly = d.ly, K = d.n_terms;
+  const int W = (L + 63) / 64, W2 = (2 * L + 63) / 64 + 1;
+  const uint64_t last = (L % 64) ? ((1ull << (L % 64)) - 1) : ~0ull;
+  const long b = blockIdx.x;
+  const int8_t* s = s_all + b * L * N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < N; i += FEAT_THREADS) {
+    uint64_t* D = bits + (long)i * W2;
+    for (int w = 0; w < W2; ++w) {
+      uint64_t v = 0;
+      for (int t = 0; t < 64; ++t) {
+        const int l = 64 * w + t;
+        if (l < 2 * L && s[(long)(l < L ? l : l - L) * N + i] < 0) v |= 1ull << t;
+      }
+      D[w] = v;
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < K; ++k) {
+    const int r = d.terms[2 * k], dl = d.terms[2 * k + 1];
+    long long acc = 0;
+    for (int i = tid; i < N; i += FEAT_THREADS) {
+      const uint64_t* Di = bits + (long)i * W2;
+      if (r == 0 && dl == 0) {
+        int ones = 0;
+        for (int w = 0; w < W; ++w) ones += __popcll(Di[w] & (w == W - 1 ? last : ~0ull));
+        acc += L - 2 * ones;
+        continue;
+      }
+      const int x = i % lx, y = i / lx;
+      for (int o = d.shell_off[r]; o < d.shell_off[r + 1]; ++o) {
+        int xx = x + d.shell_dxy[2 * o], yy = y + d.shell_dxy[2 * o + 1];
+        xx = ((xx % lx) + lx) % lx;
+        yy = ((yy % ly) + ly) % ly;
+        const uint64_t* Dj = bits + (long)(xx + lx * yy) * W2;
+        int diff = 0;
+        for (int w = 0; w < W; ++w)
+          diff += __popcll((Di[w] ^ bits_window(Dj, dl, w)) & (w == W - 1 ? last : ~0ull));
+        acc += L - 2 * diff;
+      }
+    }
+    const double tot = wave_sum((double)acc);  // exact integers
+    if (lane == 0) part[wave][k] = tot;
+  }
+  __syncthreads();
+  for (int k = tid; k < K; k += FEAT_THREADS) {
+    double t = 0.0;
+    for (int w = 0; w < FEAT_THREADS / 64; ++w) t += part[w][k];
+    const int r = d.terms[2 * k], dl = d.terms[2 * k + 1];
+    F[b * K + k] = (dl == 0 && r != 0) ? 0.5 * t : t;
+  }
+}
+
 int launch_features(Plan& p, const Eff& e, long count, const int8_t* s, double* F, hipStream_t st) {
   if (count <= 0) return SLQ_OK;
-  k_features<<<(unsigned)count, 256, 0, st>>>(eff_dev_view(p, e), s, F);
+  const size_t lds = (size_t)p.n * ((2 * p.L + 63) / 64 + 1) * sizeof(uint64_t);
+  if (lds <= 120 * 1024) {
+    allow_max_lds((const void*)k_features_bits);
+    k_features_bits<<<(unsigned)count, FEAT_THREADS, lds, st>>>(eff_dev_view(p, e), s, F);
+  } else {
+    k_features<<<(unsigned)count, 256, 0, st>>>(eff_dev_view(p, e), s, F);
+  }
   SLQ_LAUNCHED();
   return SLQ_OK;
 }
@@ -361,6 +548,16 @@ int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const 
     maxc = std::max(maxc, (int)sites.size() - off[c]);
   }
   off[nc] = (int32_t)sites.size();
+  std::vector<int32_t> pairs;
+  for (int k = 0; k < n_terms; ++k) {
+    const int r = terms[2 * k], dl = terms[2 * k + 1];
+    if (r == 0 && dl == 0) continue;
+    for (int o = kShellOff[r]; o < kShellOff[r + 1]; ++o)
+      for (int sg = (dl == 0 ? 0 : -1); sg <= (dl == 0 ? 0 : 1); sg += 2) {
+        const int dt = sg * dl;
+        pairs.push_back((kShellDxy[o][0] + 4) | ((kShellDxy[o][1] + 4) << 4) | ((dt + 2048) << 8) | (k << 20));
+      }
+  }
   std::vector<double> theta(1 + n_terms);
   theta[0] = c0;
   for (int k = 0; k < n_terms; ++k) theta[1 + k] = lambda[k];
@@ -380,10 +577,11 @@ int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const 
   e.n_classes = nc * L;
   e.max_class = maxc;
   const size_t b_terms = 8 * n_terms, b_theta = 8 * (1 + n_terms), b_sites = 4 * N, b_off = 4 * (nc + 1),
-               b_shoff = 4 * shoff.size(), b_shd = 4 * shd.size();
+               b_shoff = 4 * shoff.size(), b_shd = 4 * shd.size(), b_pairs = 4 * std::max<size_t>(1, pairs.size());
   const size_t o1 = 0, o2 = o1 + (b_terms + 255) / 256 * 256, o3 = o2 + (b_theta + 255) / 256 * 256,
                o4 = o3 + (b_sites + 255) / 256 * 256, o5 = o4 + (b_off + 255) / 256 * 256,
-               o6 = o5 + (b_shoff + 255) / 256 * 256, total = o6 + (b_shd + 255) / 256 * 256;
+               o6 = o5 + (b_shoff + 255) / 256 * 256, o7 = o6 + (b_shd + 255) / 256 * 256,
+               total = o7 + (b_pairs + 255) / 256 * 256;
   char* base = nullptr;
   if (hipSetDevice(p.device) != hipSuccess || hipMalloc((void**)&base, total) != hipSuccess) {
     delete h;
@@ -395,7 +593,11 @@ int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const 
   e.d_col_off = (int32_t*)(base + o4);
   e.d_shell_off = (int32_t*)(base + o5);
   e.d_shell_dxy = (int32_t*)(base + o6);
-  bool ok = hipMemcpy(e.d_terms, terms, b_terms, hipMemcpyHostToDevice) == hipSuccess &&
+  e.d_pairs = (int32_t*)(base + o7);
+  e.n_pairs = (int)pairs.size();
+  bool ok = (pairs.empty() ||
+             hipMemcpy(e.d_pairs, pairs.data(), 4 * pairs.size(), hipMemcpyHostToDevice) == hipSuccess) &&
+            hipMemcpy(e.d_terms, terms, b_terms, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(e.d_theta, theta.data(), b_theta, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(e.d_col_sites, sites.data(), b_sites, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(e.d_col_off, off.data(), b_off, hipMemcpyHostToDevice) == hipSuccess &&

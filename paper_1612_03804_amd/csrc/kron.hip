@@ -1,0 +1,242 @@
+// Exact slice products that use the structure of the kinetic factor.
+//
+// On the periodic lx x ly lattice K is a Kronecker sum (hopping along x plus
+// hopping along y, "Basics of DQMC"), so with site i = x + lx y
+//     E = exp(-dtau K) = e^{dtau mu} Cx (x) Cy,   (Cx)_{x'x} = Px[(x' - x) mod lx],
+// a product of two circulant matrices, and E^{-1} the same with dtau -> -dtau.
+// E v for a vector v of N = lx ly entries is lx-point circulant products along
+// every x-line followed by ly-point products along every y-line:
+// 2N(lx + ly) flops instead of the 2N^2 of a dense product, the same exact
+// operator (only the rounding order differs).  This is the role the paper's
+// cost count gives to a sparse form of B ("beta N^2" for the whole chain).
+//
+// A workgroup keeps nb vectors (columns, or rows, of one N x N matrix) in LDS
+// and applies a whole block of slices to them, so a block of n_stab slices
+// reads and writes each matrix once from HBM.  Each thread holds one lattice
+// line in registers; the circulant coefficients are wave-uniform (scalar
+// loads from a short window table).
+#include <algorithm>
+
+#include "slq_internal.h"
+
+namespace slq {
+
+struct KronDev {
+  int lx, ly, N, L;
+  const double* in;  // null: the identity
+  long strideIn;
+  double* out;
+  long strideOut;
+  int rows;  // 0: act on the columns of the matrix, 1: on its rows
+  const int8_t* s;
+  long strideS;
+  int slice0, count, step;
+  int scale;  // 0: none, 1: diag(d) before the kinetic factor, 2: after it
+  int lognb;  // vectors per workgroup = 1 << lognb
+  const double* wx;  // coefficient windows, 2P entries each
+  const double* wy;
+  const double* consts;  // [0] exp(-dtau xi), [1] exp(+dtau xi)
+  int inv;               // 1/d instead of d
+};
+
+// Window w of length 2P for a circulant of period n with first column c:
+// C[o][x] = c[(o - x) mod n] = w[x + n - 1 - o] for 0 <= o < n, 0 <= x < P.
+__global__ void k_kron_windows(int lx, int ly, int P, const double* __restrict__ tabs,
+                               const double* __restrict__ consts, double* __restrict__ w) {
+  const int t = threadIdx.x;  // 4 windows x 2P entries
+  if (t >= 8 * P) return;
+  const int which = t / (2 * P), j = t % (2 * P);
+  const bool xdir = (which & 1) == 0, inv = which >= 2;
+  const int n = xdir ? lx : ly;
+  const double* c = tabs + (inv ? lx + ly : 0) + (xdir ? 0 : lx);
+  const double f = xdir ? consts[inv ? 3 : 2] : 1.0;  // e^{+-dtau mu} on the x factor
+  const int d = (((n - 1 - j) % n) + n) % n;
+  w[t] = f * c[d];
+}
+
+// Coefficient windows are read-only for the whole launch: through the constant
+// address space the wave-uniform reads become scalar loads.
+typedef const __attribute__((address_space(4))) double* cdptr;
+
+// One lattice line (n <= P entries, stride `stride` in LDS) times the circulant
+// of window w, in place.  EXACT: n == P, no padding.
+template <int P, bool EXACT>
+__device__ __forceinline__ void line_product(double* __restrict__ S, int base, int stride, int n, cdptr w,
+                                             const double* __restrict__ dl, int dbase, int dstride, int scale) {
+  double r[P];
+#pragma unroll
+  for (int x = 0; x < P; ++x) {
+    double v = 0.0;
+    if (EXACT || x < n) {
+      v = S[base + x * stride];
+      if (scale == 1) v *= dl[dbase + x * dstride];
+    }
+    r[x] = v;
+  }
+#pragma unroll 2
+  for (int o = 0; o < (EXACT ? P : n); ++o) {
+    cdptr wo = w + ((EXACT ? P : n) - 1 - o);
+    double acc = 0.0;
+#pragma unroll
+    for (int x = 0; x < P; ++x) acc = fma(wo[x], r[x], acc);
+    if (scale == 2) acc *= dl[dbase + o * dstride];
+    S[base + o * stride] = acc;
+  }
+}
+
+template <int P, bool EXACT>
+__global__ __launch_bounds__(P >= 48 ? 512 : 1024) void k_kron(KronDev a) {
+  extern __shared__ double S[];  // [N][nb], then d_l [2][N] (alternating slices)
+  const int b = blockIdx.y;
+  const int lg = a.lognb, nb = 1 << lg, N = a.N, lx = a.lx, ly = a.ly;
+  const int v0 = blockIdx.x * nb;
+  const int nv = min(nb, N - v0);
+  const int tid = threadIdx.x, nt = blockDim.x;  // nt is a multiple of 64, nb <= 32
+  const double* __restrict__ in = a.in ? a.in + (long)b * a.strideIn : nullptr;
+  const double dpos = a.consts[a.inv ? 1 : 0], dneg = a.consts[a.inv ? 0 : 1];  // d for s = +1, -1
+  if (!a.rows) {
+    const int c = tid & (nb - 1), j = v0 + c;
+    for (int i = tid >> lg; i < N; i += nt >> lg) {
+      double v = 0.0;
+      if (c < nv) v = in ? in[(long)i * N + j] : (i == j ? 1.0 : 0.0);
+      S[i * nb + c] = v;
+    }
+  } else {
+    for (int c = 0; c < nb; ++c) {
+      const int j = v0 + c;
+      for (int i = tid; i < N; i += nt) {
+        double v = 0.0;
+        if (c < nv) v = in ? in[(long)j * N + i] : (i == j ? 1.0 : 0.0);
+        S[i * nb + c] = v;
+      }
+    }
+  }
+  for (int k = 0; k < a.count; ++k) {
+    int sl = (a.slice0 + k * a.step) % a.L;
+    if (sl < 0) sl += a.L;
+    // a second buffer: threads still in the y-lines of slice k - 1 may read the first
+    double* dl = S + (long)N * nb + (k & 1) * N;
+    if (a.scale) {
+      const int8_t* __restrict__ f = a.s + (long)b * a.strideS + (long)sl * N;
+      for (int i = tid; i < N; i += nt) dl[i] = f[i] > 0 ? dpos : dneg;
+    }
+    __syncthreads();
+    if (tid < ly * nb) {  // x-lines: entries y lx + x, x = 0..lx-1
+      const int y = tid >> lg, c = tid & (nb - 1);
+      line_product<P, EXACT>(S, y * lx * nb + c, nb, lx, (cdptr)a.wx, dl, y * lx, 1, a.scale == 1 ? 1 : 0);
+    }
+    __syncthreads();
+    if (tid < lx * nb) {  // y-lines: entries y lx + x, y = 0..ly-1
+      const int x = tid >> lg, c = tid & (nb - 1);
+      line_product<P, EXACT>(S, x * nb + c, lx * nb, ly, (cdptr)a.wy, dl, x, lx, a.scale == 2 ? 2 : 0);
+    }
+  }
+  __syncthreads();
+  double* out = a.out + (long)b * a.strideOut;
+  if (!a.rows) {
+    const int c = tid & (nb - 1), j = v0 + c;
+    if (c < nv)
+      for (int i = tid >> lg; i < N; i += nt >> lg) out[(long)i * N + j] = S[i * nb + c];
+  } else {
+    for (int c = 0; c < nv; ++c) {
+      const int j = v0 + c;
+      for (int i = tid; i < N; i += nt) out[(long)j * N + i] = S[i * nb + c];
+    }
+  }
+}
+
+static const int kKronSizes[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 64};
+
+int kron_line_size(int lx, int ly) {
+  const int m = std::max(lx, ly);
+  for (int P : kKronSizes)
+    if (P >= m) return P;
+  return 0;
+}
+
+int launch_kron_windows(Plan& p, hipStream_t st) {
+  if (p.kron_P == 0) return SLQ_OK;
+  k_kron_windows<<<1, 8 * p.kron_P, 0, st>>>(p.m.lx, p.m.ly, p.kron_P, p.tabs, p.consts, p.kron_w);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+
+static int kron_max_threads(int P) { return P >= 48 ? 512 : 1024; }
+
+static size_t kron_lds(int N, int nb) { return (size_t)N * (nb + 2) * sizeof(double); }
+
+int kron_default_nb(const Plan& p) {
+  const int m = std::max(p.m.lx, p.m.ly);
+  for (int nb = 32; nb > 1; nb /= 2)
+    if (kron_lds(p.n, nb) <= 80 * 1024 && m * nb <= kron_max_threads(p.kron_P)) return nb;
+  return 1;
+}
+
+template <int P>
+static void launch_p(const KronDev& d, bool exact, dim3 grid, int threads, size_t lds, hipStream_t st) {
+  if (exact) {
+    allow_max_lds((const void*)k_kron<P, true>);
+    k_kron<P, true><<<grid, threads, lds, st>>>(d);
+  } else {
+    allow_max_lds((const void*)k_kron<P, false>);
+    k_kron<P, false><<<grid, threads, lds, st>>>(d);
+  }
+}
+
+int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
+  if (a.batch <= 0 || a.count <= 0) return SLQ_OK;
+  if (p.kron_P == 0) {
+    set_error("structured slice products need lx, ly <= 64");
+    return SLQ_ERR_ARG;
+  }
+  const int nb = a.nb > 0 ? a.nb : (p.kron_nb > 0 ? p.kron_nb : kron_default_nb(p));
+  const int m = std::max(p.m.lx, p.m.ly);
+  const size_t lds = kron_lds(p.n, nb);
+  int lognb = 0;
+  while ((1 << lognb) < nb) ++lognb;
+  if ((1 << lognb) != nb || nb > 32 || m * nb > kron_max_threads(p.kron_P) || lds > 160 * 1024) {
+    set_error("structured slice product: vectors per workgroup must be a power of two <= 32 that fits");
+    return SLQ_ERR_ARG;
+  }
+  KronDev d;
+  d.lx = p.m.lx;
+  d.ly = p.m.ly;
+  d.N = p.n;
+  d.L = p.L;
+  d.in = a.in;
+  d.strideIn = a.strideIn;
+  d.out = a.out;
+  d.strideOut = a.strideOut;
+  d.rows = a.rows;
+  d.s = a.s;
+  d.strideS = (long)p.L * p.n;
+  d.slice0 = a.slice0;
+  d.count = a.count;
+  d.step = a.step;
+  d.scale = a.scale;
+  d.lognb = lognb;
+  const int P = p.kron_P;
+  d.wx = p.kron_w + (a.inv ? 4 * P : 0);
+  d.wy = d.wx + 2 * P;
+  d.consts = p.consts;
+  d.inv = a.inv;
+  const int threads = (m * nb + 63) / 64 * 64;
+  const bool exact = p.m.lx == P && p.m.ly == P;
+  dim3 grid((unsigned)((p.n + nb - 1) / nb), (unsigned)a.batch);
+  switch (P) {
+    case 4: launch_p<4>(d, exact, grid, threads, lds, st); break;
+    case 8: launch_p<8>(d, exact, grid, threads, lds, st); break;
+    case 12: launch_p<12>(d, exact, grid, threads, lds, st); break;
+    case 16: launch_p<16>(d, exact, grid, threads, lds, st); break;
+    case 20: launch_p<20>(d, exact, grid, threads, lds, st); break;
+    case 24: launch_p<24>(d, exact, grid, threads, lds, st); break;
+    case 32: launch_p<32>(d, exact, grid, threads, lds, st); break;
+    case 40: launch_p<40>(d, exact, grid, threads, lds, st); break;
+    case 48: launch_p<48>(d, exact, grid, threads, lds, st); break;
+    default: launch_p<64>(d, exact, grid, threads, lds, st); break;
+  }
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+
+}  // namespace slq

@@ -102,15 +102,7 @@ __global__ __launch_bounds__(FN_THREADS) void k_finish(FinishArgs a) {
           bi = r;
         }
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ov > best || (ov == best && oi < bi)) {
-          best = ov;
-          bi = oi;
-        }
-      }
+      wave_argmax(best, bi);
       if (lane == 0) {
         redv[wave] = best;
         redi[wave] = bi;

@@ -102,15 +102,64 @@ __device__ __forceinline__ uint32_t philox_below(uint32_t n, uint64_t c0, uint64
 enum : uint64_t { TAG_LOCAL = 1, TAG_EFFECTIVE = 2, TAG_CUMULATIVE = 3 };
 
 // ------------------------------------------------------------ reductions ----
+// Whole-wave reductions (every lane active) with DPP lane moves inside rows of
+// 16 lanes (quad permutations, row rotations) and lane reads for the four row
+// results: no LDS round trips.  Every lane returns the same value, combined in
+// a fixed order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+enum : int { DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_ROW_ROR4 = 0x124, DPP_ROW_ROR8 = 0x128 };
 __device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<DPP_QUAD_XOR1>(v);
+  v += dpp_move<DPP_QUAD_XOR2>(v);
+  v += dpp_move<DPP_ROW_ROR4>(v);
+  v += dpp_move<DPP_ROW_ROR8>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_move_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+// Largest v over the wave, ties to the smallest index i (exact: any order of
+// combination gives the same pair).
+__device__ __forceinline__ void argmax_merge(double& v, int& i, double ov, int oi) {
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double& v, int& i) {
+  const double ov = dpp_move<CTRL>(v);
+  const int oi = dpp_move_i32<CTRL>(i);
+  argmax_merge(v, i, ov, oi);
+}
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  argmax_step<DPP_QUAD_XOR1>(v, i);
+  argmax_step<DPP_QUAD_XOR2>(v, i);
+  argmax_step<DPP_ROW_ROR4>(v, i);
+  argmax_step<DPP_ROW_ROR8>(v, i);
+  double bv = read_lane(v, 0);
+  int bi = __builtin_amdgcn_readlane(i, 0);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  for (int r = 16; r < 64; r += 16) argmax_merge(bv, bi, read_lane(v, r), __builtin_amdgcn_readlane(i, r));
+  v = bv;
+  i = bi;
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_move<DPP_QUAD_XOR1>(v));
+  v = fmax(v, dpp_move<DPP_QUAD_XOR2>(v));
+  v = fmax(v, dpp_move<DPP_ROW_ROR4>(v));
+  v = fmax(v, dpp_move<DPP_ROW_ROR8>(v));
+  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
 }
 
 // ------------------------------------------------------------------ plan ----
@@ -130,7 +179,7 @@ struct Plan {
   // per-item N x N buffers
   double *Xa, *Xb, *W, *U, *V, *Vt;
   // per-item vectors
-  double *D, *invD, *Tblk;  // D, 1/D: [N]; compact-WY T blocks: [N/nb+1][nb][nb]
+  double *D, *invD, *Tblk;  // D, 1/D: [N]; compact-WY T blocks: (N + 32) * 32 per field
   int32_t* perm;            // [N]
   int32_t* ipiv;            // [N]
   int32_t* nref;            // [1] reflectors with tau != 0 in the latest QR
@@ -154,6 +203,12 @@ struct Plan {
   void* net_state = nullptr;
   // tile configuration of the FP64 chain GEMM chosen by the autotuner (-1: default)
   int gemm_cfg = -1;
+  // structured (Kronecker) slice products: register line length (0: lattice
+  // too large, dense products), coefficient windows [E x | E y | E^-1 x | E^-1 y]
+  // of 2P entries each, and the vectors per workgroup (0: default)
+  int kron_P = 0;
+  double* kron_w = nullptr;
+  int kron_nb = 0;
   // stabilised partial products kept by local sweeps, allocated on first use
   // for stack_batch fields (see sweep_stacked)
   double* stack = nullptr;
@@ -180,6 +235,10 @@ struct Eff {
   int32_t* d_ncol_sites = nullptr;  // colouring that also separates the network's range
   int32_t* d_ncol_off = nullptr;
   int n_ncolours = 0;
+  // every partner relation of the two-body terms, one entry per (offset, +-dl):
+  // (dx + 4) | (dy + 4) << 4 | (dt + 2048) << 8 | k << 20
+  int n_pairs = 0;
+  int32_t* d_pairs = nullptr;
 };
 
 // Device view of an effective model.
@@ -192,6 +251,8 @@ struct EffDev {
   const int32_t* col_off;    // [n_colours + 1]
   const int32_t* shell_off;  // [7]
   const int32_t* shell_dxy;  // [25][2]
+  int n_pairs;
+  const int32_t* pairs;      // [n_pairs], see Eff
 };
 EffDev eff_dev_view(const Plan& p, const Eff& e);
 
@@ -280,6 +341,25 @@ int launch_gemm_lp(const LpArgs& a, int prec, bool b_is_f64, hipStream_t st);
 int launch_first_slice_f32(Plan& p, int batch, const int8_t* s, long strideS, int slice, float* X, hipStream_t st);
 int launch_widen(const float* a, double* b, long n, hipStream_t st);
 int launch_narrow(const double* a, float* b, long n, hipStream_t st);
+
+// Structured slice products X <- B X for a block of slices (see kron.hip).
+struct KronArgs {
+  const double* in;  // [batch] N x N (stride strideIn); null: start from the identity
+  long strideIn;
+  double* out;       // may equal in
+  long strideOut;
+  int rows;          // 0: the operator acts on the columns, 1: on the rows (X <- X B^T)
+  const int8_t* s;   // fields [batch][L][N]
+  int slice0, count, step;  // slices (slice0 + k step) mod L, k = 0..count-1, first applied first
+  int scale;         // 0: E only, 1: E diag(d_l) (B_l), 2: diag(d_l) E (B_l^T)
+  int inv;           // E^{-1} and 1/d_l instead
+  int nb = 0;        // vectors per workgroup (0: the plan's choice)
+  int batch;
+};
+int kron_line_size(int lx, int ly);
+int kron_default_nb(const Plan& p);
+int launch_kron_windows(Plan& p, hipStream_t st);
+int launch_kron(Plan& p, const KronArgs& a, hipStream_t st);
 
 // Chain helpers
 int launch_first_slice(Plan& p, int batch, const int8_t* s, long strideS, int slice, double* X, hipStream_t st);

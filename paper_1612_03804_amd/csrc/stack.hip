@@ -105,6 +105,21 @@ static int block_product(Plan& p, int batch, const int8_t* s, int first, int cou
   const int N = p.n;
   const long NN = (long)N * N;
   const long strideS = (long)p.L * N;
+  if (p.kron_P > 0) {  // structured products, the whole block in one launch
+    KronArgs k{};
+    k.in = start;
+    k.strideIn = NN;
+    k.out = p.Xa;
+    k.strideOut = NN;
+    k.s = s;
+    k.slice0 = first;
+    k.count = count;
+    k.step = step;
+    k.scale = transposed ? 2 : 1;
+    k.batch = batch;
+    *out = p.Xa;
+    return launch_kron(p, k, st);
+  }
   GemmArgs g{};
   g.M = N;
   g.N = N;
@@ -328,14 +343,36 @@ int sweep_stacked(Plan& p, int batch, int8_t* s, double* G, double* logabs, int8
   w2.strideB = 0;
   w2.C = G;
   w2.inv_scale = 1;
+  KronArgs k1{};  // Xa = E diag(d_l) G, on the columns
+  k1.in = G;
+  k1.strideIn = NN;
+  k1.out = p.Xa;
+  k1.strideOut = NN;
+  k1.s = s;
+  k1.count = 1;
+  k1.step = 1;
+  k1.scale = 1;
+  k1.batch = batch;
+  KronArgs k2 = k1;  // G = Xa diag(1/d_l) E^{-1}: each row r -> E^{-1} diag(1/d_l) r
+  k2.in = p.Xa;
+  k2.out = G;
+  k2.rows = 1;
+  k2.inv = 1;
   for (int k = 0; k < n_sweeps; ++k) {
     if (L > ns) SLQ_TRY(build_left(p, batch, s, status, st));
     for (int l = 1; l <= L; ++l) {
       SLQ_TRY(launch_flip_slice(p, batch, s, G, logabs, sign, l - 1, seed, sweep0 + k, chain0, accepts, st));
-      w1.slice = l - 1;
-      w2.slice = l - 1;
-      SLQ_TRY(launch_gemm(w1, false, false, st));
-      SLQ_TRY(launch_gemm(w2, false, false, st));
+      if (p.kron_P > 0) {
+        k1.slice0 = l - 1;
+        k2.slice0 = l - 1;
+        SLQ_TRY(launch_kron(p, k1, st));
+        SLQ_TRY(launch_kron(p, k2, st));
+      } else {
+        w1.slice = l - 1;
+        w2.slice = l - 1;
+        SLQ_TRY(launch_gemm(w1, false, false, st));
+        SLQ_TRY(launch_gemm(w2, false, false, st));
+      }
       if (l % ns == 0) {
         SLQ_TRY(extend_right(p, batch, s, l, status, st));
         SLQ_TRY(fresh_green(p, batch, l, status, st));

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libslq.so")
 
 SLQ_OK, SLQ_ERR_ARG, SLQ_ERR_DEVICE, SLQ_ERR_WORKSPACE, SLQ_ERR_NUMERIC = 0, -1, -2, -3, -4
 SLQ_ST_BAD_SPIN, SLQ_ST_NONFINITE, SLQ_ST_SINGULAR = 1, 2, 4
-SLQ_PREC_FP64, SLQ_PREC_FP32, SLQ_PREC_BF16 = 0, 1, 2
+SLQ_PREC_FP64, SLQ_PREC_FP32, SLQ_PREC_BF16, SLQ_PREC_FP64_DENSE = 0, 1, 2, 3
 
 # every exported symbol of include/slq.h
 EXPORTS = (
