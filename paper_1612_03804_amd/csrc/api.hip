@@ -324,6 +324,7 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   const size_t oSw = take((size_t)p.L * N * B), oDv = take(8 * B), oDv2 = take(8 * B), oIv = take(8 * B);
   const size_t oX = take(8 * N * SWEEP_KD * B), oY = take(8 * N * SWEEP_KD * B), oA = take(8 * SWEEP_KD * B);
   const size_t oFo = take(8 * 64 * B), oFn = take(8 * 64 * B), oSg = take(B), oKw = take(8 * 8 * 64);
+  const size_t oQw = take(N > 64 ? 8 * (size_t)qr_workspace_per_field((int)N) * B : 8);
   p.bytes = off;
   void* base = nullptr;
   if (hipMalloc(&base, off) != hipSuccess) {
@@ -361,6 +362,7 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   p.F_new = (double*)(c + oFn);
   p.sgn_work = (int8_t*)(c + oSg);
   p.kron_w = (double*)(c + oKw);
+  p.qrws = (double*)(c + oQw);
   p.kron_P = kron_line_size(model->lx, model->ly);
   int rc = launch_kinetic(p, 0);
   if (rc == SLQ_OK) rc = launch_kron_windows(p, 0);

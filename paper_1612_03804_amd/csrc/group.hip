@@ -33,7 +33,7 @@ struct Group {
   std::vector<slq_model> models;
   std::vector<int64_t> s_off, g_off;
   std::vector<SubPlan> subs;
-  std::vector<int> tuned_n, tuned_cfg;
+  std::vector<int> tuned_n, tuned_kind, tuned_cfg;  // kind 0: chain GEMM tile, 1: structured vectors/workgroup
   std::vector<double> tuned_tflops;
   void* dmem = nullptr;
   hipStream_t gs = nullptr;
@@ -77,12 +77,65 @@ static bool same_model(const slq_model& a, const slq_model& b) {
          a.mu == b.mu && a.dtau == b.dtau && a.xi == b.xi && a.chain_prec == b.chain_prec;
 }
 
+// Structured chain products: time every admissible number of vectors per
+// workgroup for one n_stab block on the sub-plan's buffers and batch size.
+static int autotune_kron(Group& g, SubPlan& sp) {
+  Plan& p = sp.plan->p;
+  const int N = p.n;
+  int rc = fill_i32((int32_t*)p.s_work, (long)sp.nb * p.L * N / 4, 0x01010101, g.gs);
+  if (rc != SLQ_OK) return rc;
+  KronArgs k{};
+  k.in = nullptr;
+  k.out = p.Xa;
+  k.strideOut = (long)N * N;
+  k.s = p.s_work;
+  k.slice0 = 0;
+  k.count = std::min(p.m.n_stab, p.L);
+  k.step = 1;
+  k.scale = 1;
+  k.batch = sp.nb;
+  hipEvent_t e0, e1;
+  SLQ_HIP(hipEventCreate(&e0));
+  SLQ_HIP(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int nb = 2; nb <= 32; nb *= 2) {
+    k.nb = nb;
+    if (launch_kron(p, k, g.gs) != SLQ_OK) continue;  // not admissible for this lattice
+    SLQ_HIP(hipEventRecord(e0, g.gs));
+    for (int r = 0; r < 3 && rc == SLQ_OK; ++r) rc = launch_kron(p, k, g.gs);
+    SLQ_HIP(hipEventRecord(e1, g.gs));
+    SLQ_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    SLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (rc == SLQ_OK && ms < best_ms) {
+      best_ms = ms;
+      best = nb;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != SLQ_OK) return rc;
+  if (best == 0) {
+    set_error("no admissible vector block for the structured chain product");
+    return SLQ_ERR_ARG;
+  }
+  p.kron_nb = best;
+  g.tuned_n.push_back(N);
+  g.tuned_kind.push_back(1);
+  g.tuned_cfg.push_back(best);
+  g.tuned_tflops.push_back(2.0 * (double)N * N * (p.m.lx + p.m.ly) * k.count * sp.nb * 3 / (best_ms * 1e-3) / 1e12);
+  return SLQ_OK;
+}
+
 // Time every candidate tile shape of the FP64 chain GEMM on the sub-plan's
 // own buffers and batch size, and keep the fastest for that sub-plan.
 static int autotune(Group& g, SubPlan& sp) {
   Plan& p = sp.plan->p;
   const int N = p.n;
-  if (p.m.chain_prec != SLQ_PREC_FP64 || p.gemm_cfg >= 0) return SLQ_OK;
+  if (p.m.chain_prec == SLQ_PREC_FP64 && p.kron_P > 0) return p.kron_nb > 0 ? SLQ_OK : autotune_kron(g, sp);
+  if ((p.m.chain_prec != SLQ_PREC_FP64 && p.m.chain_prec != SLQ_PREC_FP64_DENSE) || p.gemm_cfg >= 0)
+    return SLQ_OK;
   std::vector<int> cands;
   if (N <= 32) {
     cands = {GEMM_16, GEMM_32x64, GEMM_64};
@@ -134,6 +187,7 @@ static int autotune(Group& g, SubPlan& sp) {
   if (rc != SLQ_OK) return rc;
   p.gemm_cfg = best;
   g.tuned_n.push_back(N);
+  g.tuned_kind.push_back(0);
   g.tuned_cfg.push_back(best);
   g.tuned_tflops.push_back(2.0 * (double)N * N * N * sp.nb * 3 / (best_ms * 1e-3) / 1e12);
   return SLQ_OK;
@@ -312,12 +366,20 @@ int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out)
     set_error("stream/event creation failed");
     rc = SLQ_ERR_DEVICE;
   }
-  // autotune the chain GEMM once per distinct N, on the largest batch of that N
+  // autotune the chain product once per lattice, on the largest batch of that
+  // lattice, and share the choice with its other sub-plans
+  auto same_lattice = [&](size_t r, size_t q) {
+    const slq_model &a = g.subs[r].plan->p.m, &c = g.subs[q].plan->p.m;
+    return a.lx == c.lx && a.ly == c.ly && a.chain_prec == c.chain_prec;
+  };
   for (size_t q = 0; q < g.subs.size() && rc == SLQ_OK; ++q) {
     size_t pick = q;
     for (size_t r = 0; r < g.subs.size(); ++r)
-      if (g.subs[r].plan->p.n == g.subs[q].plan->p.n && g.subs[r].nb > g.subs[pick].nb) pick = r;
+      if (same_lattice(r, q) && g.subs[r].nb > g.subs[pick].nb) pick = r;
     rc = autotune(g, g.subs[pick]);
+    Plan& tp = g.subs[pick].plan->p;
+    g.subs[q].plan->p.kron_nb = tp.kron_nb;
+    g.subs[q].plan->p.gemm_cfg = tp.gemm_cfg;
   }
   if (rc == SLQ_OK && hipStreamSynchronize(g.gs) != hipSuccess) {
     set_error("autotuning failed");
@@ -367,8 +429,8 @@ int slq_group_describe(const slq_group* grp, char* buf, size_t len) {
   s += "], \"tuned\": [";
   for (size_t q = 0; q < g.tuned_n.size(); ++q) {
     char tmp[128];
-    snprintf(tmp, sizeof(tmp), "%s{\"N\": %d, \"cfg\": %d, \"tflops\": %.3f}", q ? ", " : "", g.tuned_n[q],
-             g.tuned_cfg[q], g.tuned_tflops[q]);
+    snprintf(tmp, sizeof(tmp), "%s{\"N\": %d, \"kind\": \"%s\", \"cfg\": %d, \"tflops\": %.3f}", q ? ", " : "",
+             g.tuned_n[q], g.tuned_kind[q] ? "kron_nb" : "gemm_cfg", g.tuned_cfg[q], g.tuned_tflops[q]);
     s += tmp;
   }
   s += "]}";

@@ -59,13 +59,14 @@ __global__ __launch_bounds__(PQ_THREADS) void k_prepivot(int N, const double* __
   double* W = Wall + b * NN;
   const double* D = Dall + (long)b * N;
   int32_t* perm = permall + (long)b * N;
-  double* nrm = lds;
-  int* rp = (int*)(lds + N);
+  double* nrm = lds;           // [N] scaled column norms, then the scale of the c-th pivoted column
+  int* rp = (int*)(lds + N);   // [N]
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   for (int j = threadIdx.x; j < N; j += PQ_THREADS) {
     double ss = 0.0, mx = 0.0;
+#pragma unroll 8
     for (int i = 0; i < N; ++i) {
       const double v = X[(long)i * N + j];
       ss += v * v;
@@ -75,6 +76,7 @@ __global__ __launch_bounds__(PQ_THREADS) void k_prepivot(int N, const double* __
     if (!(nv < INFINITY) || (nv < 1e-150 && mx > 0.0)) {  // rescale when the plain sum over/underflows
       ss = 0.0;
       const double inv = 1.0 / mx;
+#pragma unroll 8
       for (int i = 0; i < N; ++i) {
         const double v = X[(long)i * N + j] * inv;
         ss += v * v;
@@ -92,6 +94,7 @@ __global__ __launch_bounds__(PQ_THREADS) void k_prepivot(int N, const double* __
   for (int j = threadIdx.x; j < N; j += PQ_THREADS) {
     const double nj = nrm[j];
     int r = 0;
+#pragma unroll 8
     for (int i = 0; i < N; ++i) {
       const double ni = nrm[i];
       r += (ni > nj) || (ni == nj && i < j);
@@ -99,11 +102,17 @@ __global__ __launch_bounds__(PQ_THREADS) void k_prepivot(int N, const double* __
     rp[r] = j;
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < N; c += PQ_THREADS) perm[c] = rp[c];
-  for (long idx = threadIdx.x; idx < NN; idx += PQ_THREADS) {
-    const int i = (int)(idx / N), c = (int)(idx % N);
-    const int pc = rp[c];
-    W[idx] = X[(long)i * N + pc] * D[pc];
+  for (int c = threadIdx.x; c < N; c += PQ_THREADS) {
+    perm[c] = rp[c];
+    nrm[c] = D[rp[c]];
+  }
+  __syncthreads();
+  // W[:, c] = X[:, perm[c]] D[perm[c]]: one wave per row, lanes along the row
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < N; i += PQ_WAVES) {
+    const double* xr = X + (long)i * N;
+    double* wr = W + (long)i * N;
+    for (int c = lane; c < N; c += 64) wr[c] = xr[rp[c]] * nrm[c];
   }
   if (threadIdx.x == 0 && bad && status) atomicOr(&status[b], SLQ_ST_NONFINITE);
 }
@@ -112,9 +121,11 @@ __global__ __launch_bounds__(PQ_THREADS) void k_prepivot(int N, const double* __
 struct PanelArgs {
   int N, j0, nbw;
   double* W;       // [b][N][N]: panel columns j0..j0+nbw, rows j0..N-1 (in: A, out: R above / V below)
-  double* Vbuf;    // [b][N][N]: explicit V of the panel at rows j0.., columns j0..j0+NB
-  double* T;       // [b] + strideT: compact-WY factor of this panel, [NB][NB] row-major
+  double* Vbuf;    // [b][N][N]: explicit V of the panel at rows zrow0.., columns j0..j0+nbw
+  int zrow0;       // rows zrow0..j0-1 of V are written as zeros
+  double* T;       // [b] + strideT: compact-WY factor of this panel, row stride ldt
   long strideT;
+  int ldt, tzero;  // rows nbw..tzero-1 of the panel's T columns are written as zeros
   double* D;       // [b][N] out: |R_jj|
   double* invD;    // [b][N] out: 1/|R_jj|
   int32_t* nref;   // [b] in/out: reflectors with tau != 0
@@ -306,8 +317,15 @@ __global__ __launch_bounds__(PQ_THREADS) void k_panel(PanelArgs a) {
       Vb[(long)(j0 + r) * N + j0 + c] = (r == c) ? 1.0 : (r > c ? pv : 0.0);
     }
   }
+  for (int r = a.zrow0 + tid / NB; r < j0; r += PQ_THREADS / NB) {
+    const int c = tid % NB;
+    if (c < nbw) Vb[(long)r * N + j0 + c] = 0.0;
+  }
   double* Tg = a.T + b * a.strideT;
-  for (int idx = tid; idx < NB * NB; idx += PQ_THREADS) Tg[idx] = T[(idx / NB) * LT + idx % NB];
+  for (int idx = tid; idx < a.tzero * NB; idx += PQ_THREADS) {
+    const int i = idx / NB, j = idx % NB;
+    if (j < nbw) Tg[(long)i * a.ldt + j] = i < nbw ? T[i * LT + j] : 0.0;
+  }
 }
 
 // panel width and register rows per lane by matrix size
@@ -333,101 +351,99 @@ __global__ void k_zero_i32(int32_t* x, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = 0;
 }
 
+// Two levels: panels of NB columns inside outer blocks of QR_NBO columns.  A
+// panel's reflectors update the rest of its outer block at once; the
+// trailing columns beyond the block, and later Q, are updated once per outer
+// block with its combined compact-WY factor
+//     T_O = [[T_A, -T_A (V_A^T V_B) T_B], [0, T_B]]
+// built panel by panel, so the large blocks are read and written a quarter
+// as often as with one level.
 template <int NB>
 static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st) {
   const int N = p.n;
   const long NN = (long)N * N;
-  const int npanel = (N + NB - 1) / NB;
-  // scratch: Vbuf = Xb-or-Xa not holding X (both are free once W is written),
-  // T per panel, Wt = V^T A and Wt2 = T^T Wt (or T Wt)
-  double* Vbuf = (X == p.Xa) ? p.Xb : p.Xa;
-  double* Tb = p.Tblk;  // [b][npanel][NB][NB]
-  const long strideT = (long)npanel * NB * NB;
-  double* Wt = p.dY;    // [b][NB][N]
-  double* Wt2 = p.dX;   // [b][NB][N]
+  constexpr int NBO = QR_NBO;
+  const int nout = (N + NBO - 1) / NBO;
+  double* Vbuf = (X == p.Xa) ? p.Xb : p.Xa;  // free once W holds the pivoted copy of X
+  const long sW = qr_workspace_per_field(N);
+  const long sT = (long)NBO * NBO;
+  double* TO = p.qrws;               // [b]: [nout][NBO][NBO] outer factors
+  double* Gb = TO + nout * sT;       // [NBO][NBO] Gram blocks
+  double* Wt = Gb + sT;              // [NBO][N]
+  double* Wt2 = Wt + (long)NBO * N;  // [NBO][N]
   const size_t lpp = sizeof(double) * N + sizeof(int) * N;
   allow_max_lds((const void*)k_prepivot);
   k_prepivot<<<batch, PQ_THREADS, lpp, st>>>(N, X, p.W, o.D, p.perm, status);
   SLQ_LAUNCHED();
   k_zero_i32<<<(batch + 255) / 256, 256, 0, st>>>(o.nref, batch);
   SLQ_LAUNCHED();
-  // Wt = V^T B;  Wt2 = op(T) Wt;  B -= V Wt2   (B: m x n block at row/col j0, col jc)
-  auto apply = [&](int j0, int nbw, int m, double* Bblk, int n, bool transT, double* Tp) -> int {
-    GemmArgs g1{};
-    g1.M = nbw;
-    g1.N = n;
-    g1.K = m;
-    g1.A = Vbuf + (long)j0 * N + j0;
-    g1.lda = N;
-    g1.strideA = NN;
-    g1.B = Bblk;
-    g1.ldb = N;
-    g1.strideB = NN;
-    g1.C = Wt;
-    g1.ldc = N;
-    g1.strideC = (long)NB * N;
-    g1.alpha = 1.0;
-    g1.batch = batch;
-    int rc = launch_gemm(g1, true, false, st);
-    if (rc != SLQ_OK) return rc;
-    GemmArgs gt{};
-    gt.M = nbw;
-    gt.N = n;
-    gt.K = nbw;
-    gt.A = Tp;
-    gt.lda = NB;
-    gt.strideA = strideT;
-    gt.B = Wt;
-    gt.ldb = N;
-    gt.strideB = (long)NB * N;
-    gt.C = Wt2;
-    gt.ldc = N;
-    gt.strideC = (long)NB * N;
-    gt.alpha = 1.0;
-    gt.batch = batch;
-    rc = launch_gemm(gt, transT, false, st);
-    if (rc != SLQ_OK) return rc;
-    GemmArgs g2{};
-    g2.M = m;
-    g2.N = n;
-    g2.K = nbw;
-    g2.A = Vbuf + (long)j0 * N + j0;
-    g2.lda = N;
-    g2.strideA = NN;
-    g2.B = Wt2;
-    g2.ldb = N;
-    g2.strideB = (long)NB * N;
-    g2.C = Bblk;
-    g2.ldc = N;
-    g2.strideC = NN;
-    g2.alpha = -1.0;
-    g2.beta = 1.0;
-    g2.batch = batch;
-    return launch_gemm(g2, false, false, st);
+  // tiles from a sweep of these shapes on MI355X (N = 400, 256 fields): 64 x 128 for
+  // the products with 128 rows of output, 32 x 64 with K 16 for the rank-k updates
+  auto gemm = [&](int M, int Nc, int K, const double* A, long lda, long sA, bool ta, const double* B, long ldb,
+                  long sB, double* C, long ldc, long sC, double alpha, double beta) -> int {
+    GemmArgs g{};
+    g.cfg = (M >= 64 && M <= 128) ? GEMM_64x128 : GEMM_32x64;
+    g.M = M;
+    g.N = Nc;
+    g.K = K;
+    g.A = A;
+    g.lda = lda;
+    g.strideA = sA;
+    g.B = B;
+    g.ldb = ldb;
+    g.strideB = sB;
+    g.C = C;
+    g.ldc = ldc;
+    g.strideC = sC;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.batch = batch;
+    return launch_gemm(g, ta, false, st);
   };
-  for (int pi = 0; pi < npanel; ++pi) {
-    const int j0 = pi * NB, nbw = std::min(NB, N - j0), m = N - j0, nt = N - j0 - nbw;
-    PanelArgs a{N, j0, nbw, p.W, Vbuf, Tb + (long)pi * NB * NB, strideT, o.D, p.invD, o.nref, status};
-    const size_t lds = sizeof(double) * ((size_t)NB * (m + 1) + 2 * NB * (NB + 1) + NB);
-    constexpr int RPL = PanelShape<NB>::RPL;
-    constexpr bool CACHE = PanelShape<NB>::CACHE;
-    allow_max_lds((const void*)k_panel<NB, RPL, CACHE>);
-    k_panel<NB, RPL, CACHE><<<batch, PQ_THREADS, lds, st>>>(a);
-    SLQ_LAUNCHED();
-    if (nt <= 0) continue;
-    // A_trail <- Q_p^T A_trail = A_trail - V (T^T (V^T A_trail))
-    int rc = apply(j0, nbw, m, p.W + (long)j0 * N + j0 + nbw, nt, true, Tb + (long)pi * NB * NB);
-    if (rc != SLQ_OK) return rc;
+  // B <- B - V op(T) (V^T B): V m x k (ld N), T k x k (ld NBO), B m x n (ld N)
+  auto apply = [&](const double* Vp, const double* Tp, int k, double* Bp, int m, int n, bool transT) -> int {
+    int rc = gemm(k, n, m, Vp, N, NN, true, Bp, N, NN, Wt, N, sW, 1.0, 0.0);
+    if (rc == SLQ_OK) rc = gemm(k, n, k, Tp, NBO, sW, transT, Wt, N, sW, Wt2, N, sW, 1.0, 0.0);
+    if (rc == SLQ_OK) rc = gemm(m, n, k, Vp, N, NN, false, Wt2, N, sW, Bp, N, NN, -1.0, 1.0);
+    return rc;
+  };
+  for (int ob = 0; ob < nout; ++ob) {
+    const int J0 = ob * NBO, wo = std::min(NBO, N - J0);
+    double* Tb = TO + ob * sT;
+    for (int j0 = J0; j0 < J0 + wo; j0 += NB) {
+      const int nbw = std::min(NB, N - j0), m = N - j0, sft = j0 - J0;
+      double* Tp = Tb + (long)sft * NBO + sft;
+      PanelArgs a{N, j0, nbw, p.W, Vbuf, J0, Tp, sW, NBO, wo - sft, o.D, p.invD, o.nref, status};
+      const size_t lds = sizeof(double) * ((size_t)NB * (m + 1) + 2 * NB * (NB + 1) + NB);
+      constexpr int RPL = PanelShape<NB>::RPL;
+      constexpr bool CACHE = PanelShape<NB>::CACHE;
+      allow_max_lds((const void*)k_panel<NB, RPL, CACHE>);
+      k_panel<NB, RPL, CACHE><<<batch, PQ_THREADS, lds, st>>>(a);
+      SLQ_LAUNCHED();
+      const int nin = wo - sft - nbw;  // rest of the outer block
+      if (nin > 0) SLQ_TRY(apply(Vbuf + (long)j0 * N + j0, Tp, nbw, p.W + (long)j0 * N + j0 + nbw, m, nin, true));
+      if (sft > 0) {  // T_O[0:sft, sft:sft+nbw] = -T_O[0:sft, 0:sft] (V_A^T V_B) T_B, rows j0.. only
+        SLQ_TRY(gemm(sft, nbw, m, Vbuf + (long)j0 * N + J0, N, NN, true, Vbuf + (long)j0 * N + j0, N, NN, Gb, NBO,
+                     sW, 1.0, 0.0));
+        SLQ_TRY(gemm(sft, nbw, nbw, Gb, NBO, sW, false, Tp, NBO, sW, Wt2, N, sW, 1.0, 0.0));
+        SLQ_TRY(gemm(sft, nbw, sft, Tb, NBO, sW, false, Wt2, N, sW, Tb + sft, NBO, sW, -1.0, 0.0));
+      }
+    }
+    if (J0 + wo < N)
+      SLQ_TRY(apply(Vbuf + (long)J0 * N + J0, Tb, wo, p.W + (long)J0 * N + J0 + wo, N - J0, N - J0 - wo, true));
   }
-  // explicit Q, backwards: U[j0:, j0:] <- Q_p U[j0:, j0:] = U - V (T (V^T U))
-  int rc = launch_set_identity(p, batch, o.U, st);
-  if (rc != SLQ_OK) return rc;
-  for (int pi = npanel - 1; pi >= 0; --pi) {
-    const int j0 = pi * NB, nbw = std::min(NB, N - j0), m = N - j0;
-    rc = apply(j0, nbw, m, o.U + (long)j0 * N + j0, m, false, Tb + (long)pi * NB * NB);
-    if (rc != SLQ_OK) return rc;
+  // explicit Q, backwards: U[J0:, J0:] <- Q_O U[J0:, J0:] = U - V_O (T_O (V_O^T U))
+  SLQ_TRY(launch_set_identity(p, batch, o.U, st));
+  for (int ob = nout - 1; ob >= 0; --ob) {
+    const int J0 = ob * NBO, wo = std::min(NBO, N - J0);
+    SLQ_TRY(apply(Vbuf + (long)J0 * N + J0, TO + ob * sT, wo, o.U + (long)J0 * N + J0, N - J0, N - J0, false));
   }
   return SLQ_OK;
+}
+
+long qr_workspace_per_field(int N) {
+  const long nout = (N + QR_NBO - 1) / QR_NBO;
+  return (nout + 1) * QR_NBO * QR_NBO + 2L * QR_NBO * N;
 }
 
 int qr_blocked_width(int N) { return N <= 448 ? 32 : (N <= 1152 ? 16 : 8); }

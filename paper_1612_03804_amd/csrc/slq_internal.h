@@ -209,6 +209,8 @@ struct Plan {
   int kron_P = 0;
   double* kron_w = nullptr;
   int kron_nb = 0;
+  // blocked QR workspace: outer compact-WY factors, Gram blocks, V^T A products
+  double* qrws = nullptr;
   // stabilised partial products kept by local sweeps, allocated on first use
   // for stack_batch fields (see sweep_stacked)
   double* stack = nullptr;
@@ -278,6 +280,8 @@ __device__ __forceinline__ int local_field_dev(const EffDev& d, const int8_t* __
 }
 
 constexpr int QR_NB = 16;     // Householder / LU panel width
+constexpr int QR_NBO = 128;   // outer block of the blocked QR
+long qr_workspace_per_field(int N);  // doubles per field of Plan::qrws
 constexpr int SWEEP_KD = 32;  // delayed local updates per flush
 
 // ------------------------------------------------------------- launchers ----
@@ -317,6 +321,7 @@ enum GemmCfg {
   GEMM_160x80,     // 160 x 80, 10 wavefronts, K 8
   GEMM_64,         // 64 x 64, K 8
   GEMM_48,         // 48 x 48, 3 wavefronts, K 8
+  GEMM_64x128,     // 64 x 128, 8 wavefronts, K 8 (long-K products of the blocked QR)
   GEMM_NCFG
 };
 int launch_gemm_cfg(const GemmArgs& a, bool transA, bool transB, int cfg, hipStream_t st);
