@@ -207,6 +207,7 @@ def main():
     seed = 0x5D0C + 2
     dev = torch.device("cuda")
     plan = slq.Plan(model, B)
+    kron_nb = slq.slq_plan_tune(plan, B)
     terms = default_terms(model.n_slices)
 
     # training set and fit (step ii): exact weights of B seeded fields
@@ -260,7 +261,8 @@ def main():
         "data": "synthetic: seeded iid +-1 auxiliary fields, effective model fitted on the GPU",
         "config": {"workload": "dqmc_20x20", "lattice": "20x20", "N": model.n_sites, "L": model.n_slices,
                    "beta": model.beta, "t": model.t, "mu": model.mu, "xi": model.xi, "n_stab": model.n_stab,
-                   "chains": B, "effective_moves_per_step": n_moves, "terms": len(terms)},
+                   "chains": B, "effective_moves_per_step": n_moves, "terms": len(terms),
+                   "chain_block_vectors_per_workgroup": kron_nb},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "kernel": "k_kron: block of 10 slices X <- E diag(d_l) X, E = e^{dtau mu} Cx (x) Cy "

@@ -105,6 +105,15 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out);
 int slq_plan_destroy(slq_plan* plan);
 /* Device bytes held by the plan. */
 int slq_plan_bytes(const slq_plan* plan, size_t* bytes);
+
+/* slq_plan_tune - time the admissible block widths (vectors per workgroup:
+ * 2, 4, ..., 32) of the structured chain product (SLQ_PREC_FP64) on `batch`
+ * fields of the plan's own workspace and keep the fastest for later calls;
+ * *chosen (host, may be NULL) receives it, 0 when the plan uses dense
+ * products.  Synchronous on `stream`; overwrites the plan's scratch; must not
+ * run during stream capture.  Without it the plan uses a width fixed by the
+ * LDS size. */
+int slq_plan_tune(slq_plan* plan, int32_t batch, int32_t* chosen, hipStream_t stream);
 /* Copy E (or E^{-1} when inverse != 0) into caller memory d_out [N][N]. */
 int slq_kinetic(slq_plan* plan, int32_t inverse, double* d_out, hipStream_t stream);
 

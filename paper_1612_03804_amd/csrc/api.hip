@@ -242,7 +242,7 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
       SLQ_TRY(launch_qr(p, batch, cur, status, st));
     }
     SLQ_TRY(launch_permute_rows(p, batch, p.V, p.Vt, st));
-    GemmArgs v{};
+    GemmArgs v{};  // V <- diag(1/D) triu(R) (Pi^T V)
     v.M = N;
     v.N = N;
     v.K = N;
@@ -366,6 +366,7 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   p.kron_P = kron_line_size(model->lx, model->ly);
   int rc = launch_kinetic(p, 0);
   if (rc == SLQ_OK) rc = launch_kron_windows(p, 0);
+
   if (rc == SLQ_OK) rc = launch_narrow(p.E, p.E32, NN, 0);
   if (rc == SLQ_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(SLQ_ERR_DEVICE, "kinetic build failed");
   if (rc != SLQ_OK) {
@@ -424,6 +425,18 @@ int slq_plan_destroy(slq_plan* plan) {
   release_stack(plan->p);
   hipFree(plan->p.base);
   delete plan;
+  return SLQ_OK;
+}
+
+int slq_plan_tune(slq_plan* plan, int32_t batch, int32_t* chosen, hipStream_t stream) {
+  if (!plan) return fail(SLQ_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  SLQ_TRY(check_batch(p, batch));
+  if (chosen) *chosen = 0;
+  if (batch == 0 || p.m.chain_prec != SLQ_PREC_FP64 || p.kron_P == 0) return SLQ_OK;
+  SLQ_HIP(hipSetDevice(p.device));
+  SLQ_TRY(tune_kron(p, batch, stream, nullptr));
+  if (chosen) *chosen = p.kron_nb;
   return SLQ_OK;
 }
 

@@ -760,8 +760,7 @@ int slq_cumulative_step(slq_plan* plan, const slq_eff* eff, int32_t batch, int8_
   if (rc == SLQ_OK) rc = launch_finish(p, batch, nullptr, p.dvec, p.sgn_work, status, stream);
   if (rc != SLQ_OK) return rc;
   return launch_accept(p, e, batch, d_s, p.s_work, d_logabs, d_sign, p.dvec, p.sgn_work, p.F_old, p.F_new, sn_old,
-                       sn_new, seed,
-                       step, chain0, d_accepted, d_logA, stream);
+                       sn_new, seed, step, chain0, d_accepted, d_logA, stream);
 }
 
 int slq_fit_effective(slq_plan* plan, const slq_eff* eff, int64_t n_samples, const int8_t* d_S,

@@ -77,54 +77,18 @@ static bool same_model(const slq_model& a, const slq_model& b) {
          a.mu == b.mu && a.dtau == b.dtau && a.xi == b.xi && a.chain_prec == b.chain_prec;
 }
 
-// Structured chain products: time every admissible number of vectors per
-// workgroup for one n_stab block on the sub-plan's buffers and batch size.
+// Structured chain products: the fastest number of vectors per workgroup on
+// the sub-plan's own buffers and batch size.
 static int autotune_kron(Group& g, SubPlan& sp) {
   Plan& p = sp.plan->p;
-  const int N = p.n;
-  int rc = fill_i32((int32_t*)p.s_work, (long)sp.nb * p.L * N / 4, 0x01010101, g.gs);
+  float ms = 0.f;
+  const int rc = tune_kron(p, sp.nb, g.gs, &ms);
   if (rc != SLQ_OK) return rc;
-  KronArgs k{};
-  k.in = nullptr;
-  k.out = p.Xa;
-  k.strideOut = (long)N * N;
-  k.s = p.s_work;
-  k.slice0 = 0;
-  k.count = std::min(p.m.n_stab, p.L);
-  k.step = 1;
-  k.scale = 1;
-  k.batch = sp.nb;
-  hipEvent_t e0, e1;
-  SLQ_HIP(hipEventCreate(&e0));
-  SLQ_HIP(hipEventCreate(&e1));
-  int best = 0;
-  float best_ms = 1e30f;
-  for (int nb = 2; nb <= 32; nb *= 2) {
-    k.nb = nb;
-    if (launch_kron(p, k, g.gs) != SLQ_OK) continue;  // not admissible for this lattice
-    SLQ_HIP(hipEventRecord(e0, g.gs));
-    for (int r = 0; r < 3 && rc == SLQ_OK; ++r) rc = launch_kron(p, k, g.gs);
-    SLQ_HIP(hipEventRecord(e1, g.gs));
-    SLQ_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    SLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (rc == SLQ_OK && ms < best_ms) {
-      best_ms = ms;
-      best = nb;
-    }
-  }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  if (rc != SLQ_OK) return rc;
-  if (best == 0) {
-    set_error("no admissible vector block for the structured chain product");
-    return SLQ_ERR_ARG;
-  }
-  p.kron_nb = best;
-  g.tuned_n.push_back(N);
+  g.tuned_n.push_back(p.n);
   g.tuned_kind.push_back(1);
-  g.tuned_cfg.push_back(best);
-  g.tuned_tflops.push_back(2.0 * (double)N * N * (p.m.lx + p.m.ly) * k.count * sp.nb * 3 / (best_ms * 1e-3) / 1e12);
+  g.tuned_cfg.push_back(p.kron_nb);
+  const int cnt = std::min(p.m.n_stab, p.L);
+  g.tuned_tflops.push_back(2.0 * (double)p.n * p.n * (p.m.lx + p.m.ly) * cnt * sp.nb / (ms * 1e-3) / 1e12);
   return SLQ_OK;
 }
 

@@ -239,4 +239,56 @@ int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
   return SLQ_OK;
 }
 
+// Time every admissible number of vectors per workgroup for one n_stab block
+// on `batch` fields of the plan's workspace (fields of +1 spins written into
+// s_work) and keep the fastest in the plan.  Synchronous on st.
+int tune_kron(Plan& p, int batch, hipStream_t st, float* best_ms_out) {
+  if (p.kron_P == 0) return SLQ_OK;
+  const int N = p.n;
+  int rc = fill_i32((int32_t*)p.s_work, (long)batch * p.L * N / 4, 0x01010101, st);
+  if (rc != SLQ_OK) return rc;
+  KronArgs k{};
+  k.in = nullptr;
+  k.out = p.Xa;
+  k.strideOut = (long)N * N;
+  k.s = p.s_work;
+  k.slice0 = 0;
+  k.count = std::min(p.m.n_stab, p.L);
+  k.step = 1;
+  k.scale = 1;
+  k.batch = batch;
+  hipEvent_t e0, e1;
+  SLQ_HIP(hipEventCreate(&e0));
+  SLQ_HIP(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int nb = 2; nb <= 32 && rc == SLQ_OK; nb *= 2) {
+    k.nb = nb;
+    if (launch_kron(p, k, st) != SLQ_OK) continue;  // not admissible for this lattice
+    if (hipEventRecord(e0, st) != hipSuccess) rc = SLQ_ERR_DEVICE;
+    for (int r = 0; r < 3 && rc == SLQ_OK; ++r) rc = launch_kron(p, k, st);
+    float ms = 0.f;
+    if (rc == SLQ_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = SLQ_ERR_DEVICE;
+    if (rc == SLQ_OK && ms < best_ms) {
+      best_ms = ms;
+      best = nb;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != SLQ_OK) {
+    set_error("timing of the structured chain product failed");
+    return rc;
+  }
+  if (best == 0) {
+    set_error("no admissible vector block for the structured chain product");
+    return SLQ_ERR_ARG;
+  }
+  p.kron_nb = best;
+  if (best_ms_out) *best_ms_out = best_ms / 3;
+  return SLQ_OK;
+}
+
 }  // namespace slq

@@ -211,6 +211,7 @@ struct Plan {
   int kron_nb = 0;
   // blocked QR workspace: outer compact-WY factors, Gram blocks, V^T A products
   double* qrws = nullptr;
+
   // stabilised partial products kept by local sweeps, allocated on first use
   // for stack_batch fields (see sweep_stacked)
   double* stack = nullptr;
@@ -365,6 +366,7 @@ int kron_line_size(int lx, int ly);
 int kron_default_nb(const Plan& p);
 int launch_kron_windows(Plan& p, hipStream_t st);
 int launch_kron(Plan& p, const KronArgs& a, hipStream_t st);
+int tune_kron(Plan& p, int batch, hipStream_t st, float* best_ms);
 
 // Chain helpers
 int launch_first_slice(Plan& p, int batch, const int8_t* s, long strideS, int slice, double* X, hipStream_t st);

@@ -164,3 +164,43 @@ def test_batch_over_capacity_is_rejected(slq):
     with pytest.raises(slq.SlqError):
         slq.slq_weight(plan, s, la, sg)
     plan.close()
+
+
+@pytest.mark.parametrize("model", [
+    Model(9, 10, 24, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=10),   # rectangular lattice: padded lines
+    DQMC_20x20,
+])
+def test_dense_fp64_products_agree(slq, model):
+    """SLQ_PREC_FP64_DENSE (dense E on the matrix cores) against the oracle."""
+    from tests.gpu_util import dev, host
+    fields = [iid_field(model, 5100 + i) for i in range(3)]
+    plan = slq.Plan(model, 3, chain_prec=slq.SLQ_PREC_FP64_DENSE)
+    s = dev(np.stack(fields).astype(np.int8))
+    G = torch.empty((3, plan.n, plan.n), dtype=torch.float64, device="cuda")
+    la = torch.empty(3, dtype=torch.float64, device="cuda")
+    sg = torch.empty(3, dtype=torch.int8, device="cuda")
+    st = torch.empty(3, dtype=torch.int32, device="cuda")
+    slq.slq_green(plan, s, G, la, sg, st)
+    check_parity(model, fields, host(G), host(la), host(sg), host(st))
+    plan.close()
+
+
+def test_tuned_block_width_keeps_parity(slq):
+    """slq_plan_tune picks a power-of-two block width and results stay exact."""
+    from tests.gpu_util import dev, host
+    model = Model(12, 12, 30, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=10)
+    fields = [iid_field(model, 5200 + i) for i in range(6)]
+    plan = slq.Plan(model, 6)
+    nb = slq.slq_plan_tune(plan, 6)
+    assert nb in (2, 4, 8, 16, 32)
+    s = dev(np.stack(fields).astype(np.int8))
+    G = torch.empty((6, plan.n, plan.n), dtype=torch.float64, device="cuda")
+    la = torch.empty(6, dtype=torch.float64, device="cuda")
+    sg = torch.empty(6, dtype=torch.int8, device="cuda")
+    st = torch.empty(6, dtype=torch.int32, device="cuda")
+    slq.slq_green(plan, s, G, la, sg, st)
+    check_parity(model, fields, host(G), host(la), host(sg), host(st))
+    dense = slq.Plan(model, 6, chain_prec=slq.SLQ_PREC_FP64_DENSE)
+    assert slq.slq_plan_tune(dense, 6) == 0
+    dense.close()
+    plan.close()
