@@ -432,11 +432,39 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     if (J0 + wo < N)
       SLQ_TRY(apply(Vbuf + (long)J0 * N + J0, Tb, wo, p.W + (long)J0 * N + J0 + wo, N - J0, N - J0 - wo, true));
   }
-  // explicit Q, backwards: U[J0:, J0:] <- Q_O U[J0:, J0:] = U - V_O (T_O (V_O^T U))
+  // explicit Q, backwards: U[J0:, J0:] <- Q_O U[J0:, J0:] = U - V_O (T_O (V_O^T U)).
+  // Columns J0..J0+wo-1 of U still hold [I; 0] there (later blocks only touch
+  // columns beyond), so for them V_O^T U = V_top^T, the unit lower triangle of
+  // V_O: U[:, block] = [I; 0] - V_O (T_O V_top^T), one small and one rank-wo GEMM.
   SLQ_TRY(launch_set_identity(p, batch, o.U, st));
   for (int ob = nout - 1; ob >= 0; --ob) {
-    const int J0 = ob * NBO, wo = std::min(NBO, N - J0);
-    SLQ_TRY(apply(Vbuf + (long)J0 * N + J0, TO + ob * sT, wo, o.U + (long)J0 * N + J0, N - J0, N - J0, false));
+    const int J0 = ob * NBO, wo = std::min(NBO, N - J0), m = N - J0;
+    const double* Vp = Vbuf + (long)J0 * N + J0;
+    double* Ub = o.U + (long)J0 * N + J0;
+    if (m > wo) {  // columns beyond the block: their rows J0..J0+wo-1 are still zero
+      const int n2 = m - wo;
+      SLQ_TRY(gemm(wo, n2, n2, Vp + (long)wo * N, N, NN, true, Ub + (long)wo * N + wo, N, NN, Wt, N, sW, 1.0, 0.0));
+      SLQ_TRY(gemm(wo, n2, wo, TO + ob * sT, NBO, sW, false, Wt, N, sW, Wt2, N, sW, 1.0, 0.0));
+      SLQ_TRY(gemm(m, n2, wo, Vp, N, NN, false, Wt2, N, sW, Ub + wo, N, NN, -1.0, 1.0));
+    }
+    GemmArgs y{};  // Wt2 = T_O V_top^T
+    y.M = wo;
+    y.N = wo;
+    y.K = wo;
+    y.A = TO + ob * sT;
+    y.lda = NBO;
+    y.strideA = sW;
+    y.B = Vp;
+    y.ldb = N;
+    y.strideB = NN;
+    y.C = Wt2;
+    y.ldc = N;
+    y.strideC = sW;
+    y.alpha = 1.0;
+    y.batch = batch;
+    y.cfg = GEMM_32x64;
+    SLQ_TRY(launch_gemm(y, false, true, st));
+    SLQ_TRY(gemm(m, wo, wo, Vp, N, NN, false, Wt2, N, sW, Ub, N, NN, -1.0, 1.0));
   }
   return SLQ_OK;
 }
