@@ -84,8 +84,44 @@ __device__ __forceinline__ void line_product(double* __restrict__ S, int base, i
   }
 }
 
+// Exact line length P <= 32: both loops unrolled and the circulant read from
+// its P/2 + 1 distinct values (its first column is symmetric, c[d] = c[P - d]),
+// which stay in scalar registers for the whole launch.
+template <int P>
+__device__ __forceinline__ void line_product_sym(double* __restrict__ S, int base, int stride,
+                                                 const double (&c)[P / 2 + 1], const double* __restrict__ dl,
+                                                 int dbase, int dstride, int scale) {
+  double r[P];
+#pragma unroll
+  for (int x = 0; x < P; ++x) {
+    double v = S[base + x * stride];
+    if (scale == 1) v *= dl[dbase + x * dstride];
+    r[x] = v;
+  }
+  constexpr int OB = P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1);  // independent accumulators
+#pragma unroll
+  for (int o0 = 0; o0 < P; o0 += OB) {
+    double acc[OB];
+#pragma unroll
+    for (int q = 0; q < OB; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int x = 0; x < P; ++x)
+#pragma unroll
+      for (int q = 0; q < OB; ++q) {
+        const int d = ((o0 + q - x) % P + P) % P;
+        acc[q] = fma(c[d <= P / 2 ? d : P - d], r[x], acc[q]);
+      }
+#pragma unroll
+    for (int q = 0; q < OB; ++q) {
+      double v = acc[q];
+      if (scale == 2) v *= dl[dbase + (o0 + q) * dstride];
+      S[base + (o0 + q) * stride] = v;
+    }
+  }
+}
+
 template <int P, bool EXACT>
-__global__ __launch_bounds__(P >= 48 ? 512 : 1024) void k_kron(KronDev a) {
+__global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
   extern __shared__ double S[];  // [N][nb], then d_l [2][N] (alternating slices)
   const int b = blockIdx.y;
   const int lg = a.lognb, nb = 1 << lg, N = a.N, lx = a.lx, ly = a.ly;
@@ -94,6 +130,15 @@ __global__ __launch_bounds__(P >= 48 ? 512 : 1024) void k_kron(KronDev a) {
   const int tid = threadIdx.x, nt = blockDim.x;  // nt is a multiple of 64, nb <= 32
   const double* __restrict__ in = a.in ? a.in + (long)b * a.strideIn : nullptr;
   const double dpos = a.consts[a.inv ? 1 : 0], dneg = a.consts[a.inv ? 0 : 1];  // d for s = +1, -1
+  // distinct circulant values c[d] = w[P - 1 - d], d = 0..P/2 (exact lines only)
+  double cx[P / 2 + 1], cy[P / 2 + 1];
+  if constexpr (EXACT && P <= 32) {
+#pragma unroll
+    for (int d = 0; d <= P / 2; ++d) {
+      cx[d] = ((cdptr)a.wx)[P - 1 - d];
+      cy[d] = ((cdptr)a.wy)[P - 1 - d];
+    }
+  }
   if (!a.rows) {
     const int c = tid & (nb - 1), j = v0 + c;
     for (int i = tid >> lg; i < N; i += nt >> lg) {
@@ -121,14 +166,26 @@ __global__ __launch_bounds__(P >= 48 ? 512 : 1024) void k_kron(KronDev a) {
       for (int i = tid; i < N; i += nt) dl[i] = f[i] > 0 ? dpos : dneg;
     }
     __syncthreads();
-    if (tid < ly * nb) {  // x-lines: entries y lx + x, x = 0..lx-1
-      const int y = tid >> lg, c = tid & (nb - 1);
-      line_product<P, EXACT>(S, y * lx * nb + c, nb, lx, (cdptr)a.wx, dl, y * lx, 1, a.scale == 1 ? 1 : 0);
-    }
-    __syncthreads();
-    if (tid < lx * nb) {  // y-lines: entries y lx + x, y = 0..ly-1
-      const int x = tid >> lg, c = tid & (nb - 1);
-      line_product<P, EXACT>(S, x * nb + c, lx * nb, ly, (cdptr)a.wy, dl, x, lx, a.scale == 2 ? 2 : 0);
+    if constexpr (EXACT && P <= 32) {
+      if (tid < ly * nb) {  // x-lines: entries y lx + x, x = 0..lx-1
+        const int y = tid >> lg, c = tid & (nb - 1);
+        line_product_sym<P>(S, y * lx * nb + c, nb, cx, dl, y * lx, 1, a.scale == 1 ? 1 : 0);
+      }
+      __syncthreads();
+      if (tid < lx * nb) {  // y-lines: entries y lx + x, y = 0..ly-1
+        const int x = tid >> lg, c = tid & (nb - 1);
+        line_product_sym<P>(S, x * nb + c, lx * nb, cy, dl, x, lx, a.scale == 2 ? 2 : 0);
+      }
+    } else {
+      if (tid < ly * nb) {  // x-lines: entries y lx + x, x = 0..lx-1
+        const int y = tid >> lg, c = tid & (nb - 1);
+        line_product<P, EXACT>(S, y * lx * nb + c, nb, lx, (cdptr)a.wx, dl, y * lx, 1, a.scale == 1 ? 1 : 0);
+      }
+      __syncthreads();
+      if (tid < lx * nb) {  // y-lines: entries y lx + x, y = 0..ly-1
+        const int x = tid >> lg, c = tid & (nb - 1);
+        line_product<P, EXACT>(S, x * nb + c, lx * nb, ly, (cdptr)a.wy, dl, x, lx, a.scale == 2 ? 2 : 0);
+      }
     }
   }
   __syncthreads();
@@ -161,7 +218,7 @@ int launch_kron_windows(Plan& p, hipStream_t st) {
   return SLQ_OK;
 }
 
-static int kron_max_threads(int P) { return P >= 48 ? 512 : 1024; }
+static int kron_max_threads(int P) { return P >= 32 ? 512 : 1024; }
 
 static size_t kron_lds(int N, int nb) { return (size_t)N * (nb + 2) * sizeof(double); }
 

@@ -377,12 +377,13 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
   SLQ_LAUNCHED();
   k_zero_i32<<<(batch + 255) / 256, 256, 0, st>>>(o.nref, batch);
   SLQ_LAUNCHED();
-  // tiles from a sweep of these shapes on MI355X (N = 400, 256 fields): 64 x 128 for
-  // the products with 128 rows of output, 32 x 64 with K 16 for the rank-k updates
+  // tiles from a sweep of these shapes on MI355X (N = 400, 256 fields): 128 x 64
+  // with 8 wavefronts wherever the output has 64 rows or more, 32 x 64 with K 16
+  // for the thin products of the panels
   auto gemm = [&](int M, int Nc, int K, const double* A, long lda, long sA, bool ta, const double* B, long ldb,
                   long sB, double* C, long ldc, long sC, double alpha, double beta) -> int {
     GemmArgs g{};
-    g.cfg = (M >= 64 && M <= 128) ? GEMM_64x128 : GEMM_32x64;
+    g.cfg = M >= 64 ? GEMM_128x64 : GEMM_32x64;
     g.M = M;
     g.N = Nc;
     g.K = K;

@@ -322,7 +322,8 @@ enum GemmCfg {
   GEMM_160x80,     // 160 x 80, 10 wavefronts, K 8
   GEMM_64,         // 64 x 64, K 8
   GEMM_48,         // 48 x 48, 3 wavefronts, K 8
-  GEMM_64x128,     // 64 x 128, 8 wavefronts, K 8 (long-K products of the blocked QR)
+  GEMM_64x128,     // 64 x 128, 8 wavefronts, K 8
+  GEMM_128x64,     // 128 x 64, 8 wavefronts, K 8 (products of the blocked QR)
   GEMM_NCFG
 };
 int launch_gemm_cfg(const GemmArgs& a, bool transA, bool transB, int cfg, hipStream_t st);
