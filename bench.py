@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--ess", action="store_true", help="also measure effective samples/s of both samplers")
     ap.add_argument("--ess-steps", type=int, default=60)
     ap.add_argument("--ess-sweeps", type=int, default=40)
-    ap.add_argument("--ess-dqmc-chains", type=int, default=64)
+    ap.add_argument("--ess-dqmc-chains", type=int, default=0, help="local-DQMC chains (0: as many as --batch)")
     ap.add_argument("--ess-burn", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -301,7 +301,7 @@ def main():
         details["dqmc_max_drift"] = float(drift.max().item())
         details["group_64_uneven"] = group_rate(slq, dev)
     if args.ess:
-        details["ess"] = ess_rates(slq, plan, model, terms, seed, args.ess_steps, args.ess_dqmc_chains,
+        details["ess"] = ess_rates(slq, plan, model, terms, seed, args.ess_steps, args.ess_dqmc_chains or B,
                                    args.ess_sweeps, args.ess_burn)
     out["details"] = details
     if not args.no_cpu_baseline:

@@ -101,6 +101,15 @@ __device__ __forceinline__ uint32_t philox_below(uint32_t n, uint64_t c0, uint64
 
 enum : uint64_t { TAG_LOCAL = 1, TAG_EFFECTIVE = 2, TAG_CUMULATIVE = 3 };
 
+// Workgroup barrier that orders LDS traffic only: each wave's LDS accesses
+// complete before it, but its global loads stay in flight (a full
+// __syncthreads() also waits for every outstanding global access).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------ reductions ----
 // Whole-wave reductions (every lane active) with DPP lane moves inside rows of
 // 16 lanes (quad permutations, row rotations) and lane reads for the four row

@@ -120,6 +120,204 @@ __global__ __launch_bounds__(FL_THREADS) void k_flip_slice(FlipArgs f) {
   }
 }
 
+// The same sweep for N <= FF_MAXN with the delayed-update factors on chip:
+// thread c owns column c, keeps y_m[c] (m < KD) in registers and writes x_m[c]
+// into an LDS table X[c][m].  For site i every thread forms its entry of the
+// current column and row of G,
+//     G[c][i] = G_0[c][i] - sum_m a_m x_m[c] y_m[i],   G[i][c] = G_0[i][c] - sum_m a_m x_m[i] y_m[c],
+// from G_0 values fetched FF_PD sites ahead, the y_m[i] published by thread i
+// and the x_m[i] read from the table; the rank-KD flush runs on the matrix
+// cores from the same table.  The spins, the uniforms and
+// the two possible deltas of the slice are prepared in LDS first, so the
+// decision of a site reads LDS only.  One barrier per rejected site, two per
+// accepted site; these order LDS traffic only, so the fetches of G_0 stay in
+// flight across them.
+constexpr int FF_MAXN = FL_THREADS, FF_KD = 16, FF_XP = FF_KD + 2, FF_PD = 4;
+
+typedef double fd4_t __attribute__((ext_vector_type(4)));
+
+// G_0 -= X diag(a) Y on the matrix cores: X [N][k] is the LDS table, AY [k][N]
+// holds a_m y_m (written by the column owners), unused slots are zero.  Wave w
+// takes the 16 x 16 tiles w, w + 8, ...; a tile of G_0 is fetched one tile
+// ahead.  Lane l holds rows l/16 + 4q and column l%16 of its tile, the
+// operand and result layout of v_mfma_f64_16x16x4_f64.
+__device__ __forceinline__ void flush_mfma(double* __restrict__ G, int N, const double* __restrict__ Xs,
+                                           const double* __restrict__ AY, int ldy) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nt = (N + 15) / 16, tiles = nt * nt;
+  auto load = [&](int t, fd4_t& v) {
+    const int tr = t / nt, tc = t % nt, col = tc * 16 + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = tr * 16 + (lane >> 4) + 4 * q;
+      v[q] = (t < tiles && row < N && col < N) ? G[(long)row * N + col] : 0.0;
+    }
+  };
+  fd4_t cur, nxt;
+  load(wave, cur);
+  for (int t = wave; t < tiles; t += FL_WAVES) {
+    load(t + FL_WAVES, nxt);
+    const int tr = t / nt, tc = t % nt, col = tc * 16 + (lane & 15), xrow = tr * 16 + (lane & 15);
+#pragma unroll
+    for (int ks = 0; ks < FF_KD; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      const double xa = xrow < N ? -Xs[(long)xrow * FF_XP + kk] : 0.0;
+      const double yb = col < N ? AY[(long)kk * ldy + col] : 0.0;
+      cur = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb, cur, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = tr * 16 + (lane >> 4) + 4 * q;
+      if (row < N && col < N) G[(long)row * N + col] = cur[q];
+    }
+    cur = nxt;
+  }
+}
+
+__global__ __launch_bounds__(FL_THREADS) void k_flip_fast(FlipArgs f) {
+  extern __shared__ double lds[];
+  const int N = f.N;
+  const int b = blockIdx.x;
+  const int c = threadIdx.x;
+  const bool own = c < N;
+  const long NN = (long)N * N;
+  double* G = f.G + b * NN;
+  int8_t* s = f.s + (long)b * f.L * N + (long)f.slice * N;
+  double* Xs = lds;                     // [N][FF_XP] x_m[r] at Xs[r * FF_XP + m]
+  double* diag = Xs + (long)N * FF_XP;  // [N] diagonal of the current G
+  double* U = diag + N;                 // [N] uniform of each site
+  double* A = U + N;                    // [KD] a_m
+  double* yi = A + FF_KD;               // [KD] y_m[i] of the current site
+  double* shared2 = yi + FF_KD;         // [2][2] decision of the site, by parity
+  const int ldy = N + 1;
+  double* AY = shared2 + 4;             // [KD][N + 1] a_m y_m[c] for the flush
+  int* sp = (int*)(AY + (long)FF_KD * ldy);  // [N] spins of the slice
+
+  const uint64_t chain = f.chain0 + b;
+  for (int q = c; q < N * FF_XP; q += FL_THREADS) Xs[q] = 0.0;  // unused slots enter the flush times zero
+  if (own) {
+    diag[c] = G[(long)c * N + c];
+    sp[c] = s[c];
+    U[c] = philox_uniform((uint64_t)c, (uint64_t)f.slice, f.sweep, chain, f.seed, TAG_LOCAL);
+  }
+  const double dplus = exp(2.0 * f.a) - 1.0, dminus = exp(-2.0 * f.a) - 1.0;  // delta for s = +1, -1
+  double y[FF_KD];
+#pragma unroll
+  for (int m = 0; m < FF_KD; ++m) y[m] = 0.0;
+  // G_0[c][i] and G_0[i][c] for the sites of the current and of the next group of FF_PD
+  double pc[FF_PD], pr[FF_PD], nc[FF_PD], nr[FF_PD];
+  auto fetch = [&](double(&col)[FF_PD], double(&row)[FF_PD], int i0) {
+#pragma unroll
+    for (int j = 0; j < FF_PD; ++j) {
+      const int i = i0 + j;
+      col[j] = (own && i < N) ? G[(long)c * N + i] : 0.0;
+      row[j] = (own && i < N) ? G[(long)i * N + c] : 0.0;
+    }
+  };
+  fetch(pc, pr, 0);
+  fetch(nc, nr, FF_PD);
+  lds_barrier();
+
+  double la = 0.0;
+  int neg = 0;
+  int64_t nacc = 0;
+  int k = 0;
+  for (int i0 = 0; i0 < N; i0 += FF_PD) {
+#pragma unroll
+    for (int j = 0; j < FF_PD; ++j) {
+      const int i = i0 + j;
+      if (i >= N) break;  // uniform
+      double* shared = shared2 + 2 * (i & 1);
+      if (c == 0) {
+        const int si = sp[i];
+        const double delta = si > 0 ? dplus : dminus;
+        const double R = 1.0 + delta * (1.0 - diag[i]);
+        const bool acc = U[i] < fabs(R);
+        shared[0] = acc ? 1.0 : 0.0;
+        shared[1] = delta / R;
+        if (acc) {
+          sp[i] = -si;
+          la += log(fabs(R));
+          neg ^= (R < 0.0);
+          ++nacc;
+        }
+      }
+      if (c == i) {
+#pragma unroll
+        for (int m = 0; m < FF_KD; ++m)
+          if (m < k) yi[m] = y[m];
+      }
+      lds_barrier();
+      if (shared[0] == 0.0) continue;  // uniform
+      const double a = shared[1];
+      if (own) {
+        double gc = pc[j], gr = pr[j];
+        const double* xr = Xs + (long)c * FF_XP;
+        const double* xi = Xs + (long)i * FF_XP;
+#pragma unroll
+        for (int m = 0; m < FF_KD; ++m)
+          if (m < k) {
+            gc -= A[m] * xr[m] * yi[m];
+            gr -= A[m] * xi[m] * y[m];
+          }
+        const double x = (c == i ? 1.0 : 0.0) - gc;
+        Xs[(long)c * FF_XP + k] = x;
+#pragma unroll
+        for (int m = 0; m < FF_KD; ++m)
+          if (m == k) y[m] = gr;
+        diag[c] -= a * x * gr;
+      }
+      if (c == 0) A[k] = a;
+      ++k;
+      lds_barrier();
+      if (k == FF_KD) {  // G_0 -= sum_m a_m x_m y_m^T
+        if (own) {
+#pragma unroll
+          for (int m = 0; m < FF_KD; ++m) {
+            AY[(long)m * ldy + c] = A[m] * y[m];
+            y[m] = 0.0;
+          }
+        }
+        lds_barrier();
+        flush_mfma(G, N, Xs, AY, ldy);
+        k = 0;
+        __syncthreads();
+        // the fetched G_0 values predate the flush: fetch the rest of this group and the next again
+#pragma unroll
+        for (int j2 = 0; j2 < FF_PD; ++j2) {
+          const int i2 = i0 + j2;
+          if (j2 > j) {
+            pc[j2] = (own && i2 < N) ? G[(long)c * N + i2] : 0.0;
+            pr[j2] = (own && i2 < N) ? G[(long)i2 * N + c] : 0.0;
+          }
+        }
+        fetch(nc, nr, i0 + FF_PD);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < FF_PD; ++j) {
+      pc[j] = nc[j];
+      pr[j] = nr[j];
+    }
+    fetch(nc, nr, i0 + 2 * FF_PD);
+  }
+  if (k > 0) {
+    if (own) {
+#pragma unroll
+      for (int m = 0; m < FF_KD; ++m) AY[(long)m * ldy + c] = m < k ? A[m] * y[m] : 0.0;
+    }
+    lds_barrier();
+    flush_mfma(G, N, Xs, AY, ldy);
+  }
+  __syncthreads();  // the decisions of every site are in sp
+  if (own) s[c] = (int8_t)sp[c];
+  if (c == 0) {
+    f.logabs[b] += la;
+    if (neg) f.sign[b] = (int8_t)(-f.sign[b]);
+    f.accepts[b] += nacc;
+  }
+}
+
 int launch_flip_slice(Plan& p, int batch, int8_t* s, double* G, double* logabs, int8_t* sign, int slice,
                       uint64_t seed, uint64_t sweep, uint64_t chain0, int64_t* accepts, hipStream_t st) {
   FlipArgs f;
@@ -137,6 +335,14 @@ int launch_flip_slice(Plan& p, int batch, int8_t* s, double* G, double* logabs, 
   f.seed = seed;
   f.sweep = sweep;
   f.chain0 = chain0;
+  if (p.n <= FF_MAXN) {
+    const size_t lds = sizeof(double) * ((size_t)p.n * FF_XP + 2 * p.n + 2 * FF_KD + 4 + (size_t)FF_KD * (p.n + 1)) +
+                       sizeof(int) * p.n;
+    allow_max_lds((const void*)k_flip_fast);
+    k_flip_fast<<<batch, FL_THREADS, lds, st>>>(f);
+    SLQ_LAUNCHED();
+    return SLQ_OK;
+  }
   const size_t lds = sizeof(double) * ((size_t)p.n + SWEEP_KD + 4);
   allow_max_lds((const void*)k_flip_slice);
   k_flip_slice<<<batch, FL_THREADS, lds, st>>>(f);
