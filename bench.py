@@ -150,6 +150,32 @@ def ess_rates(slq, plan, model, terms, seed, steps, n_dq, sweeps, burn):
             "burn_in": burn, "ess_ratio": best["ess_per_s"] / ess_dq}
 
 
+def local_sweep_rate(slq, plan, model, sweeps, seed):
+    """Local DQMC sweeps per second on all chains of the plan (one untimed
+    sweep first, which also allocates the stabilised partial products)."""
+    import torch
+    from slq_inputs import iid_fields
+    dev = torch.device("cuda")
+    B, N = plan.max_batch, model.n_sites
+    s = torch.from_numpy(iid_fields(model, B, 3000)).to(dev)
+    G = torch.empty((B, N, N), dtype=torch.float64, device=dev)
+    la = torch.empty(B, dtype=torch.float64, device=dev)
+    sg = torch.empty(B, dtype=torch.int8, device=dev)
+    st = torch.empty(B, dtype=torch.int32, device=dev)
+    acc = torch.empty(B, dtype=torch.int64, device=dev)
+    drift = torch.empty(B, dtype=torch.float64, device=dev)
+    slq.slq_green(plan, s, G, la, sg, st)
+    slq.slq_sweep_local(plan, s, G, la, sg, 1, seed, 0, 0, acc, drift, st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    slq.slq_sweep_local(plan, s, G, la, sg, sweeps, seed, 1, 0, acc, drift, st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"mode": "local_sweeps", "workload": "dqmc_20x20", "chains": B, "sweeps": sweeps,
+            "sweeps_per_s": B * sweeps / dt, "acceptance": float(acc.sum().item()) / (B * sweeps * N * model.n_slices),
+            "max_drift": float(drift.max().item())}
+
+
 def group_rate(slq, dev, reps: int = 5):
     """Exact weights of 64 chains of uneven size (Lx = Ly in {8..24}, L in
     {40..100}) per second, one graph launch per evaluation."""
@@ -188,6 +214,9 @@ def main():
     ap.add_argument("--ess-sweeps", type=int, default=40)
     ap.add_argument("--ess-dqmc-chains", type=int, default=0, help="local-DQMC chains (0: as many as --batch)")
     ap.add_argument("--ess-burn", type=int, default=5)
+    ap.add_argument("--sweeps-only", type=int, default=0,
+                    help="time this many local DQMC sweeps of --batch chains instead (a profiling aid; "
+                         "prints its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note.",
@@ -207,6 +236,9 @@ def main():
     seed = 0x5D0C + 2
     dev = torch.device("cuda")
     plan = slq.Plan(model, B)
+    if args.sweeps_only:
+        print(json.dumps(local_sweep_rate(slq, plan, model, args.sweeps_only, seed)), flush=True)
+        return
     kron_nb = slq.slq_plan_tune(plan, B)
     terms = default_terms(model.n_slices)
 
