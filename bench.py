@@ -31,6 +31,12 @@ import time
 
 METRIC = "exact fermion-weight evals/sec + effective indep. samples/sec vs FP64 DQMC"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (and matrix) peak
+COPY_CALIBRATION_BYTES = 1 << 30
+# HBM bytes per k_kron launch (batch 512, 8 vectors per workgroup), averaged
+# over the 8 blocks of an evaluation (the first block starts from the identity
+# and reads no X): rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, each scaled by
+# what the same counter reads for the 1 GiB copy of --copy-calibration.
+KRON_TRAFFIC = {"batch": 512, "vectors_per_workgroup": 8, "bytes": None}
 
 
 def cpu_baseline(model, terms, theta, fields, logabs, signs, steps, seed):
@@ -214,6 +220,9 @@ def main():
     ap.add_argument("--ess-sweeps", type=int, default=40)
     ap.add_argument("--ess-dqmc-chains", type=int, default=0, help="local-DQMC chains (0: as many as --batch)")
     ap.add_argument("--ess-burn", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device (a plain copy kernel of known size, against which "
+                         "HBM byte counters collected over this run are scaled)")
     ap.add_argument("--sweeps-only", type=int, default=0,
                     help="time this many local DQMC sweeps of --batch chains instead (a profiling aid; "
                          "prints its own JSON line)")
@@ -230,6 +239,14 @@ def main():
         sys.exit(1)
     from paper_1612_03804_amd import slq
     from slq_inputs import DQMC_20x20, iid_fields, default_terms
+
+    if args.copy_calibration:
+        src = torch.ones(COPY_CALIBRATION_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     model = DQMC_20x20
     B = args.batch
@@ -277,6 +294,8 @@ def main():
     elapsed = t1 - t0
     value = B * args.steps / elapsed
     achieved = flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+    traffic = (KRON_TRAFFIC["bytes"] if (B, kron_nb) == (KRON_TRAFFIC["batch"], KRON_TRAFFIC["vectors_per_workgroup"])
+               else None)
 
     out = {
         "metric": METRIC,
@@ -296,7 +315,7 @@ def main():
                    "chains": B, "effective_moves_per_step": n_moves, "terms": len(terms),
                    "chain_block_vectors_per_workgroup": kron_nb},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "k_kron: block of 10 slices X <- E diag(d_l) X, E = e^{dtau mu} Cx (x) Cy "
                                "(lattice-line circulant products, FP64 FMA); flops = 2 N^2 (lx+ly) per slice "
                                "and field",

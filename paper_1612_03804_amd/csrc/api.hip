@@ -320,7 +320,7 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   const size_t oXa = take(8 * NN * B), oXb = take(8 * NN * B), oW = take(8 * NN * B), oU = take(8 * NN * B),
                oV = take(8 * NN * B), oVt = take(8 * NN * B);
   const size_t oD = take(8 * N * B), oID = take(8 * N * B), oT = take(8 * (N + 32) * 32 * B);
-  const size_t oPerm = take(4 * N * B), oPiv = take(4 * N * B), oNref = take(4 * B), oSt = take(4 * B);
+  const size_t oPerm = take(4 * N * B), oNref = take(4 * B), oSt = take(4 * B);
   const size_t oSw = take((size_t)p.L * N * B), oDv = take(8 * B), oDv2 = take(8 * B), oIv = take(8 * B);
   const size_t oX = take(8 * N * SWEEP_KD * B), oY = take(8 * N * SWEEP_KD * B), oA = take(8 * SWEEP_KD * B);
   const size_t oFo = take(8 * 64 * B), oFn = take(8 * 64 * B), oSg = take(B), oKw = take(8 * 8 * 64);
@@ -348,7 +348,6 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   p.invD = (double*)(c + oID);
   p.Tblk = (double*)(c + oT);
   p.perm = (int32_t*)(c + oPerm);
-  p.ipiv = (int32_t*)(c + oPiv);
   p.nref = (int32_t*)(c + oNref);
   p.status = (int32_t*)(c + oSt);
   p.s_work = (int8_t*)(c + oSw);

@@ -256,6 +256,9 @@ int default_gemm(int M, int N) {
 int launch_gemm(const GemmArgs& a, bool ta, bool tb, hipStream_t st) {
   int cfg = -1;
   if (a.cfg >= 0) cfg = a.cfg;
+  // the triangular product of the stabilisation (400^3, 512 fields: 0.96 ms
+  // on 64 x 128 tiles against 1.01 ms on 80 x 80)
+  if (cfg < 0 && a.a_upper && a.M >= 64) cfg = GEMM_64x128;
   if (cfg < 0) cfg = default_gemm(a.M, a.N);
   return launch_gemm_cfg(a, ta, tb, cfg, st);
 }

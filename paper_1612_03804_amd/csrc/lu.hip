@@ -8,14 +8,19 @@
 // determinant) and G = M^{-1} D_b^{-1} U^T.  M is well conditioned: the large
 // scales sit in D_b^{-1} <= 1 and the small ones in D_s <= 1.  det U = +-1
 // from the number of Householder reflectors; det M from an LU factorisation
-// with partial pivoting (blocked, panel in LDS, right-looking updates with
-// one column per thread).
+// with partial pivoting (blocked: the panel is factored in LDS, its row
+// interchanges are applied to the other columns as one gather, and the
+// trailing update runs over (column, 16-row) work items so that every thread
+// keeps a block of loads in flight).
 #include "slq_internal.h"
 
 namespace slq {
 
 constexpr int FN_THREADS = 512;
 constexpr int FN_WAVES = FN_THREADS / 64;
+constexpr int FN_RB = 8;            // rows per work item of the rank-NB updates
+constexpr int FN_TS = 32;           // transpose tile: FN_TS source columns
+constexpr int FN_TW = 4 * FN_TS;    // ... by FN_TW source rows
 
 struct FinishArgs {
   int N;
@@ -24,43 +29,87 @@ struct FinishArgs {
   const double* V;
   const int32_t* nref;
   double* W;
-  int32_t* ipiv;
   double* G;  // may be null
   double* logabs;
   int8_t* sign;
   int32_t* status;
 };
 
-// out[i][j] = scale_i * src[j][i]  (+ add_i * addm[i][j] when addm != null), tiled through LDS.
+// out[orow[k]][j] = src[j][k] / max(D[k], 1)  (+ min(D[k], 1) addm[k][j] when
+// addm != null; orow null is the identity), through LDS tiles of FN_TS source
+// columns by FN_TW source rows: coalesced on both sides.
 __device__ void transpose_scaled(int N, const double* __restrict__ src, const double* __restrict__ D,
-                                 const double* __restrict__ addm, double* __restrict__ out, double* tile) {
-  constexpr int TS = 32;
-  const int nt = (N + TS - 1) / TS;
-  for (int t = 0; t < nt * nt; ++t) {
-    const int ti = t / nt, tj = t % nt;  // output tile rows i in ti, columns j in tj
-    __syncthreads();
-    for (int e = threadIdx.x; e < TS * TS; e += FN_THREADS) {
-      const int r = e / TS, c = e % TS;  // src row j = tj*TS + r, col i = ti*TS + c
-      const int j = tj * TS + r, i = ti * TS + c;
-      tile[r * (TS + 1) + c] = (j < N && i < N) ? src[(long)j * N + i] : 0.0;
+                                 const double* __restrict__ addm, double* __restrict__ out, double* tile,
+                                 const uint16_t* orow) {
+  constexpr int PER = FN_TS * FN_TW / FN_THREADS;
+  const int nk = (N + FN_TS - 1) / FN_TS, nj = (N + FN_TW - 1) / FN_TW;
+  for (int t = 0; t < nk * nj; ++t) {
+    const int k0 = (t / nj) * FN_TS, jb = (t % nj) * FN_TW;
+    double v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * FN_THREADS;
+      const int j = jb + e / FN_TS, k = k0 + e % FN_TS;  // source row j, column k
+      v[q] = (j < N && k < N) ? src[(long)j * N + k] : 0.0;
+    }
+    __syncthreads();  // the previous tile has been read
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * FN_THREADS;
+      tile[(e / FN_TS) * (FN_TS + 1) + e % FN_TS] = v[q];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < TS * TS; e += FN_THREADS) {
-      const int r = e / TS, c = e % TS;  // out row i = ti*TS + r, col j = tj*TS + c
-      const int i = ti * TS + r, j = tj * TS + c;
-      if (i < N && j < N) {
-        const double d = D[i];
-        double v = tile[c * (TS + 1) + r] / fmax(d, 1.0);
-        if (addm) v += fmin(d, 1.0) * addm[(long)i * N + j];
-        out[(long)i * N + j] = v;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * FN_THREADS;
+      const int kk = e / FN_TW, jj = e % FN_TW;
+      const int k = k0 + kk, j = jb + jj;
+      if (k < N && j < N) {
+        const double d = D[k];
+        double x = tile[jj * (FN_TS + 1) + kk] / fmax(d, 1.0);
+        if (addm) x += fmin(d, 1.0) * addm[(long)k * N + j];
+        out[(long)(orow ? orow[k] : k) * N + j] = x;
       }
     }
   }
   __syncthreads();
 }
 
+// A[rowoff + r][j] -= sum_c P[c][r] A[xrow0 + c][j] for r in [rbeg, rend), j in
+// [jbeg, jend): the rank-nbw update of LU and of the two triangular solves.
+// Work items are (column, FN_RB consecutive rows), columns fastest, so that
+// a thread has FN_RB + NB loads in flight at once and the rows of a wave are
+// coalesced.  The rows xrow0.. are disjoint from the updated ones.
 template <int NB>
-__global__ __launch_bounds__(FN_THREADS) void k_finish(FinishArgs a) {
+__device__ __forceinline__ void rank_update(double* __restrict__ A, int N, const double* P, int ldp, int nbw,
+                                            int xrow0, int rowoff, int rbeg, int rend, int jbeg, int jend) {
+  const int ncol = jend - jbeg;
+  if (ncol <= 0 || rend <= rbeg) return;
+  const int nch = (rend - rbeg + FN_RB - 1) / FN_RB;
+  for (int it = threadIdx.x; it < ncol * nch; it += FN_THREADS) {
+    const int j = jbeg + it % ncol;
+    const int r0 = rbeg + (it / ncol) * FN_RB;
+    double x[NB], w[FN_RB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) x[c] = c < nbw ? A[(long)(xrow0 + c) * N + j] : 0.0;
+#pragma unroll
+    for (int q = 0; q < FN_RB; ++q) w[q] = r0 + q < rend ? A[(long)(rowoff + r0 + q) * N + j] : 0.0;
+#pragma unroll
+    for (int q = 0; q < FN_RB; ++q) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < nbw && r0 + q < rend) s += P[c * ldp + r0 + q] * x[c];
+      w[q] -= s;
+    }
+#pragma unroll
+    for (int q = 0; q < FN_RB; ++q)
+      if (r0 + q < rend) A[(long)(rowoff + r0 + q) * N + j] = w[q];
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(FN_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_finish(FinishArgs a) {
   extern __shared__ double lds[];
   const int N = a.N;
   const int b = blockIdx.x;
@@ -70,20 +119,23 @@ __global__ __launch_bounds__(FN_THREADS) void k_finish(FinishArgs a) {
   const double* V = a.V + b * NN;
   const double* D = a.D + (long)b * N;
   double* W = a.W + b * NN;
-  int32_t* ipiv = a.ipiv + (long)b * N;
 
-  double* P = lds;                    // [NB][N] panel, or the 32 x 33 transpose tile
-  double* redv = P + max(NB * N, 32 * 33);  // [FN_WAVES]
-  int* redi = (int*)(redv + FN_WAVES);  // [FN_WAVES]
-  int* flag = redi + FN_WAVES;          // [2]
+  const int ldp = N;
+  double* P = lds;                                           // [NB][N] panel, or the transpose tile
+  double* redv = P + max(NB * N, FN_TW * (FN_TS + 1));       // [FN_WAVES]
+  int* redi = (int*)(redv + FN_WAVES);                       // [FN_WAVES]
+  int* flag = redi + FN_WAVES;                               // [1] a zero pivot was met
+  int* nsl = flag + 1;                                       // [1] rows touched by a panel's interchanges
+  int* srow = nsl + 1;                                       // [2 NB] those rows, the panel's own first
+  int* ssrc = srow + 2 * NB;                                 // [2 NB] row whose entries each one receives
+  uint16_t* ipiv = (uint16_t*)(ssrc + 2 * NB);               // [N] pivot rows
+  uint16_t* orow = ipiv + N;                                 // [N] row permutation of the solves
   if (tid == 0) flag[0] = 0;
-  __syncthreads();
 
   // ---- M = D_b^{-1} U^T + D_s V
-  transpose_scaled(N, U, D, V, W, P);
+  transpose_scaled(N, U, D, V, W, P, nullptr);
 
-  // ---- LU with partial pivoting, in place
-  const int ldp = N;
+  // ---- LU with partial pivoting, in place, panels of NB columns
   for (int j0 = 0; j0 < N; j0 += NB) {
     const int nbw = min(NB, N - j0);
     const int m = N - j0;
@@ -92,24 +144,26 @@ __global__ __launch_bounds__(FN_THREADS) void k_finish(FinishArgs a) {
       P[c * ldp + r] = W[(long)(j0 + r) * N + j0 + c];
     }
     __syncthreads();
-    for (int c = 0; c < nbw; ++c) {
-      double best = -1.0;
-      int bi = m;
-      for (int r = c + tid; r < m; r += FN_THREADS) {
-        const double v = fabs(P[c * ldp + r]);
-        if (v > best) {
-          best = v;
-          bi = r;
+    {  // largest entry of the panel's first column
+      double cb = -1.0;
+      int ci = m;
+      for (int r = tid; r < m; r += FN_THREADS) {
+        const double v = fabs(P[r]);
+        if (v > cb) {
+          cb = v;
+          ci = r;
         }
       }
-      wave_argmax(best, bi);
+      wave_argmax(cb, ci);
       if (lane == 0) {
-        redv[wave] = best;
-        redi[wave] = bi;
+        redv[wave] = cb;
+        redi[wave] = ci;
       }
-      __syncthreads();
-      best = redv[0];
-      bi = redi[0];
+    }
+    __syncthreads();
+    for (int c = 0; c < nbw; ++c) {
+      double best = redv[0];
+      int bi = redi[0];
       for (int w = 1; w < FN_WAVES; ++w)
         if (redv[w] > best || (redv[w] == best && redi[w] < bi)) {
           best = redv[w];
@@ -126,18 +180,30 @@ __global__ __launch_bounds__(FN_THREADS) void k_finish(FinishArgs a) {
         P[tid * ldp + c] = P[tid * ldp + piv];
         P[tid * ldp + piv] = t;
       }
-      __syncthreads();
-      if (!zero) {
-        const double inv = 1.0 / P[c * ldp + c];
-        for (int r = c + 1 + tid; r < m; r += FN_THREADS) P[c * ldp + r] *= inv;
-        __syncthreads();
-        const int w2 = nbw - c - 1;
-        if (w2 > 0)
-          for (int idx = tid; idx < w2 * (m - c - 1); idx += FN_THREADS) {
-            const int c2 = c + 1 + idx % w2;
-            const int r = c + 1 + idx / w2;
-            P[c2 * ldp + r] -= P[c * ldp + r] * P[c2 * ldp + c];
+      __syncthreads();  // pivot row in place; the wave maxima have been read
+      // multipliers of column c, update of the panel's later columns, and the
+      // largest entry of column c + 1, row by row
+      const double inv = zero ? 0.0 : 1.0 / P[c * ldp + c];
+      double cb = -1.0;
+      int ci = m;
+      for (int r = c + 1 + tid; r < m; r += FN_THREADS) {
+        if (!zero) {
+          const double l = P[c * ldp + r] * inv;
+          P[c * ldp + r] = l;
+          for (int c2 = c + 1; c2 < nbw; ++c2) P[c2 * ldp + r] -= l * P[c2 * ldp + c];
+        }
+        if (c + 1 < nbw) {
+          const double v = fabs(P[(c + 1) * ldp + r]);
+          if (v > cb) {
+            cb = v;
+            ci = r;
           }
+        }
+      }
+      wave_argmax(cb, ci);
+      if (lane == 0) {
+        redv[wave] = cb;
+        redi[wave] = ci;
       }
       __syncthreads();
     }
@@ -145,37 +211,56 @@ __global__ __launch_bounds__(FN_THREADS) void k_finish(FinishArgs a) {
       const int c = idx % nbw, r = idx / nbw;
       W[(long)(j0 + r) * N + j0 + c] = P[c * ldp + r];
     }
-    // columns outside the panel: row swaps, then U12 = L11^{-1} A12 and the
-    // trailing update A22 -= L21 U12 (one column per thread)
-    for (int j = tid; j < N; j += FN_THREADS) {
-      if (j >= j0 && j < j0 + nbw) continue;
+    // the panel's row interchanges as one permutation of the rows they touch
+    if (tid == 0) {
+      int ns = nbw;
+      for (int k = 0; k < nbw; ++k) srow[k] = ssrc[k] = j0 + k;
       for (int c = 0; c < nbw; ++c) {
         const int pr = ipiv[j0 + c];
-        if (pr != j0 + c) {
-          const double t = W[(long)(j0 + c) * N + j];
-          W[(long)(j0 + c) * N + j] = W[(long)pr * N + j];
-          W[(long)pr * N + j] = t;
+        int k2 = -1;
+        if (pr < j0 + nbw) {
+          k2 = pr - j0;
+        } else {
+          for (int k = nbw; k < ns; ++k)
+            if (srow[k] == pr) k2 = k;
+          if (k2 < 0) {
+            k2 = ns++;
+            srow[k2] = ssrc[k2] = pr;
+          }
         }
+        const int t = ssrc[c];
+        ssrc[c] = ssrc[k2];
+        ssrc[k2] = t;
       }
-      if (j < j0 + nbw) continue;
-      double x[NB];
-#pragma unroll
-      for (int c = 0; c < NB; ++c) x[c] = (c < nbw) ? W[(long)(j0 + c) * N + j] : 0.0;
-#pragma unroll
-      for (int c = 1; c < NB; ++c)
-        if (c < nbw)
-          for (int c2 = 0; c2 < c; ++c2) x[c] -= P[c2 * ldp + c] * x[c2];
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-        if (c < nbw) W[(long)(j0 + c) * N + j] = x[c];
-      for (int r = nbw; r < m; ++r) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c < nbw) s += P[c * ldp + r] * x[c];
-        W[(long)(j0 + r) * N + j] -= s;
-      }
+      nsl[0] = ns;
     }
+    __syncthreads();
+    // columns outside the panel: interchanges (all loads before any store),
+    // then U12 = L11^{-1} A12 on the right
+    const int ns = nsl[0];
+    for (int j = tid; j < N; j += FN_THREADS) {
+      if (j >= j0 && j < j0 + nbw) continue;
+      double o[2 * NB];
+#pragma unroll
+      for (int k = 0; k < 2 * NB; ++k) o[k] = k < ns ? W[(long)ssrc[k] * N + j] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 2 * NB; ++k)
+        if (k >= nbw && k < ns) W[(long)srow[k] * N + j] = o[k];
+      if (j >= j0 + nbw) {
+#pragma unroll
+        for (int c = 1; c < NB; ++c)
+          if (c < nbw) {
+#pragma unroll
+            for (int c2 = 0; c2 < c; ++c2) o[c] -= P[c2 * ldp + c] * o[c2];
+          }
+      }
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+        if (k < nbw) W[(long)(j0 + k) * N + j] = o[k];
+    }
+    __syncthreads();
+    // trailing update A22 -= L21 U12
+    rank_update<NB>(W, N, P, ldp, nbw, j0, j0, nbw, m, j0 + nbw, N);
     __syncthreads();
   }
 
@@ -211,20 +296,24 @@ __global__ __launch_bounds__(FN_THREADS) void k_finish(FinishArgs a) {
   }
   if (!a.G) return;
 
-  // ---- G = M^{-1} D_b^{-1} U^T
-  double* G = a.G + b * NN;
-  transpose_scaled(N, U, D, nullptr, G, P);
-  // row swaps (each thread owns whole columns, so no barrier is needed)
-  for (int j = tid; j < N; j += FN_THREADS)
+  // ---- G = M^{-1} D_b^{-1} U^T: the LU's row interchanges, applied in order,
+  // move row k of the right-hand side to row orow[k]
+  if (tid == 0) {
+    for (int k = 0; k < N; ++k) orow[k] = k;  // first: the source row of each position
     for (int k = 0; k < N; ++k) {
       const int pr = ipiv[k];
       if (pr != k) {
-        const double t = G[(long)k * N + j];
-        G[(long)k * N + j] = G[(long)pr * N + j];
-        G[(long)pr * N + j] = t;
+        const uint16_t t = orow[k];
+        orow[k] = orow[pr];
+        orow[pr] = t;
       }
     }
+  }
   __syncthreads();
+  for (int k = tid; k < N; k += FN_THREADS) ipiv[orow[k]] = k;  // inverted, into the free pivot array
+  __syncthreads();
+  double* G = a.G + b * NN;
+  transpose_scaled(N, U, D, nullptr, G, P, ipiv);
   // forward substitution with the unit lower factor
   for (int i0 = 0; i0 < N; i0 += NB) {
     const int nbw = min(NB, N - i0);
@@ -240,19 +329,16 @@ __global__ __launch_bounds__(FN_THREADS) void k_finish(FinishArgs a) {
       for (int c = 0; c < NB; ++c) x[c] = (c < nbw) ? G[(long)(i0 + c) * N + j] : 0.0;
 #pragma unroll
       for (int c = 1; c < NB; ++c)
-        if (c < nbw)
+        if (c < nbw) {
+#pragma unroll
           for (int c2 = 0; c2 < c; ++c2) x[c] -= P[c2 * ldp + c] * x[c2];
+        }
 #pragma unroll
       for (int c = 0; c < NB; ++c)
         if (c < nbw) G[(long)(i0 + c) * N + j] = x[c];
-      for (int r = nbw; r < m; ++r) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c < nbw) s += P[c * ldp + r] * x[c];
-        G[(long)(i0 + r) * N + j] -= s;
-      }
     }
+    __syncthreads();
+    rank_update<NB>(G, N, P, ldp, nbw, i0, i0, nbw, m, 0, N);
     __syncthreads();
   }
   // backward substitution with the upper factor
@@ -274,29 +360,25 @@ __global__ __launch_bounds__(FN_THREADS) void k_finish(FinishArgs a) {
       for (int c = NB - 1; c >= 0; --c)
         if (c < nbw) {
           double s = x[c];
-          for (int c2 = c + 1; c2 < nbw; ++c2) s -= P[c2 * ldp + i0 + c] * x[c2];
+#pragma unroll
+          for (int c2 = c + 1; c2 < NB; ++c2)
+            if (c2 < nbw) s -= P[c2 * ldp + i0 + c] * x[c2];
           x[c] = s / P[c * ldp + i0 + c];
         }
 #pragma unroll
       for (int c = 0; c < NB; ++c)
         if (c < nbw) G[(long)(i0 + c) * N + j] = x[c];
-      for (int r = 0; r < i0; ++r) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c < nbw) s += P[c * ldp + r] * x[c];
-        G[(long)r * N + j] -= s;
-      }
     }
+    __syncthreads();
+    rank_update<NB>(G, N, P, ldp, nbw, i0, 0, 0, i0, 0, N);
     __syncthreads();
   }
 }
 
 static size_t finish_lds(int N, int nb) {
-  size_t panel = sizeof(double) * (size_t)nb * N;
-  const size_t tile = sizeof(double) * 32 * 33;
-  if (panel < tile) panel = tile;
-  return panel + sizeof(double) * FN_WAVES + sizeof(int) * (FN_WAVES + 2);
+  size_t panel = (size_t)nb * N;
+  if (panel < (size_t)FN_TW * (FN_TS + 1)) panel = (size_t)FN_TW * (FN_TS + 1);
+  return sizeof(double) * (panel + FN_WAVES) + sizeof(int) * (FN_WAVES + 2 + 4 * nb) + sizeof(uint16_t) * 2 * N;
 }
 
 int launch_finish(Plan& p, int batch, const UdvRef& f, double* G, double* logabs, int8_t* sign, int32_t* status,
@@ -308,7 +390,6 @@ int launch_finish(Plan& p, int batch, const UdvRef& f, double* G, double* logabs
   a.V = f.V;
   a.nref = f.nref;
   a.W = p.W;
-  a.ipiv = p.ipiv;
   a.G = G;
   a.logabs = logabs;
   a.sign = sign;

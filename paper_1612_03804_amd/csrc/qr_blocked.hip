@@ -3,7 +3,7 @@
 // the factorisation that is computed and why).
 //
 // For each panel of NB columns:
-//   k_panel   one workgroup per field factors the m x NB panel in LDS
+//   k_panel   one workgroup per field factors the m x NB panel in registers
 //             (LAPACK dlarfg convention, H = I - tau v v^T, beta = -sign(alpha)
 //             ||x||), forms the compact-WY factor T (Q_p = I - V T V^T), and
 //             writes V explicitly and T;
@@ -134,44 +134,66 @@ struct PanelArgs {
 
 // One workgroup per field factors the m x nbw panel.  Wave w owns the
 // columns c = w (mod waves) and keeps them in registers, row r = lane + 64 k
-// in slot k (RPL slots cover m).  Step c: the owner of column c has formed
-// reflector c (LAPACK dlarfg: beta = -sign(alpha) ||x||, v = x / (alpha -
-// beta) below the diagonal) and published v_c in LDS; after one barrier every
-// wave applies H_c = I - tau_c v_c v_c^T to its own columns > c (the owner of
-// column c+1 first, and it forms reflector c+1 at once) and adds the Gram
-// entries v_i . v_c of its finished columns i < c.  T (Q_panel = I - V T V^T)
-// follows from the Gram matrix at the end.
+// in slot k (RPL slots cover m); the panel comes in and goes out 64 rows at
+// a time through a small LDS chunk, so that several fields share a CU.  Step
+// c: the owner of column c has formed reflector c (LAPACK dlarfg: beta =
+// -sign(alpha) ||x||, v = x / (alpha - beta) below the diagonal) and
+// published v_c in LDS; after one barrier every wave applies H_c = I - tau_c
+// v_c v_c^T to its own columns > c (the owner of column c+1 first, and it
+// forms and publishes reflector c+1 at once, into the other of two buffers)
+// and adds the Gram entries v_i . v_c of its finished columns i < c.  T
+// (Q_panel = I - V T V^T) follows from the Gram matrix at the end.
 template <int NB, int RPL, bool CACHE_V>
-__global__ __launch_bounds__(PQ_THREADS) void k_panel(PanelArgs a) {
+__global__ __launch_bounds__(PQ_THREADS) __attribute__((amdgpu_waves_per_eu(NB == 32 ? 4 : 1))) void k_panel(PanelArgs a) {
   extern __shared__ double lds[];
   constexpr int CPW = NB >= PQ_WAVES ? NB / PQ_WAVES : 1;  // columns per wave
-  constexpr int LT = NB + 1;        // padded row stride of T and the Gram matrix
+  constexpr int LT = NB + 1;                 // padded row stride of T and the Gram matrix
+  constexpr int LS = 65;                     // padded column stride of the 64-row chunk
+  constexpr int VR = 64 * RPL;               // length of a published reflector
+  constexpr int SPT = 64 * NB / PQ_THREADS;  // chunk entries per thread
+  static_assert(SPT * PQ_THREADS == 64 * NB, "a chunk is 64 rows of NB columns");
   const int N = a.N, j0 = a.j0, nbw = a.nbw, m = N - j0;
   const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long NN = (long)N * N;
+  const int nch = (m + 63) / 64;    // chunks that hold rows (<= RPL)
   double* W = a.W + b * NN;
-  const int ldp = m + 1;            // column stride of the panel in LDS
-  double* P = lds;                  // [NB][ldp]: staging, then the published reflectors
-  double* T = P + (long)NB * ldp;   // [NB][LT]
+  double* S = lds;                  // [NB][LS]: 64 rows of the panel on their way in or out
+  double* Vp = S + NB * LS;         // [2][VR]: the reflectors of two consecutive steps
+  double* T = Vp + 2 * VR;          // [NB][LT]
   double* Gm = T + NB * LT;         // [NB][LT]
   double* tau = Gm + NB * LT;       // [NB]
 
-  for (int r = tid / NB; r < m; r += PQ_THREADS / NB) {
-    const int c = tid % NB;
-    if (c < nbw) P[c * ldp + r] = W[(long)(j0 + r) * N + j0 + c];
-  }
-  __syncthreads();
+  // panel -> registers: row-wise (coalesced) reads, transposed through S;
+  // the next chunk's reads are in flight while a chunk is distributed
   double col[CPW][RPL];
+  double stg[SPT];
+  auto chunk_load = [&](int k) {
 #pragma unroll
-  for (int q = 0; q < CPW; ++q) {
-    const int c = wave + PQ_WAVES * q;
+    for (int t = 0; t < SPT; ++t) {
+      const int e = tid + t * PQ_THREADS;
+      const int i = e / NB, c = e % NB, r = 64 * k + i;
+      stg[t] = (c < nbw && r < m) ? W[(long)(j0 + r) * N + j0 + c] : 0.0;
+    }
+  };
+  chunk_load(0);
 #pragma unroll
-    for (int k = 0; k < RPL; ++k) {
-      const int r = lane + 64 * k;
-      col[q][k] = (c < nbw && r < m) ? P[c * ldp + r] : 0.0;
+  for (int k = 0; k < RPL; ++k) {
+    if (k < nch) {
+      __syncthreads();  // S is free
+#pragma unroll
+      for (int t = 0; t < SPT; ++t) {
+        const int e = tid + t * PQ_THREADS;
+        S[(e % NB) * LS + e / NB] = stg[t];
+      }
+      __syncthreads();
+      if (k + 1 < nch) chunk_load(k + 1);
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) col[q][k] = S[(wave + PQ_WAVES * q) * LS + lane];
+    } else {
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) col[q][k] = 0.0;
     }
   }
-  __syncthreads();  // the staging area is reused for the reflectors
 
   // reflector of the owned column q, global column c (uniform)
   auto reflect = [&](int q, int c) {
@@ -215,11 +237,12 @@ __global__ __launch_bounds__(PQ_THREADS) void k_panel(PanelArgs a) {
         if (r > c && r < m) col[q][k] *= scal;
       }
     }
+    double* vp = Vp + (c & 1) * VR;
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
       const int r = lane + 64 * k;
       if (r == c) col[q][k] = beta;
-      if (r > c && r < m) P[c * ldp + r] = col[q][k];
+      if (r > c && r < m) vp[r] = col[q][k];
     }
     if (lane == 0) tau[c] = tc;
   };
@@ -228,10 +251,11 @@ __global__ __launch_bounds__(PQ_THREADS) void k_panel(PanelArgs a) {
   for (int c = 0; c < nbw; ++c) {
     __syncthreads();  // reflector c is published; step c - 1 is done everywhere
     const double tc = tau[c];
+    const double* vp = Vp + (c & 1) * VR;
     double vr[CACHE_V ? RPL : 1];
     auto vrow = [&](int k) -> double {  // v_c at row lane + 64 k
       const int r = lane + 64 * k;
-      return r < c || r >= m ? 0.0 : (r == c ? 1.0 : P[c * ldp + r]);
+      return r < c || r >= m ? 0.0 : (r == c ? 1.0 : vp[r]);
     };
     if (CACHE_V) {
 #pragma unroll
@@ -257,18 +281,40 @@ __global__ __launch_bounds__(PQ_THREADS) void k_panel(PanelArgs a) {
       }
     }
   }
-  __syncthreads();  // the last reflector has been read everywhere
-  // owned columns back to LDS: R above the diagonal, V below
+  // (the first barrier of the write-back also orders the last step and the
+  // Gram entries before the T build that follows it)
+  // registers -> R (on and above the diagonal) and V (below) in W, explicit V
+  // (unit diagonal, zeros above) in Vbuf, 64 rows at a time through S
+  double* Vb = a.Vbuf + b * NN;
 #pragma unroll
-  for (int q = 0; q < CPW; ++q) {
-    const int c = wave + PQ_WAVES * q;
+  for (int k = 0; k < RPL; ++k) {
+    if (k < nch) {
+      __syncthreads();  // S is free
 #pragma unroll
-    for (int k = 0; k < RPL; ++k) {
-      const int r = lane + 64 * k;
-      if (c < nbw && r < m) P[c * ldp + r] = col[q][k];
+      for (int q = 0; q < CPW; ++q) S[(wave + PQ_WAVES * q) * LS + lane] = col[q][k];
+      __syncthreads();
+      if (k == 0 && wave == 0) {  // |R_jj| of the panel's columns
+        const bool live = lane < nbw;
+        const double d = live ? fabs(S[lane * LS + lane]) : 1.0;
+        const unsigned long long bad = __ballot(live && (!(d > 0.0) || !(d < INFINITY)));
+        if (live) {
+          a.D[(long)b * N + j0 + lane] = d;
+          a.invD[(long)b * N + j0 + lane] = 1.0 / d;
+        }
+        if (lane == 0 && bad && a.status) atomicOr(&a.status[b], SLQ_ST_NONFINITE);
+      }
+#pragma unroll
+      for (int t = 0; t < SPT; ++t) {
+        const int e = tid + t * PQ_THREADS;
+        const int i = e / NB, c = e % NB, r = 64 * k + i;
+        if (c < nbw && r < m) {
+          const double pv = S[c * LS + i];
+          W[(long)(j0 + r) * N + j0 + c] = pv;
+          Vb[(long)(j0 + r) * N + j0 + c] = (r == c) ? 1.0 : (r > c ? pv : 0.0);
+        }
+      }
     }
   }
-  __syncthreads();
   if (wave == 0) {
     // T[0:j, j] = -tau_j T[0:j, 0:j] Gm[0:j, j], T[j][j] = tau_j, in registers:
     // lane i holds row i of T and row i of the Gram matrix; Gm[k][j] reaches
@@ -294,29 +340,10 @@ __global__ __launch_bounds__(PQ_THREADS) void k_panel(PanelArgs a) {
 #pragma unroll
     for (int j = 0; j < NB; ++j)
       if (lane < NB) T[lane * LT + j] = live && j < nbw ? trow[j] : 0.0;
-    const double d = live ? fabs(P[lane * ldp + lane]) : 1.0;
     const unsigned long long refl = __ballot(live && tau[lane] != 0.0);
-    const unsigned long long bad = __ballot(live && (!(d > 0.0) || !(d < INFINITY)));
-    if (live) {
-      a.D[(long)b * N + j0 + lane] = d;
-      a.invD[(long)b * N + j0 + lane] = 1.0 / d;
-    }
-    if (lane == 0) {
-      a.nref[b] += __popcll(refl);
-      if (bad && a.status) atomicOr(&a.status[b], SLQ_ST_NONFINITE);
-    }
+    if (lane == 0) a.nref[b] += __popcll(refl);
   }
-  __syncthreads();
-  // R and V back into W; explicit V (unit diagonal, zeros above); T
-  double* Vb = a.Vbuf + b * NN;
-  for (int r = tid / NB; r < m; r += PQ_THREADS / NB) {
-    const int c = tid % NB;
-    if (c < nbw) {
-      const double pv = P[c * ldp + r];
-      W[(long)(j0 + r) * N + j0 + c] = pv;
-      Vb[(long)(j0 + r) * N + j0 + c] = (r == c) ? 1.0 : (r > c ? pv : 0.0);
-    }
-  }
+  __syncthreads();  // T is in LDS
   for (int r = a.zrow0 + tid / NB; r < j0; r += PQ_THREADS / NB) {
     const int c = tid % NB;
     if (c < nbw) Vb[(long)r * N + j0 + c] = 0.0;
@@ -415,8 +442,8 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
       const int nbw = std::min(NB, N - j0), m = N - j0, sft = j0 - J0;
       double* Tp = Tb + (long)sft * NBO + sft;
       PanelArgs a{N, j0, nbw, p.W, Vbuf, J0, Tp, sW, NBO, wo - sft, o.D, p.invD, o.nref, status};
-      const size_t lds = sizeof(double) * ((size_t)NB * (m + 1) + 2 * NB * (NB + 1) + NB);
       constexpr int RPL = PanelShape<NB>::RPL;
+      const size_t lds = sizeof(double) * ((size_t)NB * 65 + 2 * 64 * RPL + 2 * NB * (NB + 1) + NB);
       constexpr bool CACHE = PanelShape<NB>::CACHE;
       allow_max_lds((const void*)k_panel<NB, RPL, CACHE>);
       k_panel<NB, RPL, CACHE><<<batch, PQ_THREADS, lds, st>>>(a);

@@ -190,7 +190,6 @@ struct Plan {
   // per-item vectors
   double *D, *invD, *Tblk;  // D, 1/D: [N]; compact-WY T blocks: (N + 32) * 32 per field
   int32_t* perm;            // [N]
-  int32_t* ipiv;            // [N]
   int32_t* nref;            // [1] reflectors with tau != 0 in the latest QR
   int32_t* status;          // [max_batch] scratch status when caller passes NULL
   int8_t* s_work;           // [max_batch][L][N] proposal fields
@@ -406,8 +405,8 @@ inline int launch_qr_blocked(Plan& p, int batch, const double* X, int32_t* statu
   return launch_qr_blocked(p, batch, X, plan_udv(p), status, st);
 }
 int launch_permute_rows(Plan& p, int batch, const double* V, double* Vt, hipStream_t st);
-// log|det(1 + U D V)|, its sign and optionally G = (1 + U D V)^{-1}; W and ipiv
-// are scratch.
+// log|det(1 + U D V)|, its sign and optionally G = (1 + U D V)^{-1}; W is
+// scratch.
 int launch_finish(Plan& p, int batch, const UdvRef& f, double* G, double* logabs, int8_t* sign, int32_t* status,
                   hipStream_t st);
 inline int launch_finish(Plan& p, int batch, double* G, double* logabs, int8_t* sign, int32_t* status,
