@@ -197,6 +197,7 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
       k.step = 1;
       k.scale = 1;
       k.batch = batch;
+      k.norm2 = p.xnorm2;
       SLQ_TRY(timed_chain_kron(p, k, st));
     } else if (!lp) {
       if (j0 == 0) {
@@ -237,7 +238,7 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
       SLQ_TRY(launch_widen(c32, cur, NN * batch, st));
     }
     if (N > 64) {
-      SLQ_TRY(launch_qr_blocked(p, batch, cur, status, st));
+      SLQ_TRY(launch_qr_blocked(p, batch, cur, status, st, kron ? p.xnorm2 : nullptr));
     } else {
       SLQ_TRY(launch_qr(p, batch, cur, status, st));
     }
@@ -319,7 +320,8 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
                oC = take(8 * 8);
   const size_t oXa = take(8 * NN * B), oXb = take(8 * NN * B), oW = take(8 * NN * B), oU = take(8 * NN * B),
                oV = take(8 * NN * B), oVt = take(8 * NN * B);
-  const size_t oD = take(8 * N * B), oID = take(8 * N * B), oT = take(8 * (N + 32) * 32 * B);
+  const size_t oD = take(8 * N * B), oID = take(8 * N * B), oT = take(8 * (N + 32) * 32 * B),
+               oXn = take(8 * N * B);
   const size_t oPerm = take(4 * N * B), oNref = take(4 * B), oSt = take(4 * B);
   const size_t oSw = take((size_t)p.L * N * B), oDv = take(8 * B), oDv2 = take(8 * B), oIv = take(8 * B);
   const size_t oX = take(8 * N * SWEEP_KD * B), oY = take(8 * N * SWEEP_KD * B), oA = take(8 * SWEEP_KD * B);
@@ -348,6 +350,7 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   p.invD = (double*)(c + oID);
   p.Tblk = (double*)(c + oT);
   p.perm = (int32_t*)(c + oPerm);
+  p.xnorm2 = (double*)(c + oXn);
   p.nref = (int32_t*)(c + oNref);
   p.status = (int32_t*)(c + oSt);
   p.s_work = (int8_t*)(c + oSw);

@@ -37,6 +37,8 @@ struct KronDev {
   const double* wy;
   const double* consts;  // [0] exp(-dtau xi), [1] exp(+dtau xi)
   int inv;               // 1/d instead of d
+  int nvb, batch;        // vector blocks per field, fields
+  double* norm2;         // columns mode: squared 2-norms of the output columns, or null
 };
 
 // Window w of length 2P for a circulant of period n with first column c:
@@ -123,9 +125,16 @@ __device__ __forceinline__ void line_product_sym(double* __restrict__ S, int bas
 template <int P, bool EXACT>
 __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
   extern __shared__ double S[];  // [N][nb], then d_l [2][N] (alternating slices)
-  const int b = blockIdx.y;
+  // XCD-aware order: the hardware deals workgroups to the 8 XCDs in turn, so
+  // hardware ids g and g + 8 run side by side on one XCD; they take the vector
+  // blocks 2p and 2p + 1, which share every 128-byte line of the field's rows
+  // in that XCD's L2 (each line is then fetched once, not once per half)
+  const int g = (int)blockIdx.x;
+  const int lin = (g & ~15) | ((g & 7) << 1) | ((g >> 3) & 1);
+  if (lin >= a.nvb * a.batch) return;
+  const int b = lin / a.nvb;
   const int lg = a.lognb, nb = 1 << lg, N = a.N, lx = a.lx, ly = a.ly;
-  const int v0 = blockIdx.x * nb;
+  const int v0 = (lin % a.nvb) * nb;
   const int nv = min(nb, N - v0);
   const int tid = threadIdx.x, nt = blockDim.x;  // nt is a multiple of 64, nb <= 32
   const double* __restrict__ in = a.in ? a.in + (long)b * a.strideIn : nullptr;
@@ -192,8 +201,26 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
   double* out = a.out + (long)b * a.strideOut;
   if (!a.rows) {
     const int c = tid & (nb - 1), j = v0 + c;
+    double ss = 0.0;
     if (c < nv)
-      for (int i = tid >> lg; i < N; i += nt >> lg) out[(long)i * N + j] = S[i * nb + c];
+      for (int i = tid >> lg; i < N; i += nt >> lg) {
+        const double v = S[i * nb + c];
+        out[(long)i * N + j] = v;
+        ss += v * v;
+      }
+    if (a.norm2) {  // lanes equal mod nb hold parts of one column; then one partial per wave
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1)
+        if (o >= nb) ss += __shfl_xor(ss, o, 64);
+      double* part = S + (long)N * (nb + 2);  // [waves][nb]
+      if ((tid & 63) < nb) part[(tid >> 6) * nb + (tid & 63)] = ss;
+      __syncthreads();
+      if (tid < nv) {
+        double t = 0.0;
+        for (int w = 0; w < (nt >> 6); ++w) t += part[w * nb + tid];
+        a.norm2[(long)b * N + v0 + tid] = t;
+      }
+    }
   } else {
     for (int c = 0; c < nv; ++c) {
       const int j = v0 + c;
@@ -220,12 +247,16 @@ int launch_kron_windows(Plan& p, hipStream_t st) {
 
 static int kron_max_threads(int P) { return P >= 32 ? 512 : 1024; }
 
-static size_t kron_lds(int N, int nb) { return (size_t)N * (nb + 2) * sizeof(double); }
+// LDS: the block of vectors, two d_l rows, one partial norm per wave and vector
+static size_t kron_lds(int N, int nb, int m) {
+  const int waves = (m * nb + 63) / 64;
+  return ((size_t)N * (nb + 2) + (size_t)waves * nb) * sizeof(double);
+}
 
 int kron_default_nb(const Plan& p) {
   const int m = std::max(p.m.lx, p.m.ly);
   for (int nb = 32; nb > 1; nb /= 2)
-    if (kron_lds(p.n, nb) <= 80 * 1024 && m * nb <= kron_max_threads(p.kron_P)) return nb;
+    if (kron_lds(p.n, nb, m) <= 80 * 1024 && m * nb <= kron_max_threads(p.kron_P)) return nb;
   return 1;
 }
 
@@ -248,7 +279,7 @@ int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
   }
   const int nb = a.nb > 0 ? a.nb : (p.kron_nb > 0 ? p.kron_nb : kron_default_nb(p));
   const int m = std::max(p.m.lx, p.m.ly);
-  const size_t lds = kron_lds(p.n, nb);
+  const size_t lds = kron_lds(p.n, nb, m);
   int lognb = 0;
   while ((1 << lognb) < nb) ++lognb;
   if ((1 << lognb) != nb || nb > 32 || m * nb > kron_max_threads(p.kron_P) || lds > 160 * 1024) {
@@ -279,7 +310,10 @@ int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
   d.inv = a.inv;
   const int threads = (m * nb + 63) / 64 * 64;
   const bool exact = p.m.lx == P && p.m.ly == P;
-  dim3 grid((unsigned)((p.n + nb - 1) / nb), (unsigned)a.batch);
+  d.norm2 = a.rows ? nullptr : a.norm2;
+  d.nvb = (p.n + nb - 1) / nb;
+  d.batch = a.batch;
+  dim3 grid((unsigned)(((long)d.nvb * a.batch + 15) / 16 * 16));
   switch (P) {
     case 4: launch_p<4>(d, exact, grid, threads, lds, st); break;
     case 8: launch_p<8>(d, exact, grid, threads, lds, st); break;
@@ -304,9 +338,10 @@ int tune_kron(Plan& p, int batch, hipStream_t st, float* best_ms_out) {
   const int N = p.n;
   int rc = fill_i32((int32_t*)p.s_work, (long)batch * p.L * N / 4, 0x01010101, st);
   if (rc != SLQ_OK) return rc;
+  // timed as in a chain block: read a product, write a product and its column norms
   KronArgs k{};
   k.in = nullptr;
-  k.out = p.Xa;
+  k.out = p.Xb;
   k.strideOut = (long)N * N;
   k.s = p.s_work;
   k.slice0 = 0;
@@ -314,6 +349,11 @@ int tune_kron(Plan& p, int batch, hipStream_t st, float* best_ms_out) {
   k.step = 1;
   k.scale = 1;
   k.batch = batch;
+  if ((rc = launch_kron(p, k, st)) != SLQ_OK) return rc;
+  k.in = p.Xb;
+  k.strideIn = (long)N * N;
+  k.out = p.Xa;
+  k.norm2 = p.xnorm2;
   hipEvent_t e0, e1;
   SLQ_HIP(hipEventCreate(&e0));
   SLQ_HIP(hipEventCreate(&e1));

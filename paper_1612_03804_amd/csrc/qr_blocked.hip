@@ -48,10 +48,14 @@ __device__ __forceinline__ double pq_block_max(double v, double* red) {
 
 // ------------------------------------------------------------ prepivot ----
 // perm = columns of X diag(D) by decreasing norm (lower index first on
-// ties); W[:, c] = X[:, perm[c]] * D[perm[c]].
+// ties); W[:, c] = X[:, perm[c]] * D[perm[c]].  With norm2 (the squared
+// column norms of X, from the kernel that produced it) X is read once; a
+// column whose plain sum of squares over- or underflowed is summed again here
+// with rescaling.
 __global__ __launch_bounds__(PQ_THREADS) void k_prepivot(int N, const double* __restrict__ Xall,
                                                          double* __restrict__ Wall, const double* __restrict__ Dall,
-                                                         int32_t* __restrict__ permall, int32_t* status) {
+                                                         int32_t* __restrict__ permall, int32_t* status,
+                                                         const double* __restrict__ norm2all) {
   extern __shared__ double lds[];
   const int b = blockIdx.x;
   const long NN = (long)N * N;
@@ -66,14 +70,23 @@ __global__ __launch_bounds__(PQ_THREADS) void k_prepivot(int N, const double* __
   __syncthreads();
   for (int j = threadIdx.x; j < N; j += PQ_THREADS) {
     double ss = 0.0, mx = 0.0;
+    if (norm2all) {
+      ss = norm2all[(long)b * N + j];
+      mx = ss > 0.0 ? 1.0 : 0.0;  // the rescaled pass below finds the true maximum if it is needed
+    } else {
 #pragma unroll 8
-    for (int i = 0; i < N; ++i) {
-      const double v = X[(long)i * N + j];
-      ss += v * v;
-      mx = fmax(mx, fabs(v));
+      for (int i = 0; i < N; ++i) {
+        const double v = X[(long)i * N + j];
+        ss += v * v;
+        mx = fmax(mx, fabs(v));
+      }
     }
     double nv = sqrt(ss);
     if (!(nv < INFINITY) || (nv < 1e-150 && mx > 0.0)) {  // rescale when the plain sum over/underflows
+      if (norm2all) {
+        mx = 0.0;
+        for (int i = 0; i < N; ++i) mx = fmax(mx, fabs(X[(long)i * N + j]));
+      }
       ss = 0.0;
       const double inv = 1.0 / mx;
 #pragma unroll 8
@@ -386,7 +399,8 @@ __global__ void k_zero_i32(int32_t* x, int n) {
 // built panel by panel, so the large blocks are read and written a quarter
 // as often as with one level.
 template <int NB>
-static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st) {
+static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st,
+                       const double* norm2) {
   const int N = p.n;
   const long NN = (long)N * N;
   constexpr int NBO = QR_NBO;
@@ -400,7 +414,7 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
   double* Wt2 = Wt + (long)NBO * N;  // [NBO][N]
   const size_t lpp = sizeof(double) * N + sizeof(int) * N;
   allow_max_lds((const void*)k_prepivot);
-  k_prepivot<<<batch, PQ_THREADS, lpp, st>>>(N, X, p.W, o.D, p.perm, status);
+  k_prepivot<<<batch, PQ_THREADS, lpp, st>>>(N, X, p.W, o.D, p.perm, status, norm2);
   SLQ_LAUNCHED();
   k_zero_i32<<<(batch + 255) / 256, 256, 0, st>>>(o.nref, batch);
   SLQ_LAUNCHED();
@@ -504,11 +518,12 @@ long qr_workspace_per_field(int N) {
 
 int qr_blocked_width(int N) { return N <= 448 ? 32 : (N <= 1152 ? 16 : 8); }
 
-int launch_qr_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st) {
+int launch_qr_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st,
+                      const double* norm2) {
   switch (qr_blocked_width(p.n)) {
-    case 32: return run_blocked<32>(p, batch, X, o, status, st);
-    case 16: return run_blocked<16>(p, batch, X, o, status, st);
-    default: return run_blocked<8>(p, batch, X, o, status, st);
+    case 32: return run_blocked<32>(p, batch, X, o, status, st, norm2);
+    case 16: return run_blocked<16>(p, batch, X, o, status, st, norm2);
+    default: return run_blocked<8>(p, batch, X, o, status, st, norm2);
   }
 }
 

@@ -190,6 +190,7 @@ struct Plan {
   // per-item vectors
   double *D, *invD, *Tblk;  // D, 1/D: [N]; compact-WY T blocks: (N + 32) * 32 per field
   int32_t* perm;            // [N]
+  double* xnorm2;           // [N]: squared column norms of a structured block product
   int32_t* nref;            // [1] reflectors with tau != 0 in the latest QR
   int32_t* status;          // [max_batch] scratch status when caller passes NULL
   int8_t* s_work;           // [max_batch][L][N] proposal fields
@@ -370,6 +371,7 @@ struct KronArgs {
   int inv;           // E^{-1} and 1/d_l instead
   int nb = 0;        // vectors per workgroup (0: the plan's choice)
   int batch;
+  double* norm2 = nullptr;  // rows == 0: [batch][N] squared 2-norms of the output columns, or null
 };
 int kron_line_size(int lx, int ly);
 int kron_default_nb(const Plan& p);
@@ -397,12 +399,15 @@ inline UdvRef plan_udv(Plan& p) { return UdvRef{p.U, p.D, p.V, p.nref}; }
 // and updates with MFMA GEMMs (it uses Xa or Xb, whichever does not hold X,
 // and Vt, dX, dY as scratch).
 int launch_qr(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st);
-int launch_qr_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st);
+// norm2 (optional): squared 2-norms of the columns of X, [batch][N]
+int launch_qr_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st,
+                      const double* norm2 = nullptr);
 inline int launch_qr(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st) {
   return launch_qr(p, batch, X, plan_udv(p), status, st);
 }
-inline int launch_qr_blocked(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st) {
-  return launch_qr_blocked(p, batch, X, plan_udv(p), status, st);
+inline int launch_qr_blocked(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st,
+                             const double* norm2 = nullptr) {
+  return launch_qr_blocked(p, batch, X, plan_udv(p), status, st, norm2);
 }
 int launch_permute_rows(Plan& p, int batch, const double* V, double* Vt, hipStream_t st);
 // log|det(1 + U D V)|, its sign and optionally G = (1 + U D V)^{-1}; W is

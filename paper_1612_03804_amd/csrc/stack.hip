@@ -99,9 +99,12 @@ void release_stack(Plan& p) {
 // Product of the count slices first, first + step, ... (0-based), the first
 // one applied first, onto `start` (the identity when start is null).  Plain:
 // X <- B_l X = E diag(d_l) X.  Transposed: X <- B_l^T X = diag(d_l) E X.
-// Returns the buffer (Xa or Xb) that holds the result.
+// Returns the buffer (Xa or Xb) that holds the result, and in *norm2 the
+// squared column norms of it when the structured product computed them
+// (else null).
 static int block_product(Plan& p, int batch, const int8_t* s, int first, int count, int step, bool transposed,
-                         const double* start, double** out, hipStream_t st) {
+                         const double* start, double** out, const double** norm2, hipStream_t st) {
+  *norm2 = nullptr;
   const int N = p.n;
   const long NN = (long)N * N;
   const long strideS = (long)p.L * N;
@@ -117,7 +120,9 @@ static int block_product(Plan& p, int batch, const int8_t* s, int first, int cou
     k.step = step;
     k.scale = transposed ? 2 : 1;
     k.batch = batch;
+    k.norm2 = p.xnorm2;
     *out = p.Xa;
+    *norm2 = p.xnorm2;
     return launch_kron(p, k, st);
   }
   GemmArgs g{};
@@ -170,7 +175,7 @@ static int block_product(Plan& p, int batch, const int8_t* s, int first, int cou
 // D_in and V_in null mean the identity; D_in may be out.D and V_in out.V.
 // X (Xa or Xb) is destroyed.
 static int stabilise(Plan& p, int batch, double* X, const double* D_in, const double* V_in, const UdvRef& out,
-                     int32_t* status, hipStream_t st) {
+                     int32_t* status, hipStream_t st, const double* norm2 = nullptr) {
   const int N = p.n;
   const long NN = (long)N * N;
   if (!D_in)
@@ -178,7 +183,7 @@ static int stabilise(Plan& p, int batch, double* X, const double* D_in, const do
   else if (D_in != out.D)
     SLQ_TRY(copy_f64(D_in, out.D, (long)batch * N, st));
   if (N > 64)
-    SLQ_TRY(launch_qr_blocked(p, batch, X, out, status, st));
+    SLQ_TRY(launch_qr_blocked(p, batch, X, out, status, st, norm2));
   else
     SLQ_TRY(launch_qr(p, batch, X, out, status, st));
   if (!V_in) {
@@ -215,13 +220,14 @@ static int build_left(Plan& p, int batch, const int8_t* s, int32_t* status, hipS
     const int top = (e == nl - 1) ? L : b + ns;     // 1-based
     const UdvRef out = entry(p, e);
     double* X = nullptr;
+    const double* n2 = nullptr;
     if (e == nl - 1) {
-      SLQ_TRY(block_product(p, batch, s, top - 1, top - b, -1, true, nullptr, &X, st));
-      SLQ_TRY(stabilise(p, batch, X, nullptr, nullptr, out, status, st));
+      SLQ_TRY(block_product(p, batch, s, top - 1, top - b, -1, true, nullptr, &X, &n2, st));
+      SLQ_TRY(stabilise(p, batch, X, nullptr, nullptr, out, status, st, n2));
     } else {
       const UdvRef prev = entry(p, e + 1);
-      SLQ_TRY(block_product(p, batch, s, top - 1, top - b, -1, true, prev.U, &X, st));
-      SLQ_TRY(stabilise(p, batch, X, prev.D, prev.V, out, status, st));
+      SLQ_TRY(block_product(p, batch, s, top - 1, top - b, -1, true, prev.U, &X, &n2, st));
+      SLQ_TRY(stabilise(p, batch, X, prev.D, prev.V, out, status, st, n2));
     }
   }
   return SLQ_OK;
@@ -232,12 +238,13 @@ static int extend_right(Plan& p, int batch, const int8_t* s, int b, int32_t* sta
   const int ns = p.m.n_stab;
   const UdvRef r = entry(p, n_left(p));
   double* X = nullptr;
+  const double* n2 = nullptr;
   if (b == ns) {
-    SLQ_TRY(block_product(p, batch, s, 0, ns, 1, false, nullptr, &X, st));
-    return stabilise(p, batch, X, nullptr, nullptr, r, status, st);
+    SLQ_TRY(block_product(p, batch, s, 0, ns, 1, false, nullptr, &X, &n2, st));
+    return stabilise(p, batch, X, nullptr, nullptr, r, status, st, n2);
   }
-  SLQ_TRY(block_product(p, batch, s, b - ns, ns, 1, false, r.U, &X, st));
-  return stabilise(p, batch, X, r.D, r.V, r, status, st);
+  SLQ_TRY(block_product(p, batch, s, b - ns, ns, 1, false, r.U, &X, &n2, st));
+  return stabilise(p, batch, X, r.D, r.V, r, status, st, n2);
 }
 
 // Fresh G_b into p.Xa from R(b) and Left(b) (b < L), or from R(L) alone.
