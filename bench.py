@@ -36,7 +36,7 @@ COPY_CALIBRATION_BYTES = 1 << 30
 # over the 8 blocks of an evaluation (the first block starts from the identity
 # and reads no X): rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, each scaled by
 # what the same counter reads for the 1 GiB copy of --copy-calibration.
-KRON_TRAFFIC = {"batch": 512, "vectors_per_workgroup": 8, "bytes": None}
+KRON_TRAFFIC = {"batch": 512, "vectors_per_workgroup": 8, "bytes": 1.2475e9}
 
 
 def cpu_baseline(model, terms, theta, fields, logabs, signs, steps, seed):
