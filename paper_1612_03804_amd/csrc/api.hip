@@ -145,7 +145,10 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
   const long NN = (long)N * N;
   const long strideS = (long)L * N;
   SLQ_TRY(fill_f64(p.D, (long)batch * N, 1.0, st));
-  SLQ_TRY(launch_set_identity(p, batch, p.V, st));
+  // V of block k goes to p.V or p.Vt so that the last block's lands in p.V
+  const int nblk = (L + ns - 1) / ns;
+  double* vnext = (nblk % 2 == 1) ? p.V : p.Vt;
+  double* vprev = nullptr;
   GemmArgs g{};
   g.M = N;
   g.N = N;
@@ -242,27 +245,13 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
     } else {
       SLQ_TRY(launch_qr(p, batch, cur, status, st));
     }
-    SLQ_TRY(launch_permute_rows(p, batch, p.V, p.Vt, st));
-    GemmArgs v{};  // V <- diag(1/D) triu(R) (Pi^T V)
-    v.M = N;
-    v.N = N;
-    v.K = N;
-    v.A = p.W;
-    v.lda = N;
-    v.strideA = NN;
-    v.B = p.Vt;
-    v.ldb = N;
-    v.strideB = NN;
-    v.C = p.V;
-    v.ldc = N;
-    v.strideC = NN;
-    v.rowscale = p.invD;
-    v.strideRS = N;
-    v.alpha = 1.0;
-    v.beta = 0.0;
-    v.a_upper = 1;
-    v.batch = batch;
-    SLQ_TRY(launch_gemm(v, false, false, st));
+    // V <- diag(1/D) triu(R) (Pi^T V)
+    if (!vprev)
+      SLQ_TRY(launch_first_v(p, batch, vnext, st));
+    else
+      SLQ_TRY(launch_v_update(p, batch, vprev, vnext, st));
+    vprev = vnext;
+    vnext = (vnext == p.V) ? p.Vt : p.V;
   }
   return SLQ_OK;
 }

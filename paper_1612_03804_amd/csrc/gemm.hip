@@ -46,6 +46,7 @@ __global__ __launch_bounds__(64 * GM * GN) void k_gemm(GemmArgs g, int ntm, int 
   constexpr int PADM = TM + 2, PADN = TN + 2;
   __shared__ double As[2][TK][PADM];
   __shared__ double Bs[2][TK][PADN];
+  extern __shared__ int brow_s[];  // triangular mode with a row gather of B: [K]
 
   // XCD-aware decode of the linear workgroup id: item = field, tile in item
   const int tpi = ntm * ntn;
@@ -76,6 +77,12 @@ __global__ __launch_bounds__(64 * GM * GN) void k_gemm(GemmArgs g, int ntm, int 
 
   double ra[APT], rb[BPT];
   const int kbeg = AUP ? (m0 / TK) * TK : 0;
+  const bool gather = AUP && g.brow;
+  if (gather) {
+    const int32_t* br = g.brow + (long)b * g.strideBrow;
+    for (int k = tid; k < g.K; k += NT) brow_s[k] = br[k];
+    __syncthreads();
+  }
 
   auto load = [&](int k0) {
 #pragma unroll
@@ -100,7 +107,7 @@ __global__ __launch_bounds__(64 * GM * GN) void k_gemm(GemmArgs g, int ntm, int 
         const int kk = TB ? idx % TK : idx / TN;
         const int gn = n0 + nn, gk = k0 + kk;
         if (gn < g.N && gk < g.K) {
-          v = TB ? B[(long)gn * g.ldb + gk] : B[(long)gk * g.ldb + gn];
+          v = TB ? B[(long)gn * g.ldb + gk] : B[(long)(gather ? brow_s[gk] : gk) * g.ldb + gn];
           if (FS) v *= (S[gk] > 0) ? rpos : rneg;
         }
       }
@@ -187,12 +194,17 @@ static int run(const GemmArgs& a, bool ta, bool tb, hipStream_t st) {
     set_error("triangular or field-scaled GEMMs are only supported untransposed");
     return SLQ_ERR_ARG;
   }
+  if (a.brow && !a.a_upper) {
+    set_error("a row gather of B is only supported with a triangular A");
+    return SLQ_ERR_ARG;
+  }
   if (a.a_upper && a.S) {
     set_error("a GEMM is either triangular or field-scaled");
     return SLQ_ERR_ARG;
   }
   if (a.a_upper) {
-    k_gemm<WM, WN, GM, GN, TK, false, false, 1><<<grid, block, 0, st>>>(a, ntm, ntn);
+    const size_t lds = a.brow ? sizeof(int) * (size_t)a.K : 0;
+    k_gemm<WM, WN, GM, GN, TK, false, false, 1><<<grid, block, lds, st>>>(a, ntm, ntn);
   } else if (a.S && a.s_out) {
     if (a.M != a.K) {
       set_error("output-row field scaling needs M == K");

@@ -385,22 +385,57 @@ int launch_set_identity(Plan& p, int batch, double* X, hipStream_t st) {
   return SLQ_OK;
 }
 
-__global__ void k_permute_rows(int N, const double* __restrict__ V, const int32_t* __restrict__ perm,
-                               double* __restrict__ Vt) {
+// V_prev = I: V[i][j] = R[i][c] / D_i where perm[c] = j, zero for c < i
+// (diag(1/D) triu(R) Pi^T).  One workgroup per 8 rows of a field; the inverse
+// permutation in LDS makes the writes coalesced.
+constexpr int FV_ROWS = 8;
+__global__ __launch_bounds__(256) void k_first_v(int N, const double* __restrict__ W, const double* __restrict__ invD,
+                                                 const int32_t* __restrict__ perm, double* __restrict__ V) {
+  extern __shared__ int cinv[];  // [N]
+  const int b = blockIdx.y, r0 = blockIdx.x * FV_ROWS;
   const long NN = (long)N * N;
-  const int b = blockIdx.y;
-  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < NN; idx += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(idx / N), j = (int)(idx % N);
-    Vt[b * NN + idx] = V[b * NN + (long)perm[(long)b * N + c] * N + j];
+  for (int c = threadIdx.x; c < N; c += blockDim.x) cinv[perm[(long)b * N + c]] = c;
+  __syncthreads();
+  const int rows = min(FV_ROWS, N - r0);
+  for (int e = threadIdx.x; e < rows * N; e += blockDim.x) {
+    const int i = r0 + e / N, j = e % N;
+    const int c = cinv[j];
+    V[b * NN + (long)i * N + j] = c >= i ? W[b * NN + (long)i * N + c] * invD[(long)b * N + i] : 0.0;
   }
 }
 
-int launch_permute_rows(Plan& p, int batch, const double* V, double* Vt, hipStream_t st) {
-  const long NN = (long)p.n * p.n;
-  dim3 grid((unsigned)std::min<long>((NN + 255) / 256, 1024), batch);
-  k_permute_rows<<<grid, 256, 0, st>>>(p.n, V, p.perm, Vt);
+int launch_first_v(Plan& p, int batch, double* V, hipStream_t st) {
+  dim3 grid((unsigned)((p.n + FV_ROWS - 1) / FV_ROWS), (unsigned)batch);
+  k_first_v<<<grid, 256, sizeof(int) * p.n, st>>>(p.n, p.W, p.invD, p.perm, V);
   SLQ_LAUNCHED();
   return SLQ_OK;
+}
+
+int launch_v_update(Plan& p, int batch, const double* V_in, double* V_out, hipStream_t st) {
+  const int N = p.n;
+  const long NN = (long)N * N;
+  GemmArgs v{};  // V_out <- diag(1/D) triu(R) (Pi^T V_in), Pi^T applied while B is read
+  v.M = N;
+  v.N = N;
+  v.K = N;
+  v.A = p.W;
+  v.lda = N;
+  v.strideA = NN;
+  v.B = V_in;
+  v.ldb = N;
+  v.strideB = NN;
+  v.brow = p.perm;
+  v.strideBrow = N;
+  v.C = V_out;
+  v.ldc = N;
+  v.strideC = NN;
+  v.rowscale = p.invD;
+  v.strideRS = N;
+  v.alpha = 1.0;
+  v.beta = 0.0;
+  v.a_upper = 1;
+  v.batch = batch;
+  return launch_gemm(v, false, false, st);
 }
 
 __global__ void k_check_spins(long total_per_item, const int8_t* __restrict__ s, int32_t* status) {

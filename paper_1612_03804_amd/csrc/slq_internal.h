@@ -315,6 +315,8 @@ struct GemmArgs {
   long strideRS;
   double alpha, beta;
   int a_upper;        // A is upper triangular: entries with k < m are taken as zero
+  const int32_t* brow = nullptr;  // a_upper only: row k of op(B) is row brow[k] of B ([batch] + strideBrow)
+  long strideBrow = 0;
   int s_out;          // apply the field factor to the rows of C instead of the rows of op(B)
   int cfg = -1;       // tile configuration (GemmCfg), -1 = default choice
   int batch;
@@ -409,7 +411,11 @@ inline int launch_qr_blocked(Plan& p, int batch, const double* X, int32_t* statu
                              const double* norm2 = nullptr) {
   return launch_qr_blocked(p, batch, X, plan_udv(p), status, st, norm2);
 }
-int launch_permute_rows(Plan& p, int batch, const double* V, double* Vt, hipStream_t st);
+// V <- diag(1/D) triu(R) Pi^T, the V update of a block whose V_prev is the
+// identity (R in p.W, 1/D in p.invD, Pi in p.perm)
+int launch_first_v(Plan& p, int batch, double* V, hipStream_t st);
+// V_out <- diag(1/D) triu(R) Pi^T V_in (V_out != V_in)
+int launch_v_update(Plan& p, int batch, const double* V_in, double* V_out, hipStream_t st);
 // log|det(1 + U D V)|, its sign and optionally G = (1 + U D V)^{-1}; W is
 // scratch.
 int launch_finish(Plan& p, int batch, const UdvRef& f, double* G, double* logabs, int8_t* sign, int32_t* status,

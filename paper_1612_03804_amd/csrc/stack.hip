@@ -186,30 +186,10 @@ static int stabilise(Plan& p, int batch, double* X, const double* D_in, const do
     SLQ_TRY(launch_qr_blocked(p, batch, X, out, status, st, norm2));
   else
     SLQ_TRY(launch_qr(p, batch, X, out, status, st));
-  if (!V_in) {
-    SLQ_TRY(launch_set_identity(p, batch, X, st));  // X is free once the QR has run
-    V_in = X;
-  }
-  SLQ_TRY(launch_permute_rows(p, batch, V_in, p.Vt, st));
-  GemmArgs v{};
-  v.M = N;
-  v.N = N;
-  v.K = N;
-  v.A = p.W;
-  v.lda = N;
-  v.strideA = NN;
-  v.B = p.Vt;
-  v.ldb = N;
-  v.strideB = NN;
-  v.C = out.V;
-  v.ldc = N;
-  v.strideC = NN;
-  v.rowscale = p.invD;
-  v.strideRS = N;
-  v.alpha = 1.0;
-  v.a_upper = 1;
-  v.batch = batch;
-  return launch_gemm(v, false, false, st);
+  if (!V_in) return launch_first_v(p, batch, out.V, st);
+  if (V_in != out.V) return launch_v_update(p, batch, V_in, out.V, st);
+  SLQ_TRY(copy_f64(V_in, p.Vt, (long)batch * NN, st));  // in place: read from a copy
+  return launch_v_update(p, batch, p.Vt, out.V, st);
 }
 
 // Left(b)^T for every boundary b < L, from the top of the chain down.
