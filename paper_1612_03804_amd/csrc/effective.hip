@@ -52,6 +52,8 @@ EffDev eff_dev_view(const Plan& p, const Eff& e) {
   d.shell_dxy = e.d_shell_dxy;
   d.n_pairs = e.n_pairs;
   d.pairs = e.d_pairs;
+  d.n_uoff = e.n_uoff;
+  d.uoff = e.d_uoff;
   return d;
 }
 
@@ -123,15 +125,21 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
   __shared__ double one_body;
   const int np = d.n_pairs, N = d.N, L = d.L, lx = d.lx, ly = d.ly;
   double* lam = sm;                            // [np]
-  int32_t* pr = (int32_t*)(lam + np);          // [np]
-  int8_t* f = (int8_t*)(pr + np);              // [L][N]
+  int32_t* pr = (int32_t*)(lam + np);          // [np]: u N | (dt + 2048) << 16
+  int16_t* spart = (int16_t*)(pr + np);        // [n_uoff][N]: partner site of each site under offset u
+  int8_t* f = (int8_t*)(spart + d.n_uoff * N); // [L][N]
   const int b = blockIdx.x, tid = threadIdx.x;
   int8_t* s = s_all + (long)b * L * N;
   const uint64_t chain = chain0 + b;
   for (int p = tid; p < np; p += EFF_THREADS) {
     const int32_t e = d.pairs[p];
-    pr[p] = e;
+    pr[p] = (e & 255) * N | (((e >> 8) & 4095) << 16);
     lam[p] = d.theta[1 + (e >> 20)];
+  }
+  for (int idx = tid; idx < d.n_uoff * N; idx += EFF_THREADS) {
+    const int u = idx / N, i = idx % N;
+    const int xx = wrap2(i % lx + d.uoff[2 * u], lx), yy = wrap2(i / lx + d.uoff[2 * u + 1], ly);
+    spart[idx] = (int16_t)(xx + lx * yy);
   }
   if (tid == 0) {
     double h = 0.0;
@@ -152,16 +160,30 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
     const int beg = d.col_off[colour], end = d.col_off[colour + 1];
     for (int t = beg + slot; t < end; t += nslot) {  // the four lanes of a quad share t
       const int i = d.col_sites[t];
-      const int x = i % lx, y = i / lx;
+      const int16_t* sp_i = spart + i;
+      // partners p = sub, sub + 4, ... four at a time: their LDS reads are in
+      // flight together (the sum keeps the order p = sub, sub + 4, ...)
       double hs = 0.0;
-      for (int p = sub; p < np; p += 4) {
-        const int32_t e = pr[p];
-        const int xx = wrap2(x + (e & 15) - 4, lx);
-        const int yy = wrap2(y + ((e >> 4) & 15) - 4, ly);
-        int ll = l + ((e >> 8) & 4095) - 2048;
-        if (ll < 0) ll += L;
-        if (ll >= L) ll -= L;
-        hs += lam[p] * (double)f[ll * N + xx + lx * yy];
+      constexpr int32_t kSelf = 2048 << 16;  // offset 0 of slice l: a valid address, weight 0
+      for (int p0 = sub; p0 < np; p0 += 16) {
+        int32_t e[4];
+        double w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int p = p0 + 4 * u;
+          e[u] = p < np ? pr[p] : kSelf;
+          w[u] = p < np ? lam[p] : 0.0;
+        }
+        double sp[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          int ll = l + (e[u] >> 16) - 2048;
+          if (ll < 0) ll += L;
+          if (ll >= L) ll -= L;
+          sp[u] = (double)f[__umul24(ll, N) + sp_i[e[u] & 0xffff]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) hs += w[u] * sp[u];
       }
       hs += dpp_move<DPP_QUAD_XOR1>(hs);
       hs += dpp_move<DPP_QUAD_XOR2>(hs);
@@ -200,7 +222,8 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
 }
 
 static size_t eff_lds_bytes(const Plan& p, const Eff& e) {
-  return (size_t)e.n_pairs * (sizeof(double) + sizeof(int32_t)) + (size_t)p.L * p.n;
+  return (size_t)e.n_pairs * (sizeof(double) + sizeof(int32_t)) + (size_t)e.n_uoff * p.n * sizeof(int16_t) +
+         (size_t)p.L * p.n;
 }
 
 int launch_eff_sweep(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, uint64_t seed, uint64_t step,
@@ -548,15 +571,23 @@ int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const 
     maxc = std::max(maxc, (int)sites.size() - off[c]);
   }
   off[nc] = (int32_t)sites.size();
-  std::vector<int32_t> pairs;
+  std::vector<int32_t> pairs, uoff;
+  int uidx[25];
+  for (int o = 0; o < 25; ++o) uidx[o] = -1;
   for (int k = 0; k < n_terms; ++k) {
     const int r = terms[2 * k], dl = terms[2 * k + 1];
     if (r == 0 && dl == 0) continue;
-    for (int o = kShellOff[r]; o < kShellOff[r + 1]; ++o)
+    for (int o = kShellOff[r]; o < kShellOff[r + 1]; ++o) {
+      if (uidx[o] < 0) {
+        uidx[o] = (int)uoff.size() / 2;
+        uoff.push_back(kShellDxy[o][0]);
+        uoff.push_back(kShellDxy[o][1]);
+      }
       for (int sg = (dl == 0 ? 0 : -1); sg <= (dl == 0 ? 0 : 1); sg += 2) {
         const int dt = sg * dl;
-        pairs.push_back((kShellDxy[o][0] + 4) | ((kShellDxy[o][1] + 4) << 4) | ((dt + 2048) << 8) | (k << 20));
+        pairs.push_back(uidx[o] | ((dt + 2048) << 8) | (k << 20));
       }
+    }
   }
   std::vector<double> theta(1 + n_terms);
   theta[0] = c0;
@@ -577,11 +608,12 @@ int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const 
   e.n_classes = nc * L;
   e.max_class = maxc;
   const size_t b_terms = 8 * n_terms, b_theta = 8 * (1 + n_terms), b_sites = 4 * N, b_off = 4 * (nc + 1),
-               b_shoff = 4 * shoff.size(), b_shd = 4 * shd.size(), b_pairs = 4 * std::max<size_t>(1, pairs.size());
+               b_shoff = 4 * shoff.size(), b_shd = 4 * shd.size(), b_pairs = 4 * std::max<size_t>(1, pairs.size()),
+               b_uoff = 4 * std::max<size_t>(1, uoff.size());
   const size_t o1 = 0, o2 = o1 + (b_terms + 255) / 256 * 256, o3 = o2 + (b_theta + 255) / 256 * 256,
                o4 = o3 + (b_sites + 255) / 256 * 256, o5 = o4 + (b_off + 255) / 256 * 256,
                o6 = o5 + (b_shoff + 255) / 256 * 256, o7 = o6 + (b_shd + 255) / 256 * 256,
-               total = o7 + (b_pairs + 255) / 256 * 256;
+               o8 = o7 + (b_pairs + 255) / 256 * 256, total = o8 + (b_uoff + 255) / 256 * 256;
   char* base = nullptr;
   if (hipSetDevice(p.device) != hipSuccess || hipMalloc((void**)&base, total) != hipSuccess) {
     delete h;
@@ -595,8 +627,11 @@ int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const 
   e.d_shell_dxy = (int32_t*)(base + o6);
   e.d_pairs = (int32_t*)(base + o7);
   e.n_pairs = (int)pairs.size();
+  e.d_uoff = (int32_t*)(base + o8);
+  e.n_uoff = (int)uoff.size() / 2;
   bool ok = (pairs.empty() ||
              hipMemcpy(e.d_pairs, pairs.data(), 4 * pairs.size(), hipMemcpyHostToDevice) == hipSuccess) &&
+            (uoff.empty() || hipMemcpy(e.d_uoff, uoff.data(), 4 * uoff.size(), hipMemcpyHostToDevice) == hipSuccess) &&
             hipMemcpy(e.d_terms, terms, b_terms, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(e.d_theta, theta.data(), b_theta, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(e.d_col_sites, sites.data(), b_sites, hipMemcpyHostToDevice) == hipSuccess &&

@@ -248,9 +248,11 @@ struct Eff {
   int32_t* d_ncol_off = nullptr;
   int n_ncolours = 0;
   // every partner relation of the two-body terms, one entry per (offset, +-dl):
-  // (dx + 4) | (dy + 4) << 4 | (dt + 2048) << 8 | k << 20
+  // u | (dt + 2048) << 8 | k << 20, u the index of the spatial offset in d_uoff
   int n_pairs = 0;
   int32_t* d_pairs = nullptr;
+  int n_uoff = 0;
+  int32_t* d_uoff = nullptr;  // [n_uoff][2] the distinct spatial offsets (dx, dy) of the pairs
 };
 
 // Device view of an effective model.
@@ -265,6 +267,8 @@ struct EffDev {
   const int32_t* shell_dxy;  // [25][2]
   int n_pairs;
   const int32_t* pairs;      // [n_pairs], see Eff
+  int n_uoff;
+  const int32_t* uoff;       // [n_uoff][2]
 };
 EffDev eff_dev_view(const Plan& p, const Eff& e);
 
