@@ -107,6 +107,7 @@ __global__ __launch_bounds__(256) void k_eff_sweep(EffDev d, int8_t* s_all, int 
 // list in LDS.  Four lanes share a site, each summing every fourth partner;
 // a quad reduction joins them and the first lane draws and flips.
 constexpr int EFF_THREADS = 512;
+constexpr int EFF_LPS = 4;  // lanes per site
 
 __device__ __forceinline__ int wrap2(int v, int n) {  // v in [-2n, 3n)
   if (v < 0) v += n;
@@ -127,7 +128,9 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
   double* lam = sm;                            // [np]
   int32_t* pr = (int32_t*)(lam + np);          // [np]: u N | (dt + 2048) << 16
   int16_t* spart = (int16_t*)(pr + np);        // [n_uoff][N]: partner site of each site under offset u
-  int8_t* f = (int8_t*)(spart + d.n_uoff * N); // [L][N]
+  int16_t* csite = spart + d.n_uoff * N;       // [N] sites by colour
+  int16_t* coff = csite + N;                   // [n_colours + 1]
+  int8_t* f = (int8_t*)(coff + d.n_colours + 1); // [L][N]
   const int b = blockIdx.x, tid = threadIdx.x;
   int8_t* s = s_all + (long)b * L * N;
   const uint64_t chain = chain0 + b;
@@ -136,6 +139,8 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
     pr[p] = (e & 255) * N | (((e >> 8) & 4095) << 16);
     lam[p] = d.theta[1 + (e >> 20)];
   }
+  for (int i = tid; i < N; i += EFF_THREADS) csite[i] = (int16_t)d.col_sites[i];
+  for (int c = tid; c <= d.n_colours; c += EFF_THREADS) coff[c] = (int16_t)d.col_off[c];
   for (int idx = tid; idx < d.n_uoff * N; idx += EFF_THREADS) {
     const int u = idx / N, i = idx % N;
     const int xx = wrap2(i % lx + d.uoff[2 * u], lx), yy = wrap2(i / lx + d.uoff[2 * u + 1], ly);
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
   }
   for (long i = tid; i < (long)L * N; i += EFF_THREADS) f[i] = s[i];
   __syncthreads();
-  const int sub = tid & 3, slot = tid >> 2, nslot = EFF_THREADS / 4;
+  const int sub = tid & (EFF_LPS - 1), slot = tid / EFF_LPS, nslot = EFF_THREADS / EFF_LPS;
   const double h1 = one_body;
   long long acc = 0;
   double dsum = 0.0;
@@ -157,20 +162,20 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
     const uint32_t cls = philox_below((uint32_t)d.n_classes, 0, (uint64_t)mv, step, chain, seed, TAG_EFFECTIVE);
     const int colour = (int)(cls % d.n_colours);
     const int l = (int)(cls / d.n_colours);  // 0-based slice
-    const int beg = d.col_off[colour], end = d.col_off[colour + 1];
-    for (int t = beg + slot; t < end; t += nslot) {  // the four lanes of a quad share t
-      const int i = d.col_sites[t];
+    const int beg = coff[colour], end = coff[colour + 1];
+    for (int t = beg + slot; t < end; t += nslot) {  // the lanes of a group share t
+      const int i = csite[t];
       const int16_t* sp_i = spart + i;
       // partners p = sub, sub + 4, ... four at a time: their LDS reads are in
       // flight together (the sum keeps the order p = sub, sub + 4, ...)
       double hs = 0.0;
       constexpr int32_t kSelf = 2048 << 16;  // offset 0 of slice l: a valid address, weight 0
-      for (int p0 = sub; p0 < np; p0 += 16) {
+      for (int p0 = sub; p0 < np; p0 += 4 * EFF_LPS) {
         int32_t e[4];
         double w[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int p = p0 + 4 * u;
+          const int p = p0 + EFF_LPS * u;
           e[u] = p < np ? pr[p] : kSelf;
           w[u] = p < np ? lam[p] : 0.0;
         }
@@ -222,8 +227,8 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
 }
 
 static size_t eff_lds_bytes(const Plan& p, const Eff& e) {
-  return (size_t)e.n_pairs * (sizeof(double) + sizeof(int32_t)) + (size_t)e.n_uoff * p.n * sizeof(int16_t) +
-         (size_t)p.L * p.n;
+  return (size_t)e.n_pairs * (sizeof(double) + sizeof(int32_t)) +
+         ((size_t)e.n_uoff * p.n + p.n + e.n_colours + 1) * sizeof(int16_t) + (size_t)p.L * p.n;
 }
 
 int launch_eff_sweep(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, uint64_t seed, uint64_t step,
