@@ -397,7 +397,11 @@ __global__ void k_zero_i32(int32_t* x, int n) {
 // block with its combined compact-WY factor
 //     T_O = [[T_A, -T_A (V_A^T V_B) T_B], [0, T_B]]
 // built panel by panel, so the large blocks are read and written a quarter
-// as often as with one level.
+// as often as with one level.  When QR_NBO does not divide N the short block
+// comes first: every later block then starts QR_NBO-aligned from the end, so
+// the large updates have row and column counts that are multiples of the
+// 128 x 64 tiles (N = 400: 384 x 256 and 256 x 128 instead of 400 x 272 and
+// 272 x 144).
 template <int NB>
 static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st,
                        const double* norm2) {
@@ -449,11 +453,14 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     if (rc == SLQ_OK) rc = gemm(m, n, k, Vp, N, NN, false, Wt2, N, sW, Bp, N, NN, -1.0, 1.0);
     return rc;
   };
+  const int rr = N % NBO;  // width of the short first block (0: none)
+  auto bstart = [&](int ob) { return rr == 0 ? ob * NBO : (ob == 0 ? 0 : rr + (ob - 1) * NBO); };
+  auto bwidth = [&](int ob) { return rr == 0 ? NBO : (ob == 0 ? rr : NBO); };
   for (int ob = 0; ob < nout; ++ob) {
-    const int J0 = ob * NBO, wo = std::min(NBO, N - J0);
+    const int J0 = bstart(ob), wo = bwidth(ob);
     double* Tb = TO + ob * sT;
     for (int j0 = J0; j0 < J0 + wo; j0 += NB) {
-      const int nbw = std::min(NB, N - j0), m = N - j0, sft = j0 - J0;
+      const int nbw = std::min(NB, J0 + wo - j0), m = N - j0, sft = j0 - J0;
       double* Tp = Tb + (long)sft * NBO + sft;
       PanelArgs a{N, j0, nbw, p.W, Vbuf, J0, Tp, sW, NBO, wo - sft, o.D, p.invD, o.nref, status};
       constexpr int RPL = PanelShape<NB>::RPL;
@@ -480,7 +487,7 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
   // V_O: U[:, block] = [I; 0] - V_O (T_O V_top^T), one small and one rank-wo GEMM.
   SLQ_TRY(launch_set_identity(p, batch, o.U, st));
   for (int ob = nout - 1; ob >= 0; --ob) {
-    const int J0 = ob * NBO, wo = std::min(NBO, N - J0), m = N - J0;
+    const int J0 = bstart(ob), wo = bwidth(ob), m = N - J0;
     const double* Vp = Vbuf + (long)J0 * N + J0;
     double* Ub = o.U + (long)J0 * N + J0;
     if (m > wo) {  // columns beyond the block: their rows J0..J0+wo-1 are still zero
