@@ -424,11 +424,11 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
   SLQ_LAUNCHED();
   // tiles from a sweep of these shapes on MI355X (N = 400, 256 fields): 128 x 64
   // with 8 wavefronts wherever the output has 64 rows or more, 32 x 64 with K 16
-  // for the thin products of the panels
+  // for the thin products of the panels, 16 x 64 for those of a 16-column block
   auto gemm = [&](int M, int Nc, int K, const double* A, long lda, long sA, bool ta, const double* B, long ldb,
                   long sB, double* C, long ldc, long sC, double alpha, double beta) -> int {
     GemmArgs g{};
-    g.cfg = M >= 64 ? GEMM_128x64 : GEMM_32x64;
+    g.cfg = M >= 64 ? GEMM_128x64 : (M <= 16 ? GEMM_16x64 : GEMM_32x64);
     g.M = M;
     g.N = Nc;
     g.K = K;
