@@ -242,6 +242,7 @@ int launch_gemm_cfg(const GemmArgs& a, bool ta, bool tb, int cfg, hipStream_t st
     case GEMM_64x128: return run<2, 2, 2, 4, 8>(a, ta, tb, st);
     case GEMM_128x64: return run<2, 2, 4, 2, 8>(a, ta, tb, st);
     case GEMM_16x64: return run<1, 1, 1, 4, 16>(a, ta, tb, st);
+    case GEMM_128x16: return run<2, 1, 4, 1, 8>(a, ta, tb, st);
     default:
       set_error("unknown GEMM tile configuration");
       return SLQ_ERR_ARG;

@@ -435,6 +435,17 @@ int launch_v_update(Plan& p, int batch, const double* V_in, double* V_out, hipSt
   v.beta = 0.0;
   v.a_upper = 1;
   v.batch = batch;
+  // columns up to the last multiple of 128 on 64 x 128 tiles, a 16-column
+  // remainder on 128 x 16 tiles (no padded columns)
+  const int Nm = N / 128 * 128;
+  if (Nm == 0 || Nm == N || (N - Nm) % 16 != 0) return launch_gemm(v, false, false, st);
+  v.N = Nm;
+  v.cfg = GEMM_64x128;
+  SLQ_TRY(launch_gemm(v, false, false, st));
+  v.N = N - Nm;
+  v.B = V_in + Nm;
+  v.C = V_out + Nm;
+  v.cfg = (N - Nm) <= 16 ? GEMM_128x16 : GEMM_64x128;
   return launch_gemm(v, false, false, st);
 }
 
