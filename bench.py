@@ -32,11 +32,11 @@ import time
 METRIC = "exact fermion-weight evals/sec + effective indep. samples/sec vs FP64 DQMC"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (and matrix) peak
 COPY_CALIBRATION_BYTES = 1 << 30
-# HBM bytes per k_kron launch (batch 512, 8 vectors per workgroup), averaged
+# HBM bytes per k_kron launch (batch 512, 16 vectors per workgroup), averaged
 # over the 8 blocks of an evaluation (the first block starts from the identity
 # and reads no X): rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, each scaled by
 # what the same counter reads for the 1 GiB copy of --copy-calibration.
-KRON_TRAFFIC = {"batch": 512, "vectors_per_workgroup": 8, "bytes": 1.2475e9}
+KRON_TRAFFIC = {"batch": 512, "vectors_per_workgroup": 16, "bytes": 1.2474e9}
 
 
 def cpu_baseline(model, terms, theta, fields, logabs, signs, steps, seed):

@@ -122,7 +122,44 @@ __device__ __forceinline__ void line_product_sym(double* __restrict__ S, int bas
   }
 }
 
-template <int P, bool EXACT>
+// The same with compile-time strides (STRIDE between entries in S, DSTRIDE in
+// d_l): every LDS address is a per-thread base plus an instruction offset.
+template <int P, int STRIDE, int DSTRIDE>
+__device__ __forceinline__ void line_product_symc(double* __restrict__ S, int base, const double (&c)[P / 2 + 1],
+                                                  const double* __restrict__ dl, int dbase, int scale) {
+  double r[P];
+#pragma unroll
+  for (int x = 0; x < P; ++x) {
+    double v = S[base + x * STRIDE];
+    if (scale == 1) v *= dl[dbase + x * DSTRIDE];
+    r[x] = v;
+  }
+  constexpr int OB = P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1);
+#pragma unroll
+  for (int o0 = 0; o0 < P; o0 += OB) {
+    double acc[OB];
+#pragma unroll
+    for (int q = 0; q < OB; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int x = 0; x < P; ++x)
+#pragma unroll
+      for (int q = 0; q < OB; ++q) {
+        const int d = ((o0 + q - x) % P + P) % P;
+        acc[q] = fma(c[d <= P / 2 ? d : P - d], r[x], acc[q]);
+      }
+#pragma unroll
+    for (int q = 0; q < OB; ++q) {
+      double v = acc[q];
+      if (scale == 2) v *= dl[dbase + (o0 + q) * DSTRIDE];
+      S[base + (o0 + q) * STRIDE] = v;
+    }
+  }
+}
+
+// NBT > 0: NBT vectors per workgroup and an exact P x P lattice, fixed at
+// compile time, so that every LDS address of the line products is a base
+// plus an instruction offset; NBT = 0: from the arguments.
+template <int P, bool EXACT, int NBT>
 __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
   extern __shared__ double S[];  // [N][nb], then d_l [2][N] (alternating slices)
   // XCD-aware order: the hardware deals workgroups to the 8 XCDs in turn, so
@@ -133,7 +170,9 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
   const int lin = (g & ~15) | ((g & 7) << 1) | ((g >> 3) & 1);
   if (lin >= a.nvb * a.batch) return;
   const int b = lin / a.nvb;
-  const int lg = a.lognb, nb = 1 << lg, N = a.N, lx = a.lx, ly = a.ly;
+  const int lg = NBT ? __builtin_ctz(NBT) : a.lognb, nb = NBT ? NBT : 1 << lg, N = a.N, lx = a.lx, ly = a.ly;
+  constexpr int ROWS = P * NBT;  // NBT > 0: stride of lattice rows in S
+  const int nS = N * nb;         // doubles of the vector block
   const int v0 = (lin % a.nvb) * nb;
   const int nv = min(nb, N - v0);
   const int tid = threadIdx.x, nt = blockDim.x;  // nt is a multiple of 64, nb <= 32
@@ -169,13 +208,24 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
     int sl = (a.slice0 + k * a.step) % a.L;
     if (sl < 0) sl += a.L;
     // a second buffer: threads still in the y-lines of slice k - 1 may read the first
-    double* dl = S + (long)N * nb + (k & 1) * N;
+    double* dl = S + nS + (k & 1) * N;
     if (a.scale) {
       const int8_t* __restrict__ f = a.s + (long)b * a.strideS + (long)sl * N;
       for (int i = tid; i < N; i += nt) dl[i] = f[i] > 0 ? dpos : dneg;
     }
     __syncthreads();
-    if constexpr (EXACT && P <= 32) {
+    if constexpr (NBT > 0) {
+      static_assert(EXACT && P <= 32, "compile-time blocks need an exact lattice of side <= 32");
+      if (tid < P * NBT) {  // x-lines
+        const int y = tid / NBT, c = tid % NBT;
+        line_product_symc<P, NBT, 1>(S, y * ROWS + c, cx, dl, y * P, a.scale == 1 ? 1 : 0);
+      }
+      __syncthreads();
+      if (tid < P * NBT) {  // y-lines
+        const int x = tid / NBT, c = tid % NBT;
+        line_product_symc<P, ROWS, P>(S, x * NBT + c, cy, dl, x, a.scale == 2 ? 2 : 0);
+      }
+    } else if constexpr (EXACT && P <= 32) {
       if (tid < ly * nb) {  // x-lines: entries y lx + x, x = 0..lx-1
         const int y = tid >> lg, c = tid & (nb - 1);
         line_product_sym<P>(S, y * lx * nb + c, nb, cx, dl, y * lx, 1, a.scale == 1 ? 1 : 0);
@@ -212,7 +262,7 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1)
         if (o >= nb) ss += __shfl_xor(ss, o, 64);
-      double* part = S + (long)N * (nb + 2);  // [waves][nb]
+      double* part = S + nS + 2 * N;  // [waves][nb]
       if ((tid & 63) < nb) part[(tid >> 6) * nb + (tid & 63)] = ss;
       __syncthreads();
       if (tid < nv) {
@@ -252,6 +302,9 @@ static size_t kron_lds(int N, int nb, int m) {
   const int waves = (m * nb + 63) / 64;
   return ((size_t)N * (nb + 2) + (size_t)waves * nb) * sizeof(double);
 }
+static bool kron_fixed(const Plan& p, int nb) {
+  return p.m.lx == p.kron_P && p.m.ly == p.kron_P && p.kron_P <= 32 && (nb == 8 || nb == 16);
+}
 
 int kron_default_nb(const Plan& p) {
   const int m = std::max(p.m.lx, p.m.ly);
@@ -261,13 +314,26 @@ int kron_default_nb(const Plan& p) {
 }
 
 template <int P>
-static void launch_p(const KronDev& d, bool exact, dim3 grid, int threads, size_t lds, hipStream_t st) {
+static void launch_p(const KronDev& d, bool exact, int nb, bool fixed, dim3 grid, int threads, size_t lds,
+                     hipStream_t st) {
+  if constexpr (P <= 32) {
+    if (fixed && nb == 8) {
+      allow_max_lds((const void*)k_kron<P, true, 8>);
+      k_kron<P, true, 8><<<grid, threads, lds, st>>>(d);
+      return;
+    }
+    if (fixed && nb == 16) {
+      allow_max_lds((const void*)k_kron<P, true, 16>);
+      k_kron<P, true, 16><<<grid, threads, lds, st>>>(d);
+      return;
+    }
+  }
   if (exact) {
-    allow_max_lds((const void*)k_kron<P, true>);
-    k_kron<P, true><<<grid, threads, lds, st>>>(d);
+    allow_max_lds((const void*)k_kron<P, true, 0>);
+    k_kron<P, true, 0><<<grid, threads, lds, st>>>(d);
   } else {
-    allow_max_lds((const void*)k_kron<P, false>);
-    k_kron<P, false><<<grid, threads, lds, st>>>(d);
+    allow_max_lds((const void*)k_kron<P, false, 0>);
+    k_kron<P, false, 0><<<grid, threads, lds, st>>>(d);
   }
 }
 
@@ -279,6 +345,7 @@ int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
   }
   const int nb = a.nb > 0 ? a.nb : (p.kron_nb > 0 ? p.kron_nb : kron_default_nb(p));
   const int m = std::max(p.m.lx, p.m.ly);
+  const bool fixed = kron_fixed(p, nb);
   const size_t lds = kron_lds(p.n, nb, m);
   int lognb = 0;
   while ((1 << lognb) < nb) ++lognb;
@@ -315,16 +382,16 @@ int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
   d.batch = a.batch;
   dim3 grid((unsigned)(((long)d.nvb * a.batch + 15) / 16 * 16));
   switch (P) {
-    case 4: launch_p<4>(d, exact, grid, threads, lds, st); break;
-    case 8: launch_p<8>(d, exact, grid, threads, lds, st); break;
-    case 12: launch_p<12>(d, exact, grid, threads, lds, st); break;
-    case 16: launch_p<16>(d, exact, grid, threads, lds, st); break;
-    case 20: launch_p<20>(d, exact, grid, threads, lds, st); break;
-    case 24: launch_p<24>(d, exact, grid, threads, lds, st); break;
-    case 32: launch_p<32>(d, exact, grid, threads, lds, st); break;
-    case 40: launch_p<40>(d, exact, grid, threads, lds, st); break;
-    case 48: launch_p<48>(d, exact, grid, threads, lds, st); break;
-    default: launch_p<64>(d, exact, grid, threads, lds, st); break;
+    case 4: launch_p<4>(d, exact, nb, fixed, grid, threads, lds, st); break;
+    case 8: launch_p<8>(d, exact, nb, fixed, grid, threads, lds, st); break;
+    case 12: launch_p<12>(d, exact, nb, fixed, grid, threads, lds, st); break;
+    case 16: launch_p<16>(d, exact, nb, fixed, grid, threads, lds, st); break;
+    case 20: launch_p<20>(d, exact, nb, fixed, grid, threads, lds, st); break;
+    case 24: launch_p<24>(d, exact, nb, fixed, grid, threads, lds, st); break;
+    case 32: launch_p<32>(d, exact, nb, fixed, grid, threads, lds, st); break;
+    case 40: launch_p<40>(d, exact, nb, fixed, grid, threads, lds, st); break;
+    case 48: launch_p<48>(d, exact, nb, fixed, grid, threads, lds, st); break;
+    default: launch_p<64>(d, exact, nb, fixed, grid, threads, lds, st); break;
   }
   SLQ_LAUNCHED();
   return SLQ_OK;
