@@ -38,8 +38,15 @@ struct Group {
   void* dmem = nullptr;
   hipStream_t gs = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // the sub-batches are dealt to up to kLanes streams (largest estimated work
+  // first, each to the least loaded lane); every lane records its own graph,
+  // and the lanes run side by side
+  static constexpr int kLanes = 4;
+  std::vector<std::vector<int>> lane_subs;
+  std::vector<hipStream_t> lane_st;
+  std::vector<hipEvent_t> lane_ev;
+  std::vector<hipGraph_t> lane_graph;
+  std::vector<hipGraphExec_t> lane_exec;
   const void* key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -157,9 +164,10 @@ static int autotune(Group& g, SubPlan& sp) {
   return SLQ_OK;
 }
 
-static int enqueue(Group& g, const int8_t* d_s, double* d_G, double* d_logabs, int8_t* d_sign, int32_t* d_status) {
-  hipStream_t st = g.gs;
-  for (SubPlan& sp : g.subs) {
+static int enqueue(Group& g, int lane, hipStream_t st, const int8_t* d_s, double* d_G, double* d_logabs,
+                   int8_t* d_sign, int32_t* d_status) {
+  for (int q : g.lane_subs[lane]) {
+    SubPlan& sp = g.subs[q];
     Plan& p = sp.plan->p;
     const long per = (long)p.L * p.n;
     dim3 grid((unsigned)std::max<long>(1, std::min<long>((per + 255) / 256, 256)), sp.nb);
@@ -183,49 +191,65 @@ static int enqueue(Group& g, const int8_t* d_s, double* d_G, double* d_logabs, i
   return SLQ_OK;
 }
 
+static void drop_graphs(Group& g) {
+  for (size_t k = 0; k < g.lane_exec.size(); ++k) {
+    if (g.lane_exec[k]) hipGraphExecDestroy(g.lane_exec[k]);
+    if (g.lane_graph[k]) hipGraphDestroy(g.lane_graph[k]);
+    g.lane_exec[k] = nullptr;
+    g.lane_graph[k] = nullptr;
+  }
+}
+
 static int group_eval(Group& g, const int8_t* d_s, double* d_G, double* d_logabs, int8_t* d_sign, int32_t* d_status,
                       hipStream_t stream) {
   SLQ_HIP(hipSetDevice(g.device));
   SLQ_HIP(hipEventRecord(g.ev_in, stream));
-  SLQ_HIP(hipStreamWaitEvent(g.gs, g.ev_in, 0));
   const void* key[5] = {d_s, d_G, d_logabs, d_sign, d_status};
-  if (!g.exec || memcmp(key, g.key, sizeof(key)) != 0) {
-    if (g.exec) {
-      hipGraphExecDestroy(g.exec);
-      hipGraphDestroy(g.graph);
-      g.exec = nullptr;
-      g.graph = nullptr;
-    }
-    // one eager pass (sets kernel attributes), then record the graph
-    int rc = enqueue(g, d_s, d_G, d_logabs, d_sign, d_status);
-    if (rc != SLQ_OK) return rc;
-    SLQ_HIP(hipStreamBeginCapture(g.gs, hipStreamCaptureModeThreadLocal));
-    rc = enqueue(g, d_s, d_G, d_logabs, d_sign, d_status);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(g.gs, &graph);
-    if (rc != SLQ_OK) {
-      if (graph) hipGraphDestroy(graph);
-      return rc;
-    }
-    if (e != hipSuccess) {
-      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-      return SLQ_ERR_DEVICE;
-    }
-    g.graph = graph;
-    SLQ_HIP(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
-    memcpy(g.key, key, sizeof(key));
+  const bool record = !g.lane_exec[0] || memcmp(key, g.key, sizeof(key)) != 0;
+  if (record) {
+    drop_graphs(g);
+    memset(g.key, 0, sizeof(g.key));
   }
-  SLQ_HIP(hipGraphLaunch(g.exec, g.gs));
-  SLQ_HIP(hipEventRecord(g.ev_out, g.gs));
-  SLQ_HIP(hipStreamWaitEvent(stream, g.ev_out, 0));
+  for (size_t k = 0; k < g.lane_st.size(); ++k) {
+    hipStream_t ls = g.lane_st[k];
+    SLQ_HIP(hipStreamWaitEvent(ls, g.ev_in, 0));
+    if (record) {
+      // one eager pass (sets kernel attributes), then record the lane's graph
+      int rc = enqueue(g, (int)k, ls, d_s, d_G, d_logabs, d_sign, d_status);
+      if (rc != SLQ_OK) return rc;
+      SLQ_HIP(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
+      rc = enqueue(g, (int)k, ls, d_s, d_G, d_logabs, d_sign, d_status);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(ls, &graph);
+      if (rc != SLQ_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+      }
+      if (e != hipSuccess) {
+        set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        return SLQ_ERR_DEVICE;
+      }
+      g.lane_graph[k] = graph;
+      SLQ_HIP(hipGraphInstantiate(&g.lane_exec[k], graph, nullptr, nullptr, 0));
+    }
+    SLQ_HIP(hipGraphLaunch(g.lane_exec[k], ls));
+    SLQ_HIP(hipEventRecord(g.lane_ev[k], ls));
+    SLQ_HIP(hipStreamWaitEvent(stream, g.lane_ev[k], 0));
+  }
+  if (record) memcpy(g.key, key, sizeof(key));
   return SLQ_OK;
 }
 
 static void release(Group& g) {
   hipSetDevice(g.device);
   if (g.gs) hipStreamSynchronize(g.gs);
-  if (g.exec) hipGraphExecDestroy(g.exec);
-  if (g.graph) hipGraphDestroy(g.graph);
+  for (hipStream_t ls : g.lane_st)
+    if (ls) hipStreamSynchronize(ls);
+  drop_graphs(g);
+  for (hipEvent_t e : g.lane_ev)
+    if (e) hipEventDestroy(e);
+  for (hipStream_t ls : g.lane_st)
+    if (ls) hipStreamDestroy(ls);
   for (SubPlan& sp : g.subs) slq_plan_destroy(sp.plan);
   if (g.dmem) hipFree(g.dmem);
   if (g.ev_in) hipEventDestroy(g.ev_in);
@@ -330,6 +354,35 @@ int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out)
     set_error("stream/event creation failed");
     rc = SLQ_ERR_DEVICE;
   }
+  if (rc == SLQ_OK) {  // lanes: estimated work per sub-batch ~ fields x (stabilisations N^3 + products N^2 (lx+ly) L)
+    const int nl = std::min<int>(Group::kLanes, (int)g.subs.size());
+    std::vector<double> work(g.subs.size()), load(nl, 0.0);
+    std::vector<int> order(g.subs.size());
+    for (size_t q = 0; q < g.subs.size(); ++q) {
+      const slq_model& m = g.subs[q].plan->p.m;
+      const double N = (double)m.lx * m.ly;
+      const double nst = (double)((m.n_slices + m.n_stab - 1) / m.n_stab);
+      work[q] = g.subs[q].nb * (nst * N * N * N + N * N * (m.lx + m.ly) * m.n_slices);
+      order[q] = (int)q;
+    }
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    g.lane_subs.assign(nl, {});
+    for (int q : order) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      g.lane_subs[k].push_back(q);
+      load[k] += work[q];
+    }
+    g.lane_st.assign(nl, nullptr);
+    g.lane_ev.assign(nl, nullptr);
+    g.lane_graph.assign(nl, nullptr);
+    g.lane_exec.assign(nl, nullptr);
+    for (int k = 0; k < nl && rc == SLQ_OK; ++k)
+      if (hipStreamCreateWithFlags(&g.lane_st[k], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&g.lane_ev[k], hipEventDisableTiming) != hipSuccess) {
+        set_error("stream/event creation failed");
+        rc = SLQ_ERR_DEVICE;
+      }
+  }
   // autotune the chain product once per lattice, on the largest batch of that
   // lattice, and share the choice with its other sub-plans
   auto same_lattice = [&](size_t r, size_t q) {
@@ -389,6 +442,12 @@ int slq_group_describe(const slq_group* grp, char* buf, size_t len) {
     const Plan& p = g.subs[q].plan->p;
     s += (q ? ", " : "") + std::string("{\"N\": ") + std::to_string(p.n) + ", \"L\": " + std::to_string(p.L) +
          ", \"chains\": " + std::to_string(g.subs[q].nb) + "}";
+  }
+  s += "], \"lanes\": [";
+  for (size_t k = 0; k < g.lane_subs.size(); ++k) {
+    s += k ? ", [" : "[";
+    for (size_t i = 0; i < g.lane_subs[k].size(); ++i) s += (i ? ", " : "") + std::to_string(g.lane_subs[k][i]);
+    s += "]";
   }
   s += "], \"tuned\": [";
   for (size_t q = 0; q < g.tuned_n.size(); ++q) {
