@@ -182,6 +182,45 @@ def local_sweep_rate(slq, plan, model, sweeps, seed):
             "max_drift": float(drift.max().item())}
 
 
+PRECISION_PEAK_TFLOPS = {0: 78.6, 3: 78.6, 1: 157.3, 2: 2500.0}  # FP64 vector / FP64, FP32, BF16 dense MFMA
+
+
+def precision_rates(slq, fields: int = 32):
+    """Chain products of the 40x40, L=100 model (dtau 0.1, xi 1.5, n_s 10) in
+    each precision mode: exact weights per second of `fields` fields and the
+    chain kernels' throughput against their own peak (structured FP64 on the
+    vector ALUs; dense FP64, FP32 and BF16 products on the matrix cores, FP32
+    accumulation for the last two)."""
+    import torch
+    from slq_inputs import MIXED_40x40, iid_fields
+    dev = torch.device("cuda")
+    model = MIXED_40x40
+    s = torch.from_numpy(iid_fields(model, fields, 4000)).to(dev)
+    out = {}
+    names = {0: "fp64_structured", 3: "fp64_dense", 1: "fp32", 2: "bf16"}
+    for prec in (0, 3, 1, 2):
+        plan = slq.Plan(model, fields, chain_prec=prec)
+        la = torch.empty(fields, dtype=torch.float64, device=dev)
+        sg = torch.empty(fields, dtype=torch.int8, device=dev)
+        st = torch.empty(fields, dtype=torch.int32, device=dev)
+        slq.slq_weight(plan, s, la, sg, st)
+        torch.cuda.synchronize()
+        slq.slq_profile_enable(plan, True)
+        t0 = time.perf_counter()
+        slq.slq_weight(plan, s, la, sg, st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms, launches, flops = slq.slq_profile_read(plan)
+        slq.slq_profile_enable(plan, False)
+        tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        out[names[prec]] = {"evals_per_s": fields / dt, "chain_tflops": tf,
+                            "chain_peak_tflops": PRECISION_PEAK_TFLOPS[prec],
+                            "chain_frac": tf / PRECISION_PEAK_TFLOPS[prec], "chain_launches": launches}
+        plan.close()
+        torch.cuda.empty_cache()
+    return {"model": "40x40, L=100", "fields": fields, **out}
+
+
 def group_rate(slq, dev, reps: int = 5):
     """Exact weights of 64 chains of uneven size (Lx = Ly in {8..24}, L in
     {40..100}) per second, one graph launch per evaluation."""
@@ -351,6 +390,7 @@ def main():
         details["dqmc_local_acceptance"] = float(acc.sum().item()) / (nb * model.n_sites * model.n_slices)
         details["dqmc_max_drift"] = float(drift.max().item())
         details["group_64_uneven"] = group_rate(slq, dev)
+        details["precision_40x40"] = precision_rates(slq)
     if args.ess:
         details["ess"] = ess_rates(slq, plan, model, terms, seed, args.ess_steps, args.ess_dqmc_chains or B,
                                    args.ess_sweeps, args.ess_burn)

@@ -133,6 +133,13 @@ static int timed_chain_kron(Plan& p, const KronArgs& k, hipStream_t st) {
   return timed_chain(p, flops, st, [&]() { return launch_kron(p, k, st); });
 }
 
+static int timed_chain_bf16t(Plan& p, int batch, const void* BT, void* out, int out_f64, const int8_t* s,
+                             long strideS, int slice_next, hipStream_t st) {
+  return timed_chain(p, 2.0 * (double)p.n * p.n * p.n * batch, st, [&]() {
+    return launch_bf16t_product(p, batch, BT, out, out_f64, s, strideS, slice_next, st);
+  });
+}
+
 static int timed_chain_lp(Plan& p, const LpArgs& g, bool b_is_f64, hipStream_t st) {
   return timed_chain(p, 2.0 * (double)g.M * g.N * g.K * g.batch, st,
                      [&]() { return launch_gemm_lp(g, p.m.chain_prec, b_is_f64, st); });
@@ -217,6 +224,19 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
         g.slice = (slice0 + j) % L;
         SLQ_TRY(timed_chain_gemm(p, g, st));
         std::swap(cur, oth);
+      }
+    } else if (p.m.chain_prec == SLQ_PREC_BF16 && N % 8 == 0) {
+      // BF16 operands, the chain kept as bf16 Y^T = (d_next X)^T between the
+      // slices of the block (two buffers in Xb), X in FP64 after the last one
+      char* bt0 = (char*)p.Xb;
+      char* bt1 = bt0 + 2 * NN * batch;
+      SLQ_TRY(launch_bt_prepare(N, batch, j0 == 0 ? nullptr : p.U, NN, s, strideS, (slice0 + j0) % L, p.consts,
+                                bt0, st));
+      for (int j = j0; j < jend; ++j) {
+        const bool last = j + 1 == jend;
+        SLQ_TRY(timed_chain_bf16t(p, batch, bt0, last ? (void*)cur : (void*)bt1, last ? 1 : 0, s, strideS,
+                                  (slice0 + j + 1) % L, st));
+        std::swap(bt0, bt1);
       }
     } else {
       // FP32 / BF16 operands, X kept in FP32 (the FP64 buffers hold it), widened before the QR
@@ -304,7 +324,7 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
     off += (bytes + 255) / 256 * 256;
     return o;
   };
-  const size_t oE32 = take(4 * NN);
+  const size_t oE32 = take(4 * NN), oE16 = take(2 * NN);
   const size_t oE = take(8 * NN), oEi = take(8 * NN), oTab = take(8 * (2 * (model->lx + model->ly) + 8)),
                oC = take(8 * 8);
   const size_t oXa = take(8 * NN * B), oXb = take(8 * NN * B), oW = take(8 * NN * B), oU = take(8 * NN * B),
@@ -328,6 +348,7 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   p.Einv = (double*)(c + oEi);
   p.tabs = (double*)(c + oTab);
   p.E32 = (float*)(c + oE32);
+  p.E16 = (void*)(c + oE16);
   p.consts = (double*)(c + oC);
   p.Xa = (double*)(c + oXa);
   p.Xb = (double*)(c + oXb);
@@ -359,6 +380,7 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   if (rc == SLQ_OK) rc = launch_kron_windows(p, 0);
 
   if (rc == SLQ_OK) rc = launch_narrow(p.E, p.E32, NN, 0);
+  if (rc == SLQ_OK) rc = launch_to_bf16(p.E32, p.E16, NN, 0);
   if (rc == SLQ_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(SLQ_ERR_DEVICE, "kinetic build failed");
   if (rc != SLQ_OK) {
     hipFree(base);

@@ -185,6 +185,7 @@ struct Plan {
   double* consts; // [0] exp(-dtau xi), [1] exp(+dtau xi), [2] exp(dtau mu), [3] exp(-dtau mu)
   double* tabs;   // 1-D propagator tables, 4*(lx+ly)
   float* E32;     // [N][N] E in FP32 (reduced-precision chains)
+  void* E16;      // [N][N] bf16(E32)
   // per-item N x N buffers
   double *Xa, *Xb, *W, *U, *V, *Vt;
   // per-item vectors
@@ -365,6 +366,13 @@ int launch_gemm_lp(const LpArgs& a, int prec, bool b_is_f64, hipStream_t st);
 int launch_first_slice_f32(Plan& p, int batch, const int8_t* s, long strideS, int slice, float* X, hipStream_t st);
 int launch_widen(const float* a, double* b, long n, hipStream_t st);
 int launch_narrow(const double* a, float* b, long n, hipStream_t st);
+// BF16 chain with k-contiguous operands (N % 8 == 0), see gemm_lp.hip
+struct LpTArgs;
+int launch_bf16t_product(Plan& p, int batch, const void* BT, void* out, int out_f64, const int8_t* s, long strideS,
+                         int slice_next, hipStream_t st);
+int launch_bt_prepare(int N, int batch, const double* X, long strideX, const int8_t* S, long strideS, int slice,
+                      const double* consts, void* BT, hipStream_t st);
+int launch_to_bf16(const float* a, void* b, long n, hipStream_t st);
 
 // Structured slice products X <- B X for a block of slices (see kron.hip).
 struct KronArgs {
