@@ -133,10 +133,12 @@ static int timed_chain_kron(Plan& p, const KronArgs& k, hipStream_t st) {
   return timed_chain(p, flops, st, [&]() { return launch_kron(p, k, st); });
 }
 
-static int timed_chain_bf16t(Plan& p, int batch, const void* BT, void* out, int out_f64, const int8_t* s,
-                             long strideS, int slice_next, hipStream_t st) {
+static int timed_chain_lpt(Plan& p, int batch, const void* BT, void* out, int out_f64, const int8_t* s,
+                           long strideS, int slice_next, hipStream_t st) {
   return timed_chain(p, 2.0 * (double)p.n * p.n * p.n * batch, st, [&]() {
-    return launch_bf16t_product(p, batch, BT, out, out_f64, s, strideS, slice_next, st);
+    return p.m.chain_prec == SLQ_PREC_BF16
+               ? launch_bf16t_product(p, batch, BT, out, out_f64, s, strideS, slice_next, st)
+               : launch_f32t_product(p, batch, BT, out, out_f64, s, strideS, slice_next, st);
   });
 }
 
@@ -225,17 +227,19 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
         SLQ_TRY(timed_chain_gemm(p, g, st));
         std::swap(cur, oth);
       }
-    } else if (p.m.chain_prec == SLQ_PREC_BF16 && N % 8 == 0) {
-      // BF16 operands, the chain kept as bf16 Y^T = (d_next X)^T between the
-      // slices of the block (two buffers in Xb), X in FP64 after the last one
+    } else if (lp && N % 8 == 0) {
+      // BF16 or FP32 operands, the chain kept as Y^T = (d_next X)^T in the
+      // operand type between the slices of the block (two buffers in Xb), X
+      // in FP64 after the last one
+      const long esz = p.m.chain_prec == SLQ_PREC_BF16 ? 2 : 4;
       char* bt0 = (char*)p.Xb;
-      char* bt1 = bt0 + 2 * NN * batch;
+      char* bt1 = bt0 + esz * NN * batch;
       SLQ_TRY(launch_bt_prepare(N, batch, j0 == 0 ? nullptr : p.U, NN, s, strideS, (slice0 + j0) % L, p.consts,
-                                bt0, st));
+                                bt0, p.m.chain_prec, st));
       for (int j = j0; j < jend; ++j) {
         const bool last = j + 1 == jend;
-        SLQ_TRY(timed_chain_bf16t(p, batch, bt0, last ? (void*)cur : (void*)bt1, last ? 1 : 0, s, strideS,
-                                  (slice0 + j + 1) % L, st));
+        SLQ_TRY(timed_chain_lpt(p, batch, bt0, last ? (void*)cur : (void*)bt1, last ? 1 : 0, s, strideS,
+                                (slice0 + j + 1) % L, st));
         std::swap(bt0, bt1);
       }
     } else {

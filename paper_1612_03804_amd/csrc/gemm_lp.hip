@@ -456,11 +456,13 @@ int launch_gemm_bf16t(const LpTArgs& a, int out, hipStream_t st) {
   return SLQ_OK;
 }
 
-// BT[b][n][k] = bf16(d[k] X[b][k][n]) (X FP64 row-major), or bf16(d[k]) on the
-// diagonal when X is null (the identity); 32 x 32 tiles through LDS.
+// BT[b][n][k] = T(d[k] X[b][k][n]) (X FP64 row-major, the product formed in
+// FP32), or T(d[k]) on the diagonal when X is null (the identity); 32 x 32
+// tiles through LDS.
+template <typename T>
 __global__ __launch_bounds__(256) void k_bt_prepare(int N, const double* __restrict__ X, long strideX,
                                                     const int8_t* __restrict__ S, long strideS, int slice,
-                                                    const double* __restrict__ consts, __bf16* __restrict__ BT) {
+                                                    const double* __restrict__ consts, T* __restrict__ BT) {
   __shared__ float t[32][33];
   const int b = blockIdx.z, k0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
@@ -478,14 +480,178 @@ __global__ __launch_bounds__(256) void k_bt_prepare(int N, const double* __restr
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {  // rows n, columns k
     const int n = n0 + r, k = k0 + tx;
-    if (n < N && k < N) BT[(long)b * N * N + (long)n * N + k] = (__bf16)t[tx][r];
+    if (n < N && k < N) BT[(long)b * N * N + (long)n * N + k] = (T)t[tx][r];
   }
 }
 
 int launch_bt_prepare(int N, int batch, const double* X, long strideX, const int8_t* S, long strideS, int slice,
-                      const double* consts, void* BT, hipStream_t st) {
+                      const double* consts, void* BT, int prec, hipStream_t st) {
   dim3 grid((unsigned)((N + 31) / 32), (unsigned)((N + 31) / 32), (unsigned)batch);
-  k_bt_prepare<<<grid, 256, 0, st>>>(N, X, strideX, S, strideS, slice, consts, (__bf16*)BT);
+  if (prec == SLQ_PREC_BF16)
+    k_bt_prepare<__bf16><<<grid, 256, 0, st>>>(N, X, strideX, S, strideS, slice, consts, (__bf16*)BT);
+  else
+    k_bt_prepare<float><<<grid, 256, 0, st>>>(N, X, strideX, S, strideS, slice, consts, (float*)BT);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+
+// The FP32 chain with k-contiguous operands: the same scheme with FP32 storage
+// (Y^T = (d_next X)^T in FP32, E32), v_mfma_f32_16x16x4_f32, 16-byte loads of
+// four k; LDS rows of 20 floats keep the 16 rows a wave reads on distinct banks.
+template <int WM, int WN, int GM, int GN, int OUT>
+__global__ __launch_bounds__(64 * GM * GN) void k_gemm_f32t(LpTArgs g, const float* __restrict__ A,
+                                                            const float* __restrict__ BTall, int ntm, int ntn) {
+  constexpr int TK = 16, KP = TK + 4;
+  constexpr int TM = 16 * WM * GM, TN = 16 * WN * GN, NT = 64 * GM * GN;
+  constexpr int AV = TM * TK / 4, BV = TN * TK / 4;  // 16-byte vectors per stage
+  constexpr int APT = (AV + NT - 1) / NT, BPT = (BV + NT - 1) / NT;
+  __shared__ __attribute__((aligned(16))) float As[2][TM][KP];
+  __shared__ __attribute__((aligned(16))) float Bs[2][TN][KP];
+  const int tpi = ntm * ntn, gid = blockIdx.x, x = gid % LP_NXCD, j = gid / LP_NXCD;
+  const int b = (j / tpi) * LP_NXCD + x;
+  if (b >= g.batch) return;
+  const int tile = j % tpi, tn = tile / ntm, tmi = tile % ntm;
+  const int m0 = tmi * TM, n0 = tn * TN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / GN) * WM * 16, wn0 = (wave % GN) * WN * 16;
+  const float* BT = BTall + (long)b * g.strideBT;
+  f4_t acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int jj = 0; jj < WN; ++jj) acc[i][jj] = f4_t{0.f, 0.f, 0.f, 0.f};
+  f4_t ra[APT], rb[BPT];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < APT; ++t) {
+      const int v = tid + t * NT;
+      f4_t w = f4_t{0.f, 0.f, 0.f, 0.f};
+      if (v < AV) {
+        const int mm = v / (TK / 4), kq = v % (TK / 4), gm = m0 + mm, gk = k0 + 4 * kq;
+        if (gm < g.M && gk < g.K) w = *(const f4_t*)(A + (long)gm * g.lda + gk);
+      }
+      ra[t] = w;
+    }
+#pragma unroll
+    for (int t = 0; t < BPT; ++t) {
+      const int v = tid + t * NT;
+      f4_t w = f4_t{0.f, 0.f, 0.f, 0.f};
+      if (v < BV) {
+        const int nn = v / (TK / 4), kq = v % (TK / 4), gn = n0 + nn, gk = k0 + 4 * kq;
+        if (gn < g.N && gk < g.K) w = *(const f4_t*)(BT + (long)gn * g.ldbt + gk);
+      }
+      rb[t] = w;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < APT; ++t) {
+      const int v = tid + t * NT;
+      if (v < AV) *(f4_t*)&As[buf][v / (TK / 4)][4 * (v % (TK / 4))] = ra[t];
+    }
+#pragma unroll
+    for (int t = 0; t < BPT; ++t) {
+      const int v = tid + t * NT;
+      if (v < BV) *(f4_t*)&Bs[buf][v / (TK / 4)][4 * (v % (TK / 4))] = rb[t];
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+    const bool more = k0 + TK < g.K;
+    if (more) load(k0 + TK);
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      float af[WM], bf[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) af[i] = As[cur][wm0 + i * 16 + (lane & 15)][kr];
+#pragma unroll
+      for (int jj = 0; jj < WN; ++jj) bf[jj] = Bs[cur][wn0 + jj * 16 + (lane & 15)][kr];
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < WN; ++jj)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[jj], acc[i][jj], 0, 0, 0);
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  if constexpr (OUT == 1) {
+    double* C = (double*)g.C + (long)b * g.strideC;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int jj = 0; jj < WN; ++jj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r, gn = n0 + wn0 + jj * 16 + (lane & 15);
+          if (gm < g.M && gn < g.N) C[(long)gm * g.ldc + gn] = (double)acc[i][jj][r];
+        }
+  } else {
+    float* C = (float*)g.C + (long)b * g.strideC;
+    const int8_t* S = g.S + (long)b * g.strideS + (long)g.slice_next * g.M;
+    const float rpos = (float)g.consts[0], rneg = (float)g.consts[1];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int jj = 0; jj < WN; ++jj) {
+        const int gm = m0 + wm0 + i * 16 + 4 * (lane >> 4), gn = n0 + wn0 + jj * 16 + (lane & 15);
+        if (gm < g.M && gn < g.N) {  // M % 4 == 0: the four rows gm..gm+3 are all inside
+          f4_t o;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) o[r] = acc[i][jj][r] * ((S[gm + r] > 0) ? rpos : rneg);
+          *(f4_t*)(C + (long)gn * g.ldc + gm) = o;
+        }
+      }
+  }
+}
+
+template <int WM, int WN, int GM, int GN>
+static void run_f32t(const LpTArgs& a, const float* A, const float* BT, int out, hipStream_t st) {
+  constexpr int TM = 16 * WM * GM, TN = 16 * WN * GN;
+  const int ntm = (a.M + TM - 1) / TM, ntn = (a.N + TN - 1) / TN;
+  const long groups = ((long)a.batch + LP_NXCD - 1) / LP_NXCD * LP_NXCD * ntm * ntn;
+  dim3 grid((unsigned)groups), block(64 * GM * GN);
+  if (out == 1)
+    k_gemm_f32t<WM, WN, GM, GN, 1><<<grid, block, 0, st>>>(a, A, BT, ntm, ntn);
+  else
+    k_gemm_f32t<WM, WN, GM, GN, 0><<<grid, block, 0, st>>>(a, A, BT, ntm, ntn);
+}
+
+int launch_f32t_product(Plan& p, int batch, const void* BT, void* out, int out_f64, const int8_t* s, long strideS,
+                        int slice_next, hipStream_t st) {
+  const int N = p.n;
+  const long NN = (long)N * N;
+  if (N % 8 != 0) {
+    set_error("the FP32 chain with k-contiguous operands needs N % 8 == 0");
+    return SLQ_ERR_ARG;
+  }
+  LpTArgs a{};
+  a.M = N;
+  a.N = N;
+  a.K = N;
+  a.lda = N;
+  a.ldbt = N;
+  a.strideBT = NN;
+  a.C = out;
+  a.ldc = N;
+  a.strideC = NN;
+  a.S = s;
+  a.strideS = strideS;
+  a.slice_next = slice_next;
+  a.consts = p.consts;
+  a.batch = batch;
+  if (batch <= 0) return SLQ_OK;
+  if (N % 160 == 0)
+    run_f32t<5, 5, 2, 2>(a, p.E32, (const float*)BT, out_f64, st);
+  else if (N <= 64)
+    run_f32t<2, 2, 2, 2>(a, p.E32, (const float*)BT, out_f64, st);
+  else
+    run_f32t<4, 4, 2, 2>(a, p.E32, (const float*)BT, out_f64, st);
   SLQ_LAUNCHED();
   return SLQ_OK;
 }

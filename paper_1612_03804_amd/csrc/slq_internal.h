@@ -370,8 +370,10 @@ int launch_narrow(const double* a, float* b, long n, hipStream_t st);
 struct LpTArgs;
 int launch_bf16t_product(Plan& p, int batch, const void* BT, void* out, int out_f64, const int8_t* s, long strideS,
                          int slice_next, hipStream_t st);
+int launch_f32t_product(Plan& p, int batch, const void* BT, void* out, int out_f64, const int8_t* s, long strideS,
+                        int slice_next, hipStream_t st);
 int launch_bt_prepare(int N, int batch, const double* X, long strideX, const int8_t* S, long strideS, int slice,
-                      const double* consts, void* BT, hipStream_t st);
+                      const double* consts, void* BT, int prec, hipStream_t st);
 int launch_to_bf16(const float* a, void* b, long n, hipStream_t st);
 
 // Structured slice products X <- B X for a block of slices (see kron.hip).
