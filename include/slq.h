@@ -114,6 +114,14 @@ int slq_plan_bytes(const slq_plan* plan, size_t* bytes);
  * run during stream capture.  Without it the plan uses a width fixed by the
  * LDS size. */
 int slq_plan_tune(slq_plan* plan, int32_t batch, int32_t* chosen, hipStream_t stream);
+/* slq_plan_set_block_width - fix the structured chain product's block width
+ * (vectors per workgroup, a power of two 1..32 whose workgroup fits the
+ * lattice: at most 1024 threads, 512 for sides above 24, and 160 KiB of LDS)
+ * instead of tuning it; 0 returns to the width fixed by the LDS size.  Host
+ * only, takes effect at the next call.  Results do not depend on the width
+ * beyond rounding order.  Errors: SLQ_ERR_ARG (NULL plan, a plan with dense
+ * products, an inadmissible width). */
+int slq_plan_set_block_width(slq_plan* plan, int32_t width);
 /* Copy E (or E^{-1} when inverse != 0) into caller memory d_out [N][N]. */
 int slq_kinetic(slq_plan* plan, int32_t inverse, double* d_out, hipStream_t stream);
 

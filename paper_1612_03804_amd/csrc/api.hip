@@ -457,6 +457,21 @@ int slq_plan_tune(slq_plan* plan, int32_t batch, int32_t* chosen, hipStream_t st
   return SLQ_OK;
 }
 
+int slq_plan_set_block_width(slq_plan* plan, int32_t width) {
+  if (!plan) return fail(SLQ_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  if (width == 0) {
+    p.kron_nb = 0;
+    return SLQ_OK;
+  }
+  if (p.m.chain_prec != SLQ_PREC_FP64 || p.kron_P == 0)
+    return fail(SLQ_ERR_ARG, "the plan has no structured chain product");
+  if (!kron_width_ok(p, width))
+    return fail(SLQ_ERR_ARG, "block width must be a power of two <= 32 whose workgroup fits the lattice");
+  p.kron_nb = width;
+  return SLQ_OK;
+}
+
 int slq_plan_bytes(const slq_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return fail(SLQ_ERR_ARG, "NULL argument");
   *bytes = plan->p.bytes;

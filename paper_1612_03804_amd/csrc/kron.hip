@@ -124,19 +124,33 @@ __device__ __forceinline__ void line_product_sym(double* __restrict__ S, int bas
 
 // The same with compile-time strides (STRIDE between entries in S, DSTRIDE in
 // d_l): every LDS address is a per-thread base plus an instruction offset.
-template <int P, int STRIDE, int DSTRIDE>
-__device__ __forceinline__ void line_product_symc(double* __restrict__ S, int base, const double (&c)[P / 2 + 1],
-                                                  const double* __restrict__ dl, int dbase, int scale) {
+// H lanes share a line: lane h of them computes the outputs o = H k + h.  It
+// reads the line rotated by h, r[x] = v[(x + h) mod P]; since the operator is
+// circulant, output H k + h of the line is output H k of the rotated one, so
+// all H lanes run the same instructions with the same coefficients.  The H
+// lanes sit side by side in one wavefront, whose reads of the line all
+// complete before its first write, so the in-place update needs no barrier.
+template <int P, int STRIDE, int DSTRIDE, int H, int SCALE>
+__device__ __forceinline__ void line_product_symc(double* __restrict__ S, int base, cdptr w,
+                                                  const double* __restrict__ dl, int dbase, int h) {
+  static_assert(P % H == 0, "the lanes of a line split its outputs evenly");
+  const int rb = base + h * STRIDE, rdb = dbase + h * DSTRIDE;
   double r[P];
 #pragma unroll
   for (int x = 0; x < P; ++x) {
-    double v = S[base + x * STRIDE];
-    if (scale == 1) v *= dl[dbase + x * DSTRIDE];
+    int o = rb + x * STRIDE, od = rdb + x * DSTRIDE;
+    if (x >= P - H + 1 && x + h >= P) {  // wraps round the periodic line
+      o -= P * STRIDE;
+      od -= P * DSTRIDE;
+    }
+    double v = S[o];
+    if constexpr (SCALE == 1) v *= dl[od];
     r[x] = v;
   }
-  constexpr int OB = P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1);
+  constexpr int PO = P / H;  // outputs per lane
+  constexpr int OB = PO % 4 == 0 ? 4 : (PO % 5 == 0 ? 5 : (PO % 3 == 0 ? 3 : (PO % 2 == 0 ? 2 : 1)));
 #pragma unroll
-  for (int o0 = 0; o0 < P; o0 += OB) {
+  for (int k0 = 0; k0 < PO; k0 += OB) {
     double acc[OB];
 #pragma unroll
     for (int q = 0; q < OB; ++q) acc[q] = 0.0;
@@ -144,120 +158,201 @@ __device__ __forceinline__ void line_product_symc(double* __restrict__ S, int ba
     for (int x = 0; x < P; ++x)
 #pragma unroll
       for (int q = 0; q < OB; ++q) {
-        const int d = ((o0 + q - x) % P + P) % P;
-        acc[q] = fma(c[d <= P / 2 ? d : P - d], r[x], acc[q]);
+        const int d = ((H * (k0 + q) - x) % P + P) % P;  // coefficient c[d] = w[P - 1 - d], c symmetric
+        acc[q] = fma(w[P - 1 - (d <= P / 2 ? d : P - d)], r[x], acc[q]);
       }
 #pragma unroll
     for (int q = 0; q < OB; ++q) {
       double v = acc[q];
-      if (scale == 2) v *= dl[dbase + (o0 + q) * DSTRIDE];
-      S[base + (o0 + q) * STRIDE] = v;
+      if constexpr (SCALE == 2) v *= dl[rdb + H * (k0 + q) * DSTRIDE];
+      S[rb + H * (k0 + q) * STRIDE] = v;
     }
   }
 }
 
+// Lanes per line of the compile-time path: two wherever the thread count allows
+constexpr int kron_lanes_per_line(int P, int nbt) { return 2 * P * nbt <= (P >= 32 ? 512 : 1024) ? 2 : 1; }
+// and its workgroup size
+constexpr int kron_fixed_threads(int P, int nbt) { return (P * nbt * kron_lanes_per_line(P, nbt) + 63) / 64 * 64; }
+
+// Workgroup-to-block order, XCD-aware: the hardware deals workgroups to the
+// 8 XCDs in turn, so hardware ids g and g + 8 run side by side on one XCD;
+// they take the vector blocks 2p and 2p + 1, which share every 128-byte line
+// of the field's rows in that XCD's L2 (each line is then fetched once, not
+// once per half).  A permutation within each aligned group of 16 ids.
+__device__ __forceinline__ int kron_item(int g) { return (g & ~15) | ((g & 7) << 1) | ((g >> 3) & 1); }
+
 // NBT > 0: NBT vectors per workgroup and an exact P x P lattice, fixed at
 // compile time, so that every LDS address of the line products is a base
-// plus an instruction offset; NBT = 0: from the arguments.
+// plus an instruction offset and every global load of a thread is in flight
+// before the first is waited for; NBT = 0: sizes from the arguments.
 template <int P, bool EXACT, int NBT>
 __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
   extern __shared__ double S[];  // [N][nb], then d_l [2][N] (alternating slices)
-  // XCD-aware order: the hardware deals workgroups to the 8 XCDs in turn, so
-  // hardware ids g and g + 8 run side by side on one XCD; they take the vector
-  // blocks 2p and 2p + 1, which share every 128-byte line of the field's rows
-  // in that XCD's L2 (each line is then fetched once, not once per half)
-  const int g = (int)blockIdx.x;
-  const int lin = (g & ~15) | ((g & 7) << 1) | ((g >> 3) & 1);
+  const int lin = kron_item((int)blockIdx.x);
   if (lin >= a.nvb * a.batch) return;
-  const int b = lin / a.nvb;
   const int lg = NBT ? __builtin_ctz(NBT) : a.lognb, nb = NBT ? NBT : 1 << lg, N = a.N, lx = a.lx, ly = a.ly;
   constexpr int ROWS = P * NBT;  // NBT > 0: stride of lattice rows in S
   const int nS = N * nb;         // doubles of the vector block
-  const int v0 = (lin % a.nvb) * nb;
-  const int nv = min(nb, N - v0);
   const int tid = threadIdx.x, nt = blockDim.x;  // nt is a multiple of 64, nb <= 32
-  const double* __restrict__ in = a.in ? a.in + (long)b * a.strideIn : nullptr;
+  const int c = tid & (nb - 1);  // the vector of this thread in loads and stores
   const double dpos = a.consts[a.inv ? 1 : 0], dneg = a.consts[a.inv ? 0 : 1];  // d for s = +1, -1
-  // distinct circulant values c[d] = w[P - 1 - d], d = 0..P/2 (exact lines only)
+  // distinct circulant values c[d] = w[P - 1 - d], d = 0..P/2 (exact lines only;
+  // the compile-time path reads them from the constant window as it goes)
   double cx[P / 2 + 1], cy[P / 2 + 1];
-  if constexpr (EXACT && P <= 32) {
+  if constexpr (NBT == 0 && EXACT && P <= 32) {
 #pragma unroll
     for (int d = 0; d <= P / 2; ++d) {
       cx[d] = ((cdptr)a.wx)[P - 1 - d];
       cy[d] = ((cdptr)a.wy)[P - 1 - d];
     }
   }
+  // NBT > 0: the thread count and N are compile-time; a thread holds rows
+  // (tid / NBT) + q RP, q < NP, of vector c of a block
+  constexpr int NTF = NBT ? kron_fixed_threads(P, NBT) : 64;
+  constexpr int RP = NBT ? NTF / NBT : 1, NP = NBT ? (P * P + RP - 1) / RP : 1;
+  double nxt[NP];  // the block's entries, loaded before the first is stored (NBT > 0)
+  auto fetch = [&]() {
+    const int b = lin / a.nvb, j = (lin % a.nvb) * nb + c;
+    const double* __restrict__ in = a.in ? a.in + (long)b * a.strideIn : nullptr;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int i = (tid >> lg) + q * RP;
+      nxt[q] = 0.0;
+      if (i < N && j < N) nxt[q] = in ? in[(long)i * N + j] : (i == j ? 1.0 : 0.0);
+    }
+  };
+  auto spins = [&](int k) {  // the field of the k-th slice of this launch
+    int sl = (a.slice0 + k * a.step) % a.L;
+    if (sl < 0) sl += a.L;
+    return a.s + (long)(lin / a.nvb) * a.strideS + (long)sl * N;
+  };
+  // NBT > 0: the next slice's spins are loaded one slice ahead, in registers
+  constexpr int SPT = NBT ? (P * P + NTF - 1) / NTF : 1;
+  int8_t spn[SPT];
+  auto prefetch = [&](const int8_t* __restrict__ f) {
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int i = tid + q * NTF;
+      spn[q] = i < N ? f[i] : 1;
+    }
+  };
+  if constexpr (NBT > 0) {
+    if (!a.rows) fetch();
+    if (a.scale) prefetch(spins(0));
+  }
+  const int b = lin / a.nvb;
+  const int v0 = (lin % a.nvb) * nb;
+  const int nv = min(nb, N - v0);
   if (!a.rows) {
-    const int c = tid & (nb - 1), j = v0 + c;
-    for (int i = tid >> lg; i < N; i += nt >> lg) {
-      double v = 0.0;
-      if (c < nv) v = in ? in[(long)i * N + j] : (i == j ? 1.0 : 0.0);
-      S[i * nb + c] = v;
+    if constexpr (NBT > 0) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const int i = (tid >> lg) + q * RP;
+        if (i < N) S[i * nb + c] = nxt[q];
+      }
+    } else {
+      const double* __restrict__ in = a.in ? a.in + (long)b * a.strideIn : nullptr;
+      const int j = v0 + c;
+      for (int i = tid >> lg; i < N; i += nt >> lg) {
+        double v = 0.0;
+        if (c < nv) v = in ? in[(long)i * N + j] : (i == j ? 1.0 : 0.0);
+        S[i * nb + c] = v;
+      }
     }
   } else {
-    for (int c = 0; c < nb; ++c) {
-      const int j = v0 + c;
+    const double* __restrict__ in = a.in ? a.in + (long)b * a.strideIn : nullptr;
+    for (int cc = 0; cc < nb; ++cc) {
+      const int j = v0 + cc;
       for (int i = tid; i < N; i += nt) {
         double v = 0.0;
-        if (c < nv) v = in ? in[(long)j * N + i] : (i == j ? 1.0 : 0.0);
-        S[i * nb + c] = v;
+        if (cc < nv) v = in ? in[(long)j * N + i] : (i == j ? 1.0 : 0.0);
+        S[i * nb + cc] = v;
       }
     }
   }
   for (int k = 0; k < a.count; ++k) {
-    int sl = (a.slice0 + k * a.step) % a.L;
-    if (sl < 0) sl += a.L;
     // a second buffer: threads still in the y-lines of slice k - 1 may read the first
     double* dl = S + nS + (k & 1) * N;
     if (a.scale) {
-      const int8_t* __restrict__ f = a.s + (long)b * a.strideS + (long)sl * N;
-      for (int i = tid; i < N; i += nt) dl[i] = f[i] > 0 ? dpos : dneg;
+      if constexpr (NBT > 0) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+          const int i = tid + q * NTF;
+          if (i < N) dl[i] = spn[q] > 0 ? dpos : dneg;
+        }
+        if (k + 1 < a.count) prefetch(spins(k + 1));
+      } else {
+        const int8_t* __restrict__ f = spins(k);
+        for (int i = tid; i < N; i += nt) dl[i] = f[i] > 0 ? dpos : dneg;
+      }
     }
     __syncthreads();
     if constexpr (NBT > 0) {
       static_assert(EXACT && P <= 32, "compile-time blocks need an exact lattice of side <= 32");
-      if (tid < P * NBT) {  // x-lines
-        const int y = tid / NBT, c = tid % NBT;
-        line_product_symc<P, NBT, 1>(S, y * ROWS + c, cx, dl, y * P, a.scale == 1 ? 1 : 0);
+      constexpr int H = kron_lanes_per_line(P, NBT);
+      const int t = tid / H, h = tid % H;
+      if (t < P * NBT) {  // x-lines
+        const int y = t / NBT, cl = t % NBT;
+        if (a.scale == 1)
+          line_product_symc<P, NBT, 1, H, 1>(S, y * ROWS + cl, (cdptr)a.wx, dl, y * P, h);
+        else
+          line_product_symc<P, NBT, 1, H, 0>(S, y * ROWS + cl, (cdptr)a.wx, dl, y * P, h);
       }
       __syncthreads();
-      if (tid < P * NBT) {  // y-lines
-        const int x = tid / NBT, c = tid % NBT;
-        line_product_symc<P, ROWS, P>(S, x * NBT + c, cy, dl, x, a.scale == 2 ? 2 : 0);
+      if (t < P * NBT) {  // y-lines
+        const int x = t / NBT, cl = t % NBT;
+        if (a.scale == 2)
+          line_product_symc<P, ROWS, P, H, 2>(S, x * NBT + cl, (cdptr)a.wy, dl, x, h);
+        else
+          line_product_symc<P, ROWS, P, H, 0>(S, x * NBT + cl, (cdptr)a.wy, dl, x, h);
       }
     } else if constexpr (EXACT && P <= 32) {
       if (tid < ly * nb) {  // x-lines: entries y lx + x, x = 0..lx-1
-        const int y = tid >> lg, c = tid & (nb - 1);
-        line_product_sym<P>(S, y * lx * nb + c, nb, cx, dl, y * lx, 1, a.scale == 1 ? 1 : 0);
+        const int y = tid >> lg, cl = tid & (nb - 1);
+        line_product_sym<P>(S, y * lx * nb + cl, nb, cx, dl, y * lx, 1, a.scale == 1 ? 1 : 0);
       }
       __syncthreads();
       if (tid < lx * nb) {  // y-lines: entries y lx + x, y = 0..ly-1
-        const int x = tid >> lg, c = tid & (nb - 1);
-        line_product_sym<P>(S, x * nb + c, lx * nb, cy, dl, x, lx, a.scale == 2 ? 2 : 0);
+        const int x = tid >> lg, cl = tid & (nb - 1);
+        line_product_sym<P>(S, x * nb + cl, lx * nb, cy, dl, x, lx, a.scale == 2 ? 2 : 0);
       }
     } else {
       if (tid < ly * nb) {  // x-lines: entries y lx + x, x = 0..lx-1
-        const int y = tid >> lg, c = tid & (nb - 1);
-        line_product<P, EXACT>(S, y * lx * nb + c, nb, lx, (cdptr)a.wx, dl, y * lx, 1, a.scale == 1 ? 1 : 0);
+        const int y = tid >> lg, cl = tid & (nb - 1);
+        line_product<P, EXACT>(S, y * lx * nb + cl, nb, lx, (cdptr)a.wx, dl, y * lx, 1, a.scale == 1 ? 1 : 0);
       }
       __syncthreads();
       if (tid < lx * nb) {  // y-lines: entries y lx + x, y = 0..ly-1
-        const int x = tid >> lg, c = tid & (nb - 1);
-        line_product<P, EXACT>(S, x * nb + c, lx * nb, ly, (cdptr)a.wy, dl, x, lx, a.scale == 2 ? 2 : 0);
+        const int x = tid >> lg, cl = tid & (nb - 1);
+        line_product<P, EXACT>(S, x * nb + cl, lx * nb, ly, (cdptr)a.wy, dl, x, lx, a.scale == 2 ? 2 : 0);
       }
     }
   }
   __syncthreads();
   double* out = a.out + (long)b * a.strideOut;
   if (!a.rows) {
-    const int c = tid & (nb - 1), j = v0 + c;
+    const int j = v0 + c;
     double ss = 0.0;
-    if (c < nv)
-      for (int i = tid >> lg; i < N; i += nt >> lg) {
-        const double v = S[i * nb + c];
-        out[(long)i * N + j] = v;
-        ss += v * v;
+    if (c < nv) {
+      if constexpr (NBT > 0) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const int i = (tid >> lg) + q * RP;
+          if (i < N) {
+            const double v = S[i * nb + c];
+            out[(long)i * N + j] = v;
+            ss += v * v;
+          }
+        }
+      } else {
+        for (int i = tid >> lg; i < N; i += nt >> lg) {
+          const double v = S[i * nb + c];
+          out[(long)i * N + j] = v;
+          ss += v * v;
+        }
       }
+    }
     if (a.norm2) {  // lanes equal mod nb hold parts of one column; then one partial per wave
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1)
@@ -272,9 +367,9 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
       }
     }
   } else {
-    for (int c = 0; c < nv; ++c) {
-      const int j = v0 + c;
-      for (int i = tid; i < N; i += nt) out[(long)j * N + i] = S[i * nb + c];
+    for (int cc = 0; cc < nv; ++cc) {
+      const int j = v0 + cc;
+      for (int i = tid; i < N; i += nt) out[(long)j * N + i] = S[i * nb + cc];
     }
   }
 }
@@ -297,19 +392,24 @@ int launch_kron_windows(Plan& p, hipStream_t st) {
 
 static int kron_max_threads(int P) { return P >= 32 ? 512 : 1024; }
 
-// LDS: the block of vectors, two d_l rows, one partial norm per wave and vector
-static size_t kron_lds(int N, int nb, int m) {
-  const int waves = (m * nb + 63) / 64;
-  return ((size_t)N * (nb + 2) + (size_t)waves * nb) * sizeof(double);
-}
 static bool kron_fixed(const Plan& p, int nb) {
   return p.m.lx == p.kron_P && p.m.ly == p.kron_P && p.kron_P <= 32 && (nb == 8 || nb == 16);
+}
+// threads of a workgroup: one per line and vector, or H per line on the fixed path
+static int kron_threads(const Plan& p, int nb) {
+  const int m = std::max(p.m.lx, p.m.ly);
+  return kron_fixed(p, nb) ? kron_fixed_threads(p.kron_P, nb) : (m * nb + 63) / 64 * 64;
+}
+// LDS: the block of vectors, two d_l rows, one partial norm per wave and vector
+static size_t kron_lds(const Plan& p, int nb) {
+  const int waves = kron_threads(p, nb) / 64;
+  return ((size_t)p.n * (nb + 2) + (size_t)waves * nb) * sizeof(double);
 }
 
 int kron_default_nb(const Plan& p) {
   const int m = std::max(p.m.lx, p.m.ly);
   for (int nb = 32; nb > 1; nb /= 2)
-    if (kron_lds(p.n, nb, m) <= 80 * 1024 && m * nb <= kron_max_threads(p.kron_P)) return nb;
+    if (kron_lds(p, nb) <= 80 * 1024 && m * nb <= kron_max_threads(p.kron_P)) return nb;
   return 1;
 }
 
@@ -337,6 +437,12 @@ static void launch_p(const KronDev& d, bool exact, int nb, bool fixed, dim3 grid
   }
 }
 
+bool kron_width_ok(const Plan& p, int nb) {
+  const int m = std::max(p.m.lx, p.m.ly);
+  return nb >= 1 && nb <= 32 && (nb & (nb - 1)) == 0 && m * nb <= kron_max_threads(p.kron_P) &&
+         kron_lds(p, nb) <= 160 * 1024;
+}
+
 int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
   if (a.batch <= 0 || a.count <= 0) return SLQ_OK;
   if (p.kron_P == 0) {
@@ -344,15 +450,14 @@ int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
     return SLQ_ERR_ARG;
   }
   const int nb = a.nb > 0 ? a.nb : (p.kron_nb > 0 ? p.kron_nb : kron_default_nb(p));
-  const int m = std::max(p.m.lx, p.m.ly);
   const bool fixed = kron_fixed(p, nb);
-  const size_t lds = kron_lds(p.n, nb, m);
-  int lognb = 0;
-  while ((1 << lognb) < nb) ++lognb;
-  if ((1 << lognb) != nb || nb > 32 || m * nb > kron_max_threads(p.kron_P) || lds > 160 * 1024) {
+  const size_t lds = kron_lds(p, nb);
+  if (!kron_width_ok(p, nb)) {
     set_error("structured slice product: vectors per workgroup must be a power of two <= 32 that fits");
     return SLQ_ERR_ARG;
   }
+  int lognb = 0;
+  while ((1 << lognb) < nb) ++lognb;
   KronDev d;
   d.lx = p.m.lx;
   d.ly = p.m.ly;
@@ -375,7 +480,7 @@ int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
   d.wy = d.wx + 2 * P;
   d.consts = p.consts;
   d.inv = a.inv;
-  const int threads = (m * nb + 63) / 64 * 64;
+  const int threads = kron_threads(p, nb);
   const bool exact = p.m.lx == P && p.m.ly == P;
   d.norm2 = a.rows ? nullptr : a.norm2;
   d.nvb = (p.n + nb - 1) / nb;

@@ -393,6 +393,7 @@ struct KronArgs {
 };
 int kron_line_size(int lx, int ly);
 int kron_default_nb(const Plan& p);
+bool kron_width_ok(const Plan& p, int nb);
 int launch_kron_windows(Plan& p, hipStream_t st);
 int launch_kron(Plan& p, const KronArgs& a, hipStream_t st);
 int tune_kron(Plan& p, int batch, hipStream_t st, float* best_ms);

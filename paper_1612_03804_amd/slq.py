@@ -28,7 +28,7 @@ EXPORTS = (
     "slq_eff_classes", "slq_eff_set_theta", "slq_eff_sweep", "slq_eff_features", "slq_cumulative_step",
     "slq_fit_effective", "slq_group_create", "slq_group_destroy", "slq_group_layout", "slq_group_describe",
     "slq_group_weight", "slq_group_green", "slq_magnetization", "slq_net_forward", "slq_net_gradient",
-    "slq_net_adam", "slq_eff_set_net", "slq_eff_net_classes", "slq_plan_tune",
+    "slq_net_adam", "slq_eff_set_net", "slq_eff_net_classes", "slq_plan_tune", "slq_plan_set_block_width",
 )
 SLQ_NET_PARAMS = 1969
 
@@ -67,6 +67,7 @@ def load_library(path: str = LIB_PATH):
         "slq_plan_destroy": ([P], C.c_int),
         "slq_plan_bytes": ([P, C.POINTER(C.c_size_t)], C.c_int),
         "slq_plan_tune": ([P, i32, C.POINTER(i32), P], C.c_int),
+        "slq_plan_set_block_width": ([P, i32], C.c_int),
         "slq_kinetic": ([P, i32, P, P], C.c_int),
         "slq_profile_enable": ([P, i32], C.c_int),
         "slq_profile_read": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int),
@@ -188,6 +189,11 @@ def slq_plan_tune(plan: Plan, batch: int, stream=None) -> int:
     v = C.c_int32()
     _check(load_library().slq_plan_tune(plan.handle, int(batch), C.byref(v), _stream(stream)))
     return v.value
+
+
+def slq_plan_set_block_width(plan: Plan, width: int):
+    """Fix the structured chain product's block width (0: back to the default)."""
+    _check(load_library().slq_plan_set_block_width(plan.handle, int(width)))
 
 
 def slq_profile_enable(plan: Plan, enable: bool = True):

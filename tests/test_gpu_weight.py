@@ -204,3 +204,42 @@ def test_tuned_block_width_keeps_parity(slq):
     assert slq.slq_plan_tune(dense, 6) == 0
     dense.close()
     plan.close()
+
+
+@pytest.mark.parametrize("model", [
+    Model(12, 12, 20, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=10),
+    Model(20, 20, 20, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=10),
+    Model(32, 32, 10, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=10),
+])
+def test_every_block_width_keeps_parity(slq, model):
+    """Each admissible block width of the structured product, the compile-time
+    widths 8 and 16 (two lanes per line where the workgroup allows) among them,
+    gives the oracle's weight and G; inadmissible widths are refused."""
+    from tests.gpu_util import dev, host
+    fields = [iid_field(model, 5300 + i) for i in range(3)]
+    refs = [stable.green(model, f) for f in fields]
+    plan = slq.Plan(model, 3)
+    s = dev(np.stack(fields).astype(np.int8))
+    tried = []
+    for width in (2, 4, 8, 16, 32):
+        try:
+            slq.slq_plan_set_block_width(plan, width)
+        except slq.SlqError:
+            continue
+        tried.append(width)
+        G = torch.empty((3, plan.n, plan.n), dtype=torch.float64, device="cuda")
+        la = torch.empty(3, dtype=torch.float64, device="cuda")
+        sg = torch.empty(3, dtype=torch.int8, device="cuda")
+        st = torch.empty(3, dtype=torch.int32, device="cuda")
+        slq.slq_green(plan, s, G, la, sg, st)
+        G, la, sg, st = host(G), host(la), host(sg), host(st)
+        for b, (ref_la, ref_sg, ref_G) in enumerate(refs):
+            assert st[b] == 0 and sg[b] == ref_sg, (width, b)
+            assert abs(la[b] - ref_la) <= LOG_TOL * max(1.0, abs(ref_la)), (width, b, la[b], ref_la)
+            assert np.max(np.abs(G[b] - ref_G)) <= G_TOL, (width, b, np.max(np.abs(G[b] - ref_G)))
+    assert 8 in tried and 16 in tried, tried
+    for bad in (3, 64, -1):
+        with pytest.raises(slq.SlqError):
+            slq.slq_plan_set_block_width(plan, bad)
+    slq.slq_plan_set_block_width(plan, 0)
+    plan.close()
