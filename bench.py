@@ -33,11 +33,12 @@ import time
 METRIC = "exact fermion-weight evals/sec + effective indep. samples/sec vs FP64 DQMC"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (and matrix) peak
 COPY_CALIBRATION_BYTES = 1 << 30
-# HBM bytes per k_kron launch (batch 512, 16 vectors per workgroup), averaged
+# HBM bytes per k_kron launch at batch 512, by vectors per workgroup, averaged
 # over the 8 blocks of an evaluation (the first block starts from the identity
 # and reads no X): rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, each scaled by
 # what the same counter reads for the 1 GiB copy of --copy-calibration.
-KRON_TRAFFIC = {"batch": 512, "vectors_per_workgroup": 16, "bytes": 1.2474e9}
+KRON_TRAFFIC_BATCH = 512
+KRON_TRAFFIC = {8: 1.2561e9, 16: 1.2474e9}
 
 
 def cpu_baseline(model, terms, theta, fields, logabs, signs, steps, seed):
@@ -252,6 +253,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--block-width", type=int, default=0,
+                    help="vectors per workgroup of the chain-block kernel (0: tuned on the plan)")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-details", action="store_true")
@@ -298,7 +301,11 @@ def main():
     if args.sweeps_only:
         print(json.dumps(local_sweep_rate(slq, plan, model, args.sweeps_only, seed)), flush=True)
         return
-    kron_nb = slq.slq_plan_tune(plan, B)
+    if args.block_width:
+        slq.slq_plan_set_block_width(plan, args.block_width)
+        kron_nb = args.block_width
+    else:
+        kron_nb = slq.slq_plan_tune(plan, B)
     terms = default_terms(model.n_slices)
 
     # training set and fit (step ii): exact weights of B seeded fields
@@ -336,8 +343,7 @@ def main():
     elapsed = t1 - t0
     value = B * args.steps / elapsed
     achieved = flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
-    traffic = (KRON_TRAFFIC["bytes"] if (B, kron_nb) == (KRON_TRAFFIC["batch"], KRON_TRAFFIC["vectors_per_workgroup"])
-               else None)
+    traffic = KRON_TRAFFIC.get(kron_nb) if B == KRON_TRAFFIC_BATCH else None
 
     out = {
         "metric": METRIC,
