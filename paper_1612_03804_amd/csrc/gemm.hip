@@ -178,7 +178,11 @@ __global__ __launch_bounds__(64 * GM * GN) void k_gemm(GemmArgs g, int ntm, int 
           if (RS) v *= RS[gm];
           if (FSO) v *= (S[gm] > 0) ? rpos : rneg;
           const long o = (long)gm * g.ldc + gn;
-          C[o] = (g.beta != 0.0) ? v + g.beta * C[o] : v;
+          if (g.beta != 0.0) {
+            const double cin = g.c_ident ? (gm == gn ? 1.0 : 0.0) : (gm < g.c_zero_rows ? 0.0 : C[o]);
+            v += g.beta * cin;
+          }
+          C[o] = v;
         }
       }
 }

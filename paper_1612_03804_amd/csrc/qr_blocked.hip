@@ -120,12 +120,34 @@ __global__ __launch_bounds__(PQ_THREADS) void k_prepivot(int N, const double* __
     nrm[c] = D[rp[c]];
   }
   __syncthreads();
-  // W[:, c] = X[:, perm[c]] D[perm[c]]: one wave per row, lanes along the row
+  // W[:, c] = X[:, perm[c]] D[perm[c]]: one wave per row, lanes along the row;
+  // the loads of two rows, up to 512 columns each, are in flight together
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < N; i += PQ_WAVES) {
-    const double* xr = X + (long)i * N;
-    double* wr = W + (long)i * N;
-    for (int c = lane; c < N; c += 64) wr[c] = xr[rp[c]] * nrm[c];
+  constexpr int CU = 8;  // columns per lane and row in flight
+  for (int c0 = 0; c0 < N; c0 += 64 * CU) {
+    for (int i = wave; i < N; i += 2 * PQ_WAVES) {
+      const int i2 = i + PQ_WAVES;
+      const double* xr = X + (long)i * N;
+      const double* xr2 = X + (long)i2 * N;
+      double v[CU], v2[CU];
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+        const int c = c0 + lane + 64 * u;
+        const bool in = c < N;
+        v[u] = in ? xr[rp[c]] : 0.0;
+        v2[u] = in && i2 < N ? xr2[rp[c]] : 0.0;
+      }
+      double* wr = W + (long)i * N;
+      double* wr2 = W + (long)i2 * N;
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+        const int c = c0 + lane + 64 * u;
+        if (c < N) {
+          wr[c] = v[u] * nrm[c];
+          if (i2 < N) wr2[c] = v2[u] * nrm[c];
+        }
+      }
+    }
   }
   if (threadIdx.x == 0 && bad && status) atomicOr(&status[b], SLQ_ST_NONFINITE);
 }
@@ -426,8 +448,11 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
   // with 8 wavefronts wherever the output has 64 rows or more, 32 x 64 with K 16
   // for the thin products of the panels, 16 x 64 for those of a 16-column block
   auto gemm = [&](int M, int Nc, int K, const double* A, long lda, long sA, bool ta, const double* B, long ldb,
-                  long sB, double* C, long ldc, long sC, double alpha, double beta) -> int {
+                  long sB, double* C, long ldc, long sC, double alpha, double beta, int c_ident = 0,
+                  int c_zero_rows = 0) -> int {
     GemmArgs g{};
+    g.c_ident = c_ident;
+    g.c_zero_rows = c_zero_rows;
     g.cfg = M >= 64 ? GEMM_128x64 : (M <= 16 ? GEMM_16x64 : GEMM_32x64);
     g.M = M;
     g.N = Nc;
@@ -481,11 +506,13 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     if (J0 + wo < N)
       SLQ_TRY(apply(Vbuf + (long)J0 * N + J0, Tb, wo, p.W + (long)J0 * N + J0 + wo, N - J0, N - J0 - wo, true));
   }
-  // explicit Q, backwards: U[J0:, J0:] <- Q_O U[J0:, J0:] = U - V_O (T_O (V_O^T U)).
-  // Columns J0..J0+wo-1 of U still hold [I; 0] there (later blocks only touch
-  // columns beyond), so for them V_O^T U = V_top^T, the unit lower triangle of
-  // V_O: U[:, block] = [I; 0] - V_O (T_O V_top^T), one small and one rank-wo GEMM.
-  SLQ_TRY(launch_set_identity(p, batch, o.U, st));
+  // explicit Q, backwards: U[J0:, J0:] <- Q_O U[J0:, J0:] = U - V_O (T_O (V_O^T U)),
+  // starting from U = I.  Columns J0..J0+wo-1 of U still hold [I; 0] there (later
+  // blocks only touch columns beyond), so for them V_O^T U = V_top^T, the unit
+  // lower triangle of V_O: U[:, block] = [I; 0] - V_O (T_O V_top^T), one small and
+  // one rank-wo GEMM.  U is never set to I in memory: the later blocks have
+  // written U[J0+wo:, J0+wo:], the rank-wo GEMMs read the rest of their C as the
+  // identity's entries (zeros in rows J0..J0+wo-1 beyond the block, I on it).
   for (int ob = nout - 1; ob >= 0; --ob) {
     const int J0 = bstart(ob), wo = bwidth(ob), m = N - J0;
     const double* Vp = Vbuf + (long)J0 * N + J0;
@@ -494,7 +521,7 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
       const int n2 = m - wo;
       SLQ_TRY(gemm(wo, n2, n2, Vp + (long)wo * N, N, NN, true, Ub + (long)wo * N + wo, N, NN, Wt, N, sW, 1.0, 0.0));
       SLQ_TRY(gemm(wo, n2, wo, TO + ob * sT, NBO, sW, false, Wt, N, sW, Wt2, N, sW, 1.0, 0.0));
-      SLQ_TRY(gemm(m, n2, wo, Vp, N, NN, false, Wt2, N, sW, Ub + wo, N, NN, -1.0, 1.0));
+      SLQ_TRY(gemm(m, n2, wo, Vp, N, NN, false, Wt2, N, sW, Ub + wo, N, NN, -1.0, 1.0, 0, wo));
     }
     GemmArgs y{};  // Wt2 = T_O V_top^T
     y.M = wo;
@@ -513,7 +540,7 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     y.batch = batch;
     y.cfg = GEMM_32x64;
     SLQ_TRY(launch_gemm(y, false, true, st));
-    SLQ_TRY(gemm(m, wo, wo, Vp, N, NN, false, Wt2, N, sW, Ub, N, NN, -1.0, 1.0));
+    SLQ_TRY(gemm(m, wo, wo, Vp, N, NN, false, Wt2, N, sW, Ub, N, NN, -1.0, 1.0, 1));
   }
   return SLQ_OK;
 }

@@ -323,6 +323,8 @@ struct GemmArgs {
   const int32_t* brow = nullptr;  // a_upper only: row k of op(B) is row brow[k] of B ([batch] + strideBrow)
   long strideBrow = 0;
   int s_out;          // apply the field factor to the rows of C instead of the rows of op(B)
+  int c_ident = 0;      // beta != 0: C is read as the identity (its own diagonal), not from memory
+  int c_zero_rows = 0;  // beta != 0: rows m < c_zero_rows of C are read as zero, not from memory
   int cfg = -1;       // tile configuration (GemmCfg), -1 = default choice
   int batch;
 };
