@@ -20,7 +20,9 @@ timed on a bounded sample of the same workload, and untimed-for-value
 details: acceptance, Green's-function evaluations/s, local DQMC sweeps/s,
 uneven batches, the chain products of each precision mode at 40x40, and the
 effective samples per second of self-learning DQMC against local FP64 DQMC
-with as many chains (skip with --no-ess).
+with as many chains: with the linear effective action and FP64 judge, with
+FP32 chain products in the judge (its error stated), and with proposals from
+the trained network action (skip with --no-ess).
 """
 from __future__ import annotations
 
@@ -117,25 +119,23 @@ def ess_rates(slq, plan, model, terms, seed, steps, n_dq, sweeps, burn):
 
     # (iii)+(iv) cumulative updates from the DQMC end configurations
     start = s_dq.repeat((B + n - 1) // n, 1, 1)[:B].contiguous()
-    runs = []
-    for n_moves in (max(1, eff.n_classes // 4), eff.n_classes, 4 * eff.n_classes):
+
+    def cumulative_run(pl, ef, n_moves):
         s = start.clone()
         logabs = torch.empty(B, dtype=f64, device=dev)
         sign = torch.empty(B, dtype=i8, device=dev)
         status = torch.empty(B, dtype=i32, device=dev)
-        slq.slq_weight(plan, s, logabs, sign, status)
+        slq.slq_weight(pl, s, logabs, sign, status)
         acc = torch.empty((steps, B), dtype=i8, device=dev)
         logA = torch.empty((steps, B), dtype=f64, device=dev)
         M = torch.empty((steps, B), dtype=i64, device=dev)
         for k in range(burn):
-            slq.slq_cumulative_step(plan, eff, s, logabs, sign, n_moves, seed, 10_000 + k, 0, acc[0], logA[0],
-                                    status)
+            slq.slq_cumulative_step(pl, ef, s, logabs, sign, n_moves, seed, 10_000 + k, 0, acc[0], logA[0], status)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
-            slq.slq_cumulative_step(plan, eff, s, logabs, sign, n_moves, seed, 20_000 + k, 0, acc[k], logA[k],
-                                    status)
-            slq.slq_magnetization(plan, s, M[k])
+            slq.slq_cumulative_step(pl, ef, s, logabs, sign, n_moves, seed, 20_000 + k, 0, acc[k], logA[k], status)
+            slq.slq_magnetization(pl, s, M[k])
         torch.cuda.synchronize()
         t_sl = time.perf_counter() - t0
         rate = float(acc.float().mean().item())
@@ -147,15 +147,93 @@ def ess_rates(slq, plan, model, terms, seed, steps, n_dq, sweeps, burn):
             run.update(tau_int_steps=tau_sl, ess_per_s=B * steps / (2 * tau_sl) / t_sl)
         else:
             run.update(tau_int_steps=None, ess_per_s=0.0)
-        runs.append(run)
-    eff.close()
+        return run, s
+
+    runs = [cumulative_run(plan, eff, n_moves)[0]
+            for n_moves in (max(1, eff.n_classes // 4), eff.n_classes, 4 * eff.n_classes)]
     best = max(runs, key=lambda r: r["ess_per_s"])
+    n_best = best["effective_moves"]
+
+    # the same update with the chain products in FP32 (stabilisation, LU and
+    # Eq. 4 in FP64); its judge's error is measured on the configurations it
+    # sampled, against the FP64 weights of the same fields
+    plan32 = slq.Plan(model, B, chain_prec=slq.SLQ_PREC_FP32)
+    eff32 = slq.Eff(plan32, terms, np.zeros(len(terms)))
+    slq.slq_eff_set_theta(eff32, theta)
+    run32, s32 = cumulative_run(plan32, eff32, n_best)
+    la64 = torch.empty(B, dtype=f64, device=dev)
+    la32 = torch.empty(B, dtype=f64, device=dev)
+    sg_w = torch.empty(B, dtype=i8, device=dev)
+    st_w = torch.empty(B, dtype=i32, device=dev)
+    slq.slq_weight(plan, s32, la64, sg_w, st_w)
+    slq.slq_weight(plan32, s32, la32, sg_w, st_w)
+    run32["max_abs_dlogW_vs_fp64"] = float((la32 - la64).abs().max().item())
+    run32["max_rel_dlogW_vs_fp64"] = float(((la32 - la64).abs() / la64.abs().clamp(min=1.0)).max().item())
+    eff32.close()
+    plan32.close()
+
+    # proposals from the learned action S_lin + S_net: the network (FP32
+    # kernels, Adam) is trained on the residual of the linear fit over the same
+    # DQMC configurations, 90 % for training and 10 % held out; its output layer
+    # starts at zero, so training starts from the linear model.  The epoch with
+    # the lowest held-out error is kept; if none beats the linear model alone,
+    # the linear model is the fallback and proposes the updates
+    from slq_inputs import net_init
+    xs, ys = train_s.view(-1, L, N), train_la.view(-1)
+    n_all = xs.shape[0]
+    n_tr = n_all - n_all // 10
+    prm = torch.from_numpy(net_init(seed)).to(dev)
+    prm[1960:] = 0.0
+    mom, vel, g = torch.zeros_like(prm), torch.zeros_like(prm), torch.empty_like(prm)
+    loss = torch.empty(1, dtype=f64, device=dev)
+
+    def held_out(params):
+        tot = 0.0
+        for k in range(n_tr, n_all, 256):
+            e = min(n_all, k + 256)
+            slq.slq_net_gradient(plan, eff, slq.SLQ_PREC_FP32, xs[k:e].contiguous(), ys[k:e].contiguous(), params,
+                                 g, loss)
+            tot += float(loss.item()) * (e - k) / (n_all - n_tr)
+        return tot
+
+    mse_lin = held_out(torch.zeros_like(prm))
+    best_prm, best_mse, curve = None, mse_lin, []
+    order = np.random.default_rng(seed)
+    t_adam, batch, epochs = 0, 64, 6
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(epochs):
+        perm = torch.from_numpy(order.permutation(n_tr)).to(dev)
+        for k in range(0, n_tr - batch + 1, batch):
+            idx = perm[k:k + batch]
+            slq.slq_net_gradient(plan, eff, slq.SLQ_PREC_FP32, xs[idx].contiguous(), ys[idx].contiguous(), prm, g,
+                                 loss)
+            t_adam += 1
+            slq.slq_net_adam(prm, g, mom, vel, t_adam, lr=1e-3)
+        curve.append(held_out(prm))
+        if curve[-1] < best_mse:
+            best_mse, best_prm = curve[-1], prm.clone()
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    if best_prm is not None:
+        slq.slq_eff_set_net(eff, best_prm, slq.SLQ_PREC_FP32)
+    run_net, _ = cumulative_run(plan, eff, n_best)
+    run_net["training"] = {"samples": n_tr, "held_out": n_all - n_tr, "epochs": epochs, "adam_steps": t_adam,
+                           "seconds": t_train, "held_out_mse_linear": mse_lin, "held_out_mse_by_epoch": curve,
+                           "proposals_from": "linear + network" if best_prm is not None else
+                           "linear (fallback: no epoch beat the linear model on held-out fields)"}
+    slq.slq_eff_set_net(eff, None)
+    eff.close()
     return {"dqmc_fp64": {"chains": n, "sweeps": sweeps, "tau_int_sweeps": tau_dq, "ess_per_s": ess_dq,
                           "sweeps_per_s": n * sweeps / t_dq,
                           "local_acceptance": float(acc_dq.sum().item()) / (n * sweeps * N * L)},
             "fit": {"samples": n * sweeps, "terms": len(terms), "r2": float(r2.item())},
             "sldqmc": {"chains": B, "steps": steps, "runs": runs},
-            "burn_in": burn, "ess_ratio": best["ess_per_s"] / ess_dq}
+            "sldqmc_fp32_chain": run32,
+            "sldqmc_learned_action": run_net,
+            "burn_in": burn, "ess_ratio": best["ess_per_s"] / ess_dq,
+            "ess_ratio_fp32_chain": run32["ess_per_s"] / ess_dq,
+            "ess_ratio_learned_action": run_net["ess_per_s"] / ess_dq}
 
 
 def local_sweep_rate(slq, plan, model, sweeps, seed):
