@@ -280,6 +280,7 @@ def precision_rates(slq, fields: int = 32):
     names = {0: "fp64_structured", 3: "fp64_dense", 1: "fp32", 2: "bf16"}
     for prec in (0, 3, 1, 2):
         plan = slq.Plan(model, fields, chain_prec=prec)
+        slq.slq_plan_tune(plan, fields)  # block width, or tile shape of the dense FP64 GEMM
         la = torch.empty(fields, dtype=torch.float64, device=dev)
         sg = torch.empty(fields, dtype=torch.int8, device=dev)
         st = torch.empty(fields, dtype=torch.int32, device=dev)

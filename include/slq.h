@@ -109,10 +109,12 @@ int slq_plan_bytes(const slq_plan* plan, size_t* bytes);
 /* slq_plan_tune - time the admissible block widths (vectors per workgroup:
  * 2, 4, ..., 32) of the structured chain product (SLQ_PREC_FP64) on `batch`
  * fields of the plan's own workspace and keep the fastest for later calls;
- * *chosen (host, may be NULL) receives it, 0 when the plan uses dense
- * products.  Synchronous on `stream`; overwrites the plan's scratch; must not
- * run during stream capture.  Without it the plan uses a width fixed by the
- * LDS size. */
+ * *chosen (host, may be NULL) receives it.  Plans with dense FP64 chain
+ * products (SLQ_PREC_FP64_DENSE) get the fastest tile shape of their chain
+ * GEMM instead, and *chosen = 0; reduced-precision plans are left as they
+ * are.  Synchronous on `stream`; overwrites the plan's scratch; must not run
+ * during stream capture.  Without it the plan uses a width fixed by the LDS
+ * size and a tile shape fixed by N. */
 int slq_plan_tune(slq_plan* plan, int32_t batch, int32_t* chosen, hipStream_t stream);
 /* slq_plan_set_block_width - fix the structured chain product's block width
  * (vectors per workgroup, a power of two 1..32 whose workgroup fits the

@@ -450,7 +450,13 @@ int slq_plan_tune(slq_plan* plan, int32_t batch, int32_t* chosen, hipStream_t st
   Plan& p = plan->p;
   SLQ_TRY(check_batch(p, batch));
   if (chosen) *chosen = 0;
-  if (batch == 0 || p.m.chain_prec != SLQ_PREC_FP64 || p.kron_P == 0) return SLQ_OK;
+  if (batch == 0) return SLQ_OK;
+  const bool dense = p.m.chain_prec == SLQ_PREC_FP64_DENSE || (p.m.chain_prec == SLQ_PREC_FP64 && p.kron_P == 0);
+  if (dense) {
+    SLQ_HIP(hipSetDevice(p.device));
+    return tune_chain_gemm(p, batch, stream, nullptr);
+  }
+  if (p.m.chain_prec != SLQ_PREC_FP64) return SLQ_OK;
   SLQ_HIP(hipSetDevice(p.device));
   SLQ_TRY(tune_kron(p, batch, stream, nullptr));
   if (chosen) *chosen = p.kron_nb;

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <vector>
 
 #include "slq_internal.h"
 
@@ -269,6 +270,69 @@ int default_gemm(int M, int N) {
   if (M >= 64 && divides(64)) return GEMM_64;
   if (M >= 48 && divides(48)) return GEMM_48;
   return GEMM_64;
+}
+
+// Time every candidate tile shape of the dense FP64 chain GEMM, X <- E diag(d) X,
+// on the plan's own buffers (Xa <- identity, spins all +1) and keep the fastest.
+int tune_chain_gemm(Plan& p, int batch, hipStream_t st, float* best_ms_out) {
+  const int N = p.n;
+  std::vector<int> cands;
+  if (N <= 32)
+    cands = {GEMM_16, GEMM_32x64, GEMM_64};
+  else
+    cands = {GEMM_128, GEMM_96, GEMM_80_K4, GEMM_80_K8, GEMM_160x80, GEMM_64, GEMM_48, GEMM_128x64, GEMM_64x128};
+  const long NN = (long)N * N;
+  SLQ_TRY(launch_set_identity(p, batch, p.Xa, st));
+  SLQ_TRY(fill_i32((int32_t*)p.s_work, (long)batch * p.L * N / 4, 0x01010101, st));
+  GemmArgs a{};
+  a.M = N;
+  a.N = N;
+  a.K = N;
+  a.A = p.E;
+  a.lda = N;
+  a.B = p.Xa;
+  a.ldb = N;
+  a.strideB = NN;
+  a.C = p.Xb;
+  a.ldc = N;
+  a.strideC = NN;
+  a.S = p.s_work;
+  a.strideS = (long)p.L * N;
+  a.consts = p.consts;
+  a.alpha = 1.0;
+  a.batch = batch;
+  hipEvent_t e0, e1;
+  SLQ_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    set_error("hipEventCreate failed");
+    return SLQ_ERR_DEVICE;
+  }
+  int best = default_gemm(N, N), rc = SLQ_OK;
+  float best_ms = 1e30f;
+  for (int cfg : cands) {
+    if ((rc = launch_gemm_cfg(a, false, false, cfg, st)) != SLQ_OK) break;
+    if (hipEventRecord(e0, st) != hipSuccess) rc = SLQ_ERR_DEVICE;
+    for (int r = 0; r < 3 && rc == SLQ_OK; ++r) rc = launch_gemm_cfg(a, false, false, cfg, st);
+    float ms = 0.f;
+    if (rc == SLQ_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = SLQ_ERR_DEVICE;
+    if (rc != SLQ_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cfg;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != SLQ_OK) {
+    if (rc == SLQ_ERR_DEVICE) set_error("timing the chain GEMM tile shapes failed");
+    return rc;
+  }
+  p.gemm_cfg = best;
+  if (best_ms_out) *best_ms_out = best_ms;
+  return SLQ_OK;
 }
 
 int launch_gemm(const GemmArgs& a, bool ta, bool tb, hipStream_t st) {

@@ -99,64 +99,17 @@ static int autotune_kron(Group& g, SubPlan& sp) {
   return SLQ_OK;
 }
 
-// Time every candidate tile shape of the FP64 chain GEMM on the sub-plan's
-// own buffers and batch size, and keep the fastest for that sub-plan.
+// Tune the sub-plan's chain product on its own buffers and batch size: the
+// block width of the structured product, or the tile shape of the dense GEMM.
 static int autotune(Group& g, SubPlan& sp) {
   Plan& p = sp.plan->p;
   const int N = p.n;
   if (p.m.chain_prec == SLQ_PREC_FP64 && p.kron_P > 0) return p.kron_nb > 0 ? SLQ_OK : autotune_kron(g, sp);
   if ((p.m.chain_prec != SLQ_PREC_FP64 && p.m.chain_prec != SLQ_PREC_FP64_DENSE) || p.gemm_cfg >= 0)
     return SLQ_OK;
-  std::vector<int> cands;
-  if (N <= 32) {
-    cands = {GEMM_16, GEMM_32x64, GEMM_64};
-  } else {
-    cands = {GEMM_128, GEMM_96, GEMM_80_K4, GEMM_80_K8, GEMM_160x80, GEMM_64, GEMM_48};
-  }
-  const long NN = (long)N * N;
-  int rc = launch_set_identity(p, sp.nb, p.Xa, g.gs);
-  if (rc != SLQ_OK) return rc;
-  rc = fill_i32((int32_t*)p.s_work, (long)sp.nb * p.L * N / 4, 0x01010101, g.gs);
-  if (rc != SLQ_OK) return rc;
-  GemmArgs a{};
-  a.M = N;
-  a.N = N;
-  a.K = N;
-  a.A = p.E;
-  a.lda = N;
-  a.B = p.Xa;
-  a.ldb = N;
-  a.strideB = NN;
-  a.C = p.Xb;
-  a.ldc = N;
-  a.strideC = NN;
-  a.S = p.s_work;
-  a.strideS = (long)p.L * N;
-  a.consts = p.consts;
-  a.alpha = 1.0;
-  a.batch = sp.nb;
-  hipEvent_t e0, e1;
-  SLQ_HIP(hipEventCreate(&e0));
-  SLQ_HIP(hipEventCreate(&e1));
-  int best = default_gemm(N, N);
-  float best_ms = 1e30f;
-  for (int cfg : cands) {
-    if ((rc = launch_gemm_cfg(a, false, false, cfg, g.gs)) != SLQ_OK) break;
-    SLQ_HIP(hipEventRecord(e0, g.gs));
-    for (int r = 0; r < 3 && rc == SLQ_OK; ++r) rc = launch_gemm_cfg(a, false, false, cfg, g.gs);
-    SLQ_HIP(hipEventRecord(e1, g.gs));
-    SLQ_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    SLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (rc == SLQ_OK && ms < best_ms) {
-      best_ms = ms;
-      best = cfg;
-    }
-  }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  if (rc != SLQ_OK) return rc;
-  p.gemm_cfg = best;
+  float best_ms = 0.f;
+  SLQ_TRY(tune_chain_gemm(p, sp.nb, g.gs, &best_ms));
+  const int best = p.gemm_cfg;
   g.tuned_n.push_back(N);
   g.tuned_kind.push_back(0);
   g.tuned_cfg.push_back(best);

@@ -348,6 +348,8 @@ enum GemmCfg {
 };
 int launch_gemm_cfg(const GemmArgs& a, bool transA, bool transB, int cfg, hipStream_t st);
 int default_gemm(int M, int N);
+struct Plan;
+int tune_chain_gemm(Plan& p, int batch, hipStream_t st, float* best_ms);
 
 // Reduced-precision chain GEMM: C(f32)[b] = A(f32, shared) diag(d_slice) B[b] (f32 or f64)
 struct LpArgs {

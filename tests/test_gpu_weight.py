@@ -186,7 +186,8 @@ def test_dense_fp64_products_agree(slq, model):
 
 
 def test_tuned_block_width_keeps_parity(slq):
-    """slq_plan_tune picks a power-of-two block width and results stay exact."""
+    """slq_plan_tune picks a power-of-two block width (structured products) or
+    a tile shape (dense products) and results stay exact."""
     from tests.gpu_util import dev, host
     model = Model(12, 12, 30, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=10)
     fields = [iid_field(model, 5200 + i) for i in range(6)]
@@ -200,10 +201,13 @@ def test_tuned_block_width_keeps_parity(slq):
     st = torch.empty(6, dtype=torch.int32, device="cuda")
     slq.slq_green(plan, s, G, la, sg, st)
     check_parity(model, fields, host(G), host(la), host(sg), host(st))
+    plan.close()
+    # dense FP64 products: the tuning picks the chain GEMM's tile shape instead
     dense = slq.Plan(model, 6, chain_prec=slq.SLQ_PREC_FP64_DENSE)
     assert slq.slq_plan_tune(dense, 6) == 0
+    slq.slq_green(dense, s, G, la, sg, st)
+    check_parity(model, fields, host(G), host(la), host(sg), host(st))
     dense.close()
-    plan.close()
 
 
 @pytest.mark.parametrize("model", [
