@@ -80,11 +80,53 @@ __device__ void transpose_scaled(int N, const double* __restrict__ src, const do
 // Work items are (column, FN_RB consecutive rows), columns fastest, so that
 // a thread has FN_RB + NB loads in flight at once and the rows of a wave are
 // coalesced.  The rows xrow0.. are disjoint from the updated ones.
+// Where N, ldp, rbeg and jbeg are even, an item is a pair of adjacent columns
+// and 4 rows instead: 16-byte loads and stores, and each 16-byte read of P
+// serves two rows of both columns.
 template <int NB>
 __device__ __forceinline__ void rank_update(double* __restrict__ A, int N, const double* P, int ldp, int nbw,
                                             int xrow0, int rowoff, int rbeg, int rend, int jbeg, int jend) {
   const int ncol = jend - jbeg;
   if (ncol <= 0 || rend <= rbeg) return;
+  if (((N | ldp | rbeg | jbeg) & 1) == 0) {
+    typedef double d2_t __attribute__((ext_vector_type(2)));
+    const int npair = ncol / 2;  // ncol = N - jbeg is even too
+    constexpr int RB2 = 4;  // rows per item: x and w of two columns stay in registers
+    const int nch = (rend - rbeg + RB2 - 1) / RB2;
+    for (int it = threadIdx.x; it < npair * nch; it += FN_THREADS) {
+      const int j = jbeg + 2 * (it % npair);
+      const int r0 = rbeg + (it / npair) * RB2;
+      d2_t w[RB2], acc[RB2];
+#pragma unroll
+      for (int q = 0; q < RB2; ++q) {
+        w[q] = r0 + q < rend ? *(const d2_t*)(A + (long)(rowoff + r0 + q) * N + j) : d2_t{0.0, 0.0};
+        acc[q] = d2_t{0.0, 0.0};
+      }
+      constexpr int CH = NB < 8 ? NB : 8;  // columns of P per pass (registers)
+#pragma unroll
+      for (int c0 = 0; c0 < NB; c0 += CH) {
+        d2_t x[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+          x[c] = c0 + c < nbw ? *(const d2_t*)(A + (long)(xrow0 + c0 + c) * N + j) : d2_t{0.0, 0.0};
+#pragma unroll
+        for (int q2 = 0; q2 < RB2; q2 += 2)
+#pragma unroll
+          for (int c = 0; c < CH; ++c)
+            if (c0 + c < nbw && r0 + q2 < rend) {
+              const d2_t pc = *(const d2_t*)(P + (c0 + c) * ldp + r0 + q2);  // rows r0+q2, r0+q2+1
+              acc[q2] += pc[0] * x[c];
+              acc[q2 + 1] += pc[1] * x[c];
+            }
+      }
+#pragma unroll
+      for (int q = 0; q < RB2; ++q) w[q] -= acc[q];
+#pragma unroll
+      for (int q = 0; q < RB2; ++q)
+        if (r0 + q < rend) *(d2_t*)(A + (long)(rowoff + r0 + q) * N + j) = w[q];
+    }
+    return;
+  }
   const int nch = (rend - rbeg + FN_RB - 1) / FN_RB;
   for (int it = threadIdx.x; it < ncol * nch; it += FN_THREADS) {
     const int j = jbeg + it % ncol;
