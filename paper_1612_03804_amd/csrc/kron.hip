@@ -207,27 +207,19 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
       cy[d] = ((cdptr)a.wy)[P - 1 - d];
     }
   }
-  // NBT > 0: the thread count and N are compile-time; a thread holds rows
-  // (tid / NBT) + q RP, q < NP, of vector c of a block
-  constexpr int NTF = NBT ? kron_fixed_threads(P, NBT) : 64;
-  constexpr int RP = NBT ? NTF / NBT : 1, NP = NBT ? (P * P + RP - 1) / RP : 1;
-  double nxt[NP];  // the block's entries, loaded before the first is stored (NBT > 0)
-  auto fetch = [&]() {
-    const int b = lin / a.nvb, j = (lin % a.nvb) * nb + c;
-    const double* __restrict__ in = a.in ? a.in + (long)b * a.strideIn : nullptr;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const int i = (tid >> lg) + q * RP;
-      nxt[q] = 0.0;
-      if (i < N && j < N) nxt[q] = in ? in[(long)i * N + j] : (i == j ? 1.0 : 0.0);
-    }
-  };
+  const int b = lin / a.nvb;
+  const int v0 = (lin % a.nvb) * nb;
+  const int nv = min(nb, N - v0);
   auto spins = [&](int k) {  // the field of the k-th slice of this launch
     int sl = (a.slice0 + k * a.step) % a.L;
     if (sl < 0) sl += a.L;
-    return a.s + (long)(lin / a.nvb) * a.strideS + (long)sl * N;
+    return a.s + (long)b * a.strideS + (long)sl * N;
   };
-  // NBT > 0: the next slice's spins are loaded one slice ahead, in registers
+  // NBT > 0: the thread count and N are compile-time; a thread holds rows
+  // (tid / NBT) + q RP, q < NP, of vector c of the block, and the spins of
+  // sites tid + q NTF, q < SPT, of the next slice (loaded one slice ahead)
+  constexpr int NTF = NBT ? kron_fixed_threads(P, NBT) : 64;
+  constexpr int RP = NBT ? NTF / NBT : 1, NP = NBT ? (P * P + RP - 1) / RP : 1;
   constexpr int SPT = NBT ? (P * P + NTF - 1) / NTF : 1;
   int8_t spn[SPT];
   auto prefetch = [&](const int8_t* __restrict__ f) {
@@ -237,19 +229,23 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
       spn[q] = i < N ? f[i] : 1;
     }
   };
-  if constexpr (NBT > 0) {
-    if (!a.rows) fetch();
-    if (a.scale) prefetch(spins(0));
-  }
-  const int b = lin / a.nvb;
-  const int v0 = (lin % a.nvb) * nb;
-  const int nv = min(nb, N - v0);
+  if (NBT > 0 && a.scale) prefetch(spins(0));
   if (!a.rows) {
     if constexpr (NBT > 0) {
+      // every load of the thread in flight before the first is stored
+      const double* __restrict__ in = a.in ? a.in + (long)b * a.strideIn : nullptr;
+      const int j = v0 + c;
+      double ent[NP];
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         const int i = (tid >> lg) + q * RP;
-        if (i < N) S[i * nb + c] = nxt[q];
+        ent[q] = 0.0;
+        if (i < N && c < nv) ent[q] = in ? in[(long)i * N + j] : (i == j ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const int i = (tid >> lg) + q * RP;
+        if (i < N) S[i * nb + c] = ent[q];
       }
     } else {
       const double* __restrict__ in = a.in ? a.in + (long)b * a.strideIn : nullptr;
