@@ -132,7 +132,9 @@ __global__ __launch_bounds__(FL_THREADS) void k_flip_slice(FlipArgs f) {
 // decision of a site reads LDS only.  One barrier per rejected site, two per
 // accepted site; these order LDS traffic only, so the fetches of G_0 stay in
 // flight across them.
-constexpr int FF_MAXN = FL_THREADS, FF_KD = 16, FF_XP = FF_KD + 2, FF_PD = 4;
+// KD: depth of the delayed update (flushes per slice N / KD, each reading and
+// writing G): 20 where the LDS holds its tables, else 16.
+constexpr int FF_MAXN = FL_THREADS, FF_PD = 4;
 
 typedef double fd4_t __attribute__((ext_vector_type(4)));
 
@@ -141,8 +143,10 @@ typedef double fd4_t __attribute__((ext_vector_type(4)));
 // takes the 16 x 16 tiles w, w + 8, ...; a tile of G_0 is fetched one tile
 // ahead.  Lane l holds rows l/16 + 4q and column l%16 of its tile, the
 // operand and result layout of v_mfma_f64_16x16x4_f64.
+template <int KD>
 __device__ __forceinline__ void flush_mfma(double* __restrict__ G, int N, const double* __restrict__ Xs,
                                            const double* __restrict__ AY, int ldy) {
+  constexpr int XP = KD + 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nt = (N + 15) / 16, tiles = nt * nt;
   auto load = [&](int t, fd4_t& v) {
@@ -159,9 +163,9 @@ __device__ __forceinline__ void flush_mfma(double* __restrict__ G, int N, const 
     load(t + FL_WAVES, nxt);
     const int tr = t / nt, tc = t % nt, col = tc * 16 + (lane & 15), xrow = tr * 16 + (lane & 15);
 #pragma unroll
-    for (int ks = 0; ks < FF_KD; ks += 4) {
+    for (int ks = 0; ks < KD; ks += 4) {
       const int kk = ks + (lane >> 4);
-      const double xa = xrow < N ? -Xs[(long)xrow * FF_XP + kk] : 0.0;
+      const double xa = xrow < N ? -Xs[(long)xrow * XP + kk] : 0.0;
       const double yb = col < N ? AY[(long)kk * ldy + col] : 0.0;
       cur = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb, cur, 0, 0, 0);
     }
@@ -174,7 +178,10 @@ __device__ __forceinline__ void flush_mfma(double* __restrict__ G, int N, const 
   }
 }
 
+template <int KD>
 __global__ __launch_bounds__(FL_THREADS) void k_flip_fast(FlipArgs f) {
+  static_assert(KD % 4 == 0, "the flush takes KD in steps of 4");
+  constexpr int FF_KD = KD, FF_XP = KD + 2;
   extern __shared__ double lds[];
   const int N = f.N;
   const int b = blockIdx.x;
@@ -279,7 +286,7 @@ __global__ __launch_bounds__(FL_THREADS) void k_flip_fast(FlipArgs f) {
           }
         }
         lds_barrier();
-        flush_mfma(G, N, Xs, AY, ldy);
+        flush_mfma<KD>(G, N, Xs, AY, ldy);
         k = 0;
         __syncthreads();
         // the fetched G_0 values predate the flush: fetch the rest of this group and the next again
@@ -307,7 +314,7 @@ __global__ __launch_bounds__(FL_THREADS) void k_flip_fast(FlipArgs f) {
       for (int m = 0; m < FF_KD; ++m) AY[(long)m * ldy + c] = m < k ? A[m] * y[m] : 0.0;
     }
     lds_barrier();
-    flush_mfma(G, N, Xs, AY, ldy);
+    flush_mfma<KD>(G, N, Xs, AY, ldy);
   }
   __syncthreads();  // the decisions of every site are in sp
   if (own) s[c] = (int8_t)sp[c];
@@ -336,10 +343,16 @@ int launch_flip_slice(Plan& p, int batch, int8_t* s, double* G, double* logabs, 
   f.sweep = sweep;
   f.chain0 = chain0;
   if (p.n <= FF_MAXN) {
-    const size_t lds = sizeof(double) * ((size_t)p.n * FF_XP + 2 * p.n + 2 * FF_KD + 4 + (size_t)FF_KD * (p.n + 1)) +
-                       sizeof(int) * p.n;
-    allow_max_lds((const void*)k_flip_fast);
-    k_flip_fast<<<batch, FL_THREADS, lds, st>>>(f);
+    auto lds_of = [&](size_t kd) {
+      return sizeof(double) * ((size_t)p.n * (kd + 2) + 2 * p.n + 2 * kd + 4 + kd * (p.n + 1)) + sizeof(int) * p.n;
+    };
+    if (lds_of(20) <= 160 * 1024) {
+      allow_max_lds((const void*)k_flip_fast<20>);
+      k_flip_fast<20><<<batch, FL_THREADS, lds_of(20), st>>>(f);
+    } else {
+      allow_max_lds((const void*)k_flip_fast<16>);
+      k_flip_fast<16><<<batch, FL_THREADS, lds_of(16), st>>>(f);
+    }
     SLQ_LAUNCHED();
     return SLQ_OK;
   }
