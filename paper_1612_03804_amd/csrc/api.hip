@@ -210,6 +210,8 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
       k.scale = 1;
       k.batch = batch;
       k.norm2 = p.xnorm2;
+      k.first_block = p.first_block;
+      k.block = j0 / ns;
       SLQ_TRY(timed_chain_kron(p, k, st));
     } else if (!lp) {
       if (j0 == 0) {

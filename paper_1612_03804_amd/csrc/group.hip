@@ -1,8 +1,11 @@
 // Groups of independent chains of uneven size (N_c, L_c): one graph-captured
 // launch evaluates the exact weight (Eq. 1; and optionally G) of every chain.
 //
-// Chains with identical models share an internal plan and run as one batch;
-// the fields are gathered from the caller's packed layout into the batch,
+// Chains with identical models share an internal plan and run as one batch,
+// and so do chains on one lattice whose lengths differ by whole stabilisation
+// blocks (structured FP64 products): the plan has the longest length and a
+// shorter chain starts its stabilised product later.  The fields are gathered
+// from the caller's packed layout into the batch,
 // evaluated (stabilised chain, QR, LU) and the results scattered back.  The
 // whole sequence is recorded once as a HIP graph on the group's own stream
 // (per set of caller pointers) and replayed as a single launch; the caller's
@@ -25,6 +28,9 @@ struct SubPlan {
   int32_t* d_ids = nullptr;   // [nb] chain index of each batch position
   int64_t* d_soff = nullptr;  // [nb] field offset (bytes) in the caller's packed layout
   int64_t* d_goff = nullptr;  // [nb] G offset (doubles)
+  int64_t* d_lead = nullptr;  // [nb] leading slices x N of the batch layout before the chain's own
+  int32_t* d_first = nullptr; // [nb] first stabilisation block of each chain
+  int lmin = 0;               // shortest chain of the batch (its plan has the longest)
 };
 
 struct Group {
@@ -52,12 +58,16 @@ struct Group {
 
 int check_model_public(const slq_model* m);
 
-__global__ void k_gather(const int8_t* __restrict__ src, const int64_t* __restrict__ soff, long per,
-                         int8_t* __restrict__ dst) {
+// Field of batch position pos: lead[pos] leading +1 entries (slices its chain
+// does not have, never multiplied), then the chain's own slices.
+__global__ void k_gather(const int8_t* __restrict__ src, const int64_t* __restrict__ soff,
+                         const int64_t* __restrict__ lead, long per, int8_t* __restrict__ dst) {
   const int pos = blockIdx.y;
+  const long l0 = lead[pos];
   const int8_t* s = src + soff[pos];
   int8_t* d = dst + (long)pos * per;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (long)gridDim.x * blockDim.x)
+    d[i] = i < l0 ? (int8_t)1 : s[i - l0];
 }
 
 __global__ void k_scatter(int nb, const int32_t* __restrict__ ids, const double* __restrict__ la,
@@ -77,6 +87,16 @@ __global__ void k_scatter_g(long NN, const int64_t* __restrict__ goff, const dou
   const double* s = G + (long)pos * NN;
   double* d = out + goff[pos];
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < NN; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
+}
+
+// Chains on one lattice with structured FP64 products whose lengths differ by
+// whole stabilisation blocks share a batch: a shorter chain starts its
+// stabilised product that many blocks later (U D V = I 1 I until then, which
+// the structured product and the QR pass through exactly).
+static bool same_but_length(const slq_model& a, const slq_model& b) {
+  return a.lx == b.lx && a.ly == b.ly && a.n_stab == b.n_stab && a.t == b.t && a.mu == b.mu && a.dtau == b.dtau &&
+         a.xi == b.xi && a.chain_prec == SLQ_PREC_FP64 && b.chain_prec == SLQ_PREC_FP64 &&
+         kron_line_size(a.lx, a.ly) > 0 && (a.n_slices - b.n_slices) % a.n_stab == 0;
 }
 
 static bool same_model(const slq_model& a, const slq_model& b) {
@@ -124,7 +144,7 @@ static int enqueue(Group& g, int lane, hipStream_t st, const int8_t* d_s, double
     Plan& p = sp.plan->p;
     const long per = (long)p.L * p.n;
     dim3 grid((unsigned)std::max<long>(1, std::min<long>((per + 255) / 256, 256)), sp.nb);
-    k_gather<<<grid, 256, 0, st>>>(d_s, sp.d_soff, per, p.s_work);
+    k_gather<<<grid, 256, 0, st>>>(d_s, sp.d_soff, sp.d_lead, per, p.s_work);
     SLQ_LAUNCHED();
     int rc = fill_i32(p.status, sp.nb, 0, st);
     if (rc == SLQ_OK) rc = launch_check_spins(p, sp.nb, p.s_work, p.status, st);
@@ -253,22 +273,25 @@ int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out)
     g.s_off[c + 1] = g.s_off[c] + (long)models[c].n_slices * N;
     g.g_off[c + 1] = g.g_off[c] + N * N;
   }
-  // sub-plans in order of first appearance
+  // sub-plans in order of first appearance: identical models, or models that
+  // differ only in their length by whole stabilisation blocks (the batch's
+  // plan has the longest); rep[k] is the longest member
   std::vector<std::vector<int>> members;
   std::vector<int> rep;
   for (int c = 0; c < n_chains; ++c) {
     int k = -1;
-    for (size_t q = 0; q < rep.size(); ++q)
-      if (same_model(models[rep[q]], models[c])) k = (int)q;
+    for (size_t q = 0; q < rep.size() && k < 0; ++q)
+      if (same_model(models[rep[q]], models[c]) || same_but_length(models[rep[q]], models[c])) k = (int)q;
     if (k < 0) {
       rep.push_back(c);
       members.emplace_back();
       k = (int)rep.size() - 1;
     }
     members[k].push_back(c);
+    if (models[c].n_slices > models[rep[k]].n_slices) rep[k] = c;
   }
   size_t bytes = 0;
-  for (auto& mset : members) bytes += mset.size() * (4 + 8 + 8) + 64;
+  for (auto& mset : members) bytes += mset.size() * (4 + 8 + 8 + 8 + 4) + 2 * 64;
   if (hipMalloc(&g.dmem, bytes) != hipSuccess) {
     delete h;
     set_error("hipMalloc failed");
@@ -281,24 +304,40 @@ int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out)
     sp.nb = (int)members[q].size();
     rc = slq_plan_create(&models[rep[q]], sp.nb, &sp.plan);
     if (rc != SLQ_OK) break;
-    std::vector<int32_t> ids(members[q].begin(), members[q].end());
-    std::vector<int64_t> so(sp.nb), go(sp.nb);
+    std::vector<int32_t> ids(members[q].begin(), members[q].end()), first(sp.nb);
+    std::vector<int64_t> so(sp.nb), go(sp.nb), lead(sp.nb);
+    const slq_model& mr = models[rep[q]];
+    const long N = (long)mr.lx * mr.ly;
+    bool varied = false;
+    sp.lmin = mr.n_slices;
     for (int i = 0; i < sp.nb; ++i) {
+      const int dl = mr.n_slices - models[ids[i]].n_slices;  // a multiple of n_stab
       so[i] = g.s_off[ids[i]];
       go[i] = g.g_off[ids[i]];
+      lead[i] = (int64_t)dl * N;
+      first[i] = dl / mr.n_stab;
+      varied = varied || dl != 0;
+      sp.lmin = std::min(sp.lmin, models[ids[i]].n_slices);
     }
     sp.d_soff = (int64_t*)dp;
     dp += 8 * sp.nb;
     sp.d_goff = (int64_t*)dp;
     dp += 8 * sp.nb;
+    sp.d_lead = (int64_t*)dp;
+    dp += 8 * sp.nb;
     sp.d_ids = (int32_t*)dp;
+    dp += 4 * sp.nb + (64 - (4 * sp.nb) % 64) % 64;
+    sp.d_first = (int32_t*)dp;
     dp += 4 * sp.nb + (64 - (4 * sp.nb) % 64) % 64;
     if (hipMemcpy(sp.d_soff, so.data(), 8 * sp.nb, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(sp.d_goff, go.data(), 8 * sp.nb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(sp.d_ids, ids.data(), 4 * sp.nb, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(sp.d_lead, lead.data(), 8 * sp.nb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(sp.d_ids, ids.data(), 4 * sp.nb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(sp.d_first, first.data(), 4 * sp.nb, hipMemcpyHostToDevice) != hipSuccess) {
       set_error("hipMemcpy failed");
       rc = SLQ_ERR_DEVICE;
     }
+    if (varied) sp.plan->p.first_block = sp.d_first;
     g.subs.push_back(sp);
   }
   if (rc == SLQ_OK && (hipStreamCreateWithFlags(&g.gs, hipStreamNonBlocking) != hipSuccess ||
@@ -394,7 +433,7 @@ int slq_group_describe(const slq_group* grp, char* buf, size_t len) {
   for (size_t q = 0; q < g.subs.size(); ++q) {
     const Plan& p = g.subs[q].plan->p;
     s += (q ? ", " : "") + std::string("{\"N\": ") + std::to_string(p.n) + ", \"L\": " + std::to_string(p.L) +
-         ", \"chains\": " + std::to_string(g.subs[q].nb) + "}";
+         ", \"L_min\": " + std::to_string(g.subs[q].lmin) + ", \"chains\": " + std::to_string(g.subs[q].nb) + "}";
   }
   s += "], \"lanes\": [";
   for (size_t k = 0; k < g.lane_subs.size(); ++k) {

@@ -39,6 +39,8 @@ struct KronDev {
   int inv;               // 1/d instead of d
   int nvb, batch;        // vector blocks per field, fields
   double* norm2;         // columns mode: squared 2-norms of the output columns, or null
+  const int32_t* first_block;  // [batch] or null: fields with block < first_block[b] pass X through
+  int block;                   // stabilisation block of this launch
 };
 
 // Window w of length 2P for a circulant of period n with first column c:
@@ -208,6 +210,8 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
     }
   }
   const int b = lin / a.nvb;
+  // a field whose chain starts at a later block passes X (the identity) through
+  const bool idle = a.first_block && a.block < a.first_block[b];
   const int v0 = (lin % a.nvb) * nb;
   const int nv = min(nb, N - v0);
   auto spins = [&](int k) {  // the field of the k-th slice of this launch
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
       spn[q] = i < N ? f[i] : 1;
     }
   };
-  if (NBT > 0 && a.scale) prefetch(spins(0));
+  if (NBT > 0 && a.scale && !idle) prefetch(spins(0));
   if (!a.rows) {
     if constexpr (NBT > 0) {
       // every load of the thread in flight before the first is stored
@@ -267,7 +271,7 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
       }
     }
   }
-  for (int k = 0; k < a.count; ++k) {
+  for (int k = 0; k < (idle ? 0 : a.count); ++k) {
     // a second buffer: threads still in the y-lines of slice k - 1 may read the first
     double* dl = S + nS + (k & 1) * N;
     if (a.scale) {
@@ -481,6 +485,8 @@ int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
   d.norm2 = a.rows ? nullptr : a.norm2;
   d.nvb = (p.n + nb - 1) / nb;
   d.batch = a.batch;
+  d.first_block = a.first_block;
+  d.block = a.block;
   dim3 grid((unsigned)(((long)d.nvb * a.batch + 15) / 16 * 16));
   switch (P) {
     case 4: launch_p<4>(d, exact, nb, fixed, grid, threads, lds, st); break;

@@ -219,6 +219,10 @@ struct Plan {
   int kron_P = 0;
   double* kron_w = nullptr;
   int kron_nb = 0;
+  // [max_batch] or null: the first stabilisation block of each field's chain
+  // (earlier blocks leave U D V = I 1 I; set by groups that batch chains of
+  // several lengths, structured products only; device memory the plan does not own)
+  const int32_t* first_block = nullptr;
   // blocked QR workspace: outer compact-WY factors, Gram blocks, V^T A products
   double* qrws = nullptr;
 
@@ -394,6 +398,8 @@ struct KronArgs {
   int nb = 0;        // vectors per workgroup (0: the plan's choice)
   int batch;
   double* norm2 = nullptr;  // rows == 0: [batch][N] squared 2-norms of the output columns, or null
+  const int32_t* first_block = nullptr;  // [batch] or null: block < first_block[b] leaves field b's X as it is
+  int block = 0;                         // stabilisation block of the launch (first_block only)
 };
 int kron_line_size(int lx, int ly);
 int kron_default_nb(const Plan& p);
