@@ -27,6 +27,8 @@ def test_uneven_group_parity_and_replays(slq):
     grp = slq.Group(models)
     info = grp.describe()
     assert info["chains"] == 64 and sum(b["chains"] for b in info["batches"]) == 64
+    # one batch per lattice: the lengths differ by whole stabilisation blocks
+    assert len(info["batches"]) == 5 and all(b["L_min"] <= b["L"] for b in info["batches"])
     assert {t["N"] for t in info["tuned"]} == {b["N"] for b in info["batches"]}
     s = dev(grp.pack(fields))
     G = torch.empty(int(grp.g_off[-1]), dtype=torch.float64, device="cuda")
@@ -64,4 +66,33 @@ def test_uneven_group_parity_and_replays(slq):
     slq.slq_group_weight(grp, s, la2, sg, st)
     assert np.array_equal(host(la2), la0)
     plan.close()
+    grp.close()
+
+
+def test_lengths_off_the_block_grid_get_their_own_batch(slq):
+    """Chains whose lengths differ by a whole number of stabilisation blocks
+    share a batch, the others do not; every chain matches the oracle."""
+    from slq_inputs import Model
+    from tests.gpu_util import dev, host
+    base = Model(4, 4, 20, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=10)
+    models = [base, base.with_(n_slices=40), base.with_(n_slices=25), base.with_(n_slices=30),
+              base.with_(n_slices=15), base.with_(lx=6, ly=6, n_slices=30)]
+    fields = [iid_field(m, 4300 + c) for c, m in enumerate(models)]
+    grp = slq.Group(models)
+    info = grp.describe()
+    got = sorted((b["N"], b["L"], b["L_min"], b["chains"]) for b in info["batches"])
+    assert got == [(16, 25, 15, 2), (16, 40, 20, 3), (36, 30, 30, 1)], got
+    s = dev(grp.pack(fields))
+    G = torch.empty(int(grp.g_off[-1]), dtype=torch.float64, device="cuda")
+    la = torch.empty(len(models), dtype=torch.float64, device="cuda")
+    sg = torch.empty(len(models), dtype=torch.int8, device="cuda")
+    st = torch.empty(len(models), dtype=torch.int32, device="cuda")
+    slq.slq_group_green(grp, s, G, la, sg, st)
+    G0, la0, sg0, st0 = host(G), host(la), host(sg), host(st)
+    for c, m in enumerate(models):
+        ref_la, ref_sg, ref_G = stable.green(m, fields[c])
+        Gc = G0[grp.g_off[c]:grp.g_off[c + 1]].reshape(m.n_sites, m.n_sites)
+        assert st0[c] == 0 and sg0[c] == ref_sg, c
+        assert abs(la0[c] - ref_la) < 1e-12 * max(1.0, abs(ref_la)), (c, la0[c], ref_la)
+        assert np.max(np.abs(Gc - ref_G)) < 1e-10, c
     grp.close()
