@@ -18,7 +18,9 @@ structured slice products of a block of 10 slices, FP64 on the vector ALUs,
 timed with HIP events on its stream over the timed region), the CPU oracle
 timed on a bounded sample of the same workload, and untimed-for-value
 details: acceptance, Green's-function evaluations/s, local DQMC sweeps/s,
-uneven batches, the chain products of each precision mode at 40x40, and the
+uneven batches, the chain products of each precision mode at 40x40, the
+48x48 workload's exact weights and cumulative updates (linear and learned
+proposals), and the
 effective samples per second of self-learning DQMC against local FP64 DQMC
 with as many chains: with the linear effective action and FP64 judge, with
 FP32 chain products in the judge (its error stated), and with proposals from
@@ -265,6 +267,65 @@ def local_sweep_rate(slq, plan, model, sweeps, seed):
 PRECISION_PEAK_TFLOPS = {0: 78.6, 3: 78.6, 1: 157.3, 2: 2500.0}  # FP64 vector / FP64, FP32, BF16 dense MFMA
 
 
+def learned_48x48_rates(slq, fields: int = 16):
+    """The largest workload, 48x48 (N = 2304), L = 100: exact weights per
+    second of `fields` fields, and cumulative updates per second of the same
+    chains with N L single-flip proposals each (one effective sweep), proposed
+    by the linear action and by the linear action plus the network (FP32, its
+    output layer at zero so the proposals are those of the linear part; the
+    network's forward passes and flip differences are all computed)."""
+    import numpy as np
+    import torch
+    from slq_inputs import LEARNED_48x48, iid_fields, default_terms, net_init
+    dev = torch.device("cuda")
+    model = LEARNED_48x48
+    F, N, L = fields, model.n_sites, model.n_slices
+    plan = slq.Plan(model, F)
+    slq.slq_plan_tune(plan, F)
+    s = torch.from_numpy(iid_fields(model, F, 6200)).to(dev)
+    la = torch.empty(F, dtype=torch.float64, device=dev)
+    sg = torch.empty(F, dtype=torch.int8, device=dev)
+    st = torch.empty(F, dtype=torch.int32, device=dev)
+    slq.slq_weight(plan, s, la, sg, st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    slq.slq_weight(plan, s, la, sg, st)
+    torch.cuda.synchronize()
+    t_w = time.perf_counter() - t0
+    terms = default_terms(L)
+    eff = slq.Eff(plan, terms, np.zeros(len(terms)))
+    acc = torch.empty(F, dtype=torch.int8, device=dev)
+    logA = torch.empty(F, dtype=torch.float64, device=dev)
+
+    def steps_per_s(n_moves, step0):
+        slq.slq_cumulative_step(plan, eff, s, la, sg, n_moves, 11, step0, 0, acc, logA, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        slq.slq_cumulative_step(plan, eff, s, la, sg, n_moves, 11, step0 + 1, 0, acc, logA, st)
+        torch.cuda.synchronize()
+        return F / (time.perf_counter() - t0)
+
+    lin = steps_per_s(eff.n_classes, 0)
+    prm = torch.from_numpy(net_init(12)).to(dev)
+    prm[1960:] = 0.0
+    slq.slq_eff_set_net(eff, prm, slq.SLQ_PREC_FP32)
+    net = steps_per_s(slq.slq_eff_net_classes(eff), 10)
+    S = torch.empty(F, dtype=torch.float64, device=dev)
+    slq.slq_net_forward(plan, slq.SLQ_PREC_FP32, s, prm, S)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    slq.slq_net_forward(plan, slq.SLQ_PREC_FP32, s, prm, S)
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    ok = bool((st == 0).all().item())
+    eff.close()
+    plan.close()
+    torch.cuda.empty_cache()
+    return {"model": "48x48, L=100", "fields": F, "weights_per_s": F / t_w,
+            "cumulative_steps_per_s_linear": lin, "cumulative_steps_per_s_learned": net,
+            "proposals_per_step": N * L, "net_forward_samples_per_s": F / t_f, "status_ok": ok}
+
+
 def precision_rates(slq, fields: int = 32):
     """Chain products of the 40x40, L=100 model (dtau 0.1, xi 1.5, n_s 10) in
     each precision mode: exact weights per second of `fields` fields and the
@@ -479,6 +540,7 @@ def main():
         details["dqmc_max_drift"] = float(drift.max().item())
         details["group_64_uneven"] = group_rate(slq, dev)
         details["precision_40x40"] = precision_rates(slq)
+        details["learned_48x48"] = learned_48x48_rates(slq)
     if not args.no_ess and not args.no_details:
         details["ess"] = ess_rates(slq, plan, model, terms, seed, args.ess_steps, args.ess_dqmc_chains or B,
                                    args.ess_sweeps, args.ess_burn)

@@ -247,3 +247,14 @@ def test_every_block_width_keeps_parity(slq, model):
             slq.slq_plan_set_block_width(plan, bad)
     slq.slq_plan_set_block_width(plan, 0)
     plan.close()
+
+
+def test_48x48_L100_parity(slq):
+    """The largest workload (48x48, N = 2304, L = 100, structured products on
+    generic 48-point lines, blocked QR with 8-column panels) against the oracle
+    on one field."""
+    from slq_inputs import LEARNED_48x48
+    m = LEARNED_48x48
+    f = iid_field(m, 6100)
+    G, la, sg, st = gpu_green(slq, m, [f])
+    check_parity(m, [f], G, la, sg, st)
