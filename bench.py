@@ -267,7 +267,7 @@ def local_sweep_rate(slq, plan, model, sweeps, seed):
 PRECISION_PEAK_TFLOPS = {0: 78.6, 3: 78.6, 1: 157.3, 2: 2500.0}  # FP64 vector / FP64, FP32, BF16 dense MFMA
 
 
-def learned_48x48_rates(slq, fields: int = 16):
+def learned_48x48_rates(slq, fields: int = 64):
     """The largest workload, 48x48 (N = 2304), L = 100: exact weights per
     second of `fields` fields, and cumulative updates per second of the same
     chains with N L single-flip proposals each (one effective sweep), proposed
