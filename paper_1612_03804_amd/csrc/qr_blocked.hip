@@ -153,6 +153,46 @@ __global__ __launch_bounds__(PQ_THREADS) void k_prepivot(int N, const double* __
 }
 
 // --------------------------------------------------------------- panel ----
+// Sums over the wave of 2 or 4 values at once.  The lane-swap instructions of
+// gfx950 fold the halves and then the 16-lane rows of two values into one
+// register (permlane32_swap exchanges the upper 32 lanes of its first operand
+// with the lower 32 of its second, permlane16_swap the odd rows of the first
+// with the even rows of the second), so that each row holds one value's
+// partial sums; DPP moves finish the rows.  Every lane returns the same sums.
+__device__ __forceinline__ double pq_fold32(double x, double y) {
+  // lanes 0-31: x[l] + x[l + 32]; lanes 32-63: y[l - 32] + y[l]
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ double pq_fold16(double x, double y) {
+  // rows 0 and 2: x's rows (0, 1) and (2, 3) summed; rows 1 and 3: y's
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ double pq_row_sum(double v) {
+  v += dpp_move<DPP_QUAD_XOR1>(v);
+  v += dpp_move<DPP_QUAD_XOR2>(v);
+  v += dpp_move<DPP_ROW_ROR4>(v);
+  return v + dpp_move<DPP_ROW_ROR8>(v);
+}
+template <int C>
+__device__ __forceinline__ void pq_wave_sums(double (&s)[C]) {
+  static_assert(C == 1 || C == 2 || C == 4, "2 or 4 values, or one");
+  if constexpr (C == 1) {
+    s[0] = wave_sum(s[0]);
+  } else if constexpr (C == 2) {
+    const double r = pq_row_sum(pq_fold16(pq_fold32(s[0], s[1]), pq_fold32(s[0], s[1])));
+    s[0] = read_lane(r, 0);   // rows 0, 1
+    s[1] = read_lane(r, 32);  // rows 2, 3
+  } else {
+    const double r = pq_row_sum(pq_fold16(pq_fold32(s[0], s[2]), pq_fold32(s[1], s[3])));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] = read_lane(r, 16 * q);  // row q
+  }
+}
+
 struct PanelArgs {
   int N, j0, nbw;
   double* W;       // [b][N][N]: panel columns j0..j0+nbw, rows j0..N-1 (in: A, out: R above / V below)
@@ -296,23 +336,29 @@ __global__ __launch_bounds__(PQ_THREADS) __attribute__((amdgpu_waves_per_eu(NB =
 #pragma unroll
       for (int k = 0; k < RPL; ++k) vr[k] = vrow(k);
     }
+    // the dot products v_c . col of the owned columns, reduced together
+    double s[CPW];
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) t += (CACHE_V ? vr[k] : vrow(k)) * col[q][k];
+      s[q] = t;
+    }
+    pq_wave_sums<CPW>(s);
 #pragma unroll
     for (int q = 0; q < CPW; ++q) {
       const int c2 = wave + PQ_WAVES * q;
       if (c2 >= nbw) continue;
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < RPL; ++k) s += (CACHE_V ? vr[k] : vrow(k)) * col[q][k];
-      s = wave_sum(s);
       if (c2 > c) {  // apply H_c
         if (tc != 0.0) {
-          s *= tc;
+          const double st = s[q] * tc;
 #pragma unroll
-          for (int k = 0; k < RPL; ++k) col[q][k] -= s * (CACHE_V ? vr[k] : vrow(k));
+          for (int k = 0; k < RPL; ++k) col[q][k] -= st * (CACHE_V ? vr[k] : vrow(k));
         }
         if (c2 == c + 1) reflect(q, c2);
       } else if (c2 < c) {  // finished column: Gram entry v_{c2} . v_c
-        if (lane == 0) Gm[c2 * LT + c] = s;
+        if (lane == 0) Gm[c2 * LT + c] = s[q];
       }
     }
   }
