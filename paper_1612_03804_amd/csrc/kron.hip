@@ -132,9 +132,9 @@ __device__ __forceinline__ void line_product_sym(double* __restrict__ S, int bas
 // all H lanes run the same instructions with the same coefficients.  The H
 // lanes sit side by side in one wavefront, whose reads of the line all
 // complete before its first write, so the in-place update needs no barrier.
-template <int P, int STRIDE, int DSTRIDE, int H, int SCALE>
-__device__ __forceinline__ void line_product_symc(double* __restrict__ S, int base, cdptr w,
-                                                  const double* __restrict__ dl, int dbase, int h) {
+template <int P, int STRIDE, int DSTRIDE, int H, int SCALE, class Coef>
+__device__ __forceinline__ void line_product_symc(double* __restrict__ S, int base, const Coef& cv,
+                                                  const double* __restrict__ dl, int dbase, int h, double f = 1.0) {
   static_assert(P % H == 0, "the lanes of a line split its outputs evenly");
   const int rb = base + h * STRIDE, rdb = dbase + h * DSTRIDE;
   double r[P];
@@ -160,13 +160,14 @@ __device__ __forceinline__ void line_product_symc(double* __restrict__ S, int ba
     for (int x = 0; x < P; ++x)
 #pragma unroll
       for (int q = 0; q < OB; ++q) {
-        const int d = ((H * (k0 + q) - x) % P + P) % P;  // coefficient c[d] = w[P - 1 - d], c symmetric
-        acc[q] = fma(w[P - 1 - (d <= P / 2 ? d : P - d)], r[x], acc[q]);
+        const int d = ((H * (k0 + q) - x) % P + P) % P;  // coefficient c[d], c symmetric
+        acc[q] = fma(cv(d <= P / 2 ? d : P - d), r[x], acc[q]);
       }
 #pragma unroll
     for (int q = 0; q < OB; ++q) {
       double v = acc[q];
       if constexpr (SCALE == 2) v *= dl[rdb + H * (k0 + q) * DSTRIDE];
+      if constexpr (SCALE == 3) v *= f;
       S[rb + H * (k0 + q) * STRIDE] = v;
     }
   }
@@ -199,8 +200,7 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
   const int tid = threadIdx.x, nt = blockDim.x;  // nt is a multiple of 64, nb <= 32
   const int c = tid & (nb - 1);  // the vector of this thread in loads and stores
   const double dpos = a.consts[a.inv ? 1 : 0], dneg = a.consts[a.inv ? 0 : 1];  // d for s = +1, -1
-  // distinct circulant values c[d] = w[P - 1 - d], d = 0..P/2 (exact lines only;
-  // the compile-time path reads them from the constant window as it goes)
+  // distinct circulant values c[d] = w[P - 1 - d], d = 0..P/2 (exact lines only)
   double cx[P / 2 + 1], cy[P / 2 + 1];
   if constexpr (NBT == 0 && EXACT && P <= 32) {
 #pragma unroll
@@ -209,6 +209,21 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
       cy[d] = ((cdptr)a.wy)[P - 1 - d];
     }
   }
+  // compile-time path (square lattice): the x and y lines share one circulant,
+  // the y window's (the x window is e^{+-dtau mu} times it), read once into
+  // scalar registers; the scalar e^{+-dtau mu} rides on the field factors d_l
+  // (or on the x-line outputs when there are none)
+  // (up to P = 24: beyond, the registers run short and the values are read
+  // from the constant windows as the products go)
+  constexpr bool CREG = NBT > 0 && P <= 24;
+  double cw[CREG ? P / 2 + 1 : 1];
+  double fmu = 1.0;
+  if constexpr (CREG) {
+#pragma unroll
+    for (int d = 0; d <= P / 2; ++d) cw[d] = ((cdptr)a.wy)[P - 1 - d];
+    fmu = a.consts[a.inv ? 3 : 2];
+  }
+  const double dposl = dpos * fmu, dnegl = dneg * fmu;
   const int b = lin / a.nvb;
   // a field whose chain starts at a later block passes X (the identity) through
   const bool idle = a.first_block && a.block < a.first_block[b];
@@ -279,7 +294,7 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
           const int i = tid + q * NTF;
-          if (i < N) dl[i] = spn[q] > 0 ? dpos : dneg;
+          if (i < N) dl[i] = spn[q] > 0 ? dposl : dnegl;
         }
         if (k + 1 < a.count) prefetch(spins(k + 1));
       } else {
@@ -292,20 +307,39 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
       static_assert(EXACT && P <= 32, "compile-time blocks need an exact lattice of side <= 32");
       constexpr int H = kron_lanes_per_line(P, NBT);
       const int t = tid / H, h = tid % H;
+      const auto creg = [&](int d) { return cw[d]; };
+      const auto cwx = [&](int d) { return ((cdptr)a.wx)[P - 1 - d]; };
+      const auto cwy = [&](int d) { return ((cdptr)a.wy)[P - 1 - d]; };
       if (t < P * NBT) {  // x-lines
         const int y = t / NBT, cl = t % NBT;
-        if (a.scale == 1)
-          line_product_symc<P, NBT, 1, H, 1>(S, y * ROWS + cl, (cdptr)a.wx, dl, y * P, h);
-        else
-          line_product_symc<P, NBT, 1, H, 0>(S, y * ROWS + cl, (cdptr)a.wx, dl, y * P, h);
+        if constexpr (CREG) {
+          if (a.scale == 1)
+            line_product_symc<P, NBT, 1, H, 1>(S, y * ROWS + cl, creg, dl, y * P, h);
+          else if (a.scale == 2)
+            line_product_symc<P, NBT, 1, H, 0>(S, y * ROWS + cl, creg, dl, y * P, h);
+          else
+            line_product_symc<P, NBT, 1, H, 3>(S, y * ROWS + cl, creg, dl, y * P, h, fmu);
+        } else {
+          if (a.scale == 1)
+            line_product_symc<P, NBT, 1, H, 1>(S, y * ROWS + cl, cwx, dl, y * P, h);
+          else
+            line_product_symc<P, NBT, 1, H, 0>(S, y * ROWS + cl, cwx, dl, y * P, h);
+        }
       }
       __syncthreads();
       if (t < P * NBT) {  // y-lines
         const int x = t / NBT, cl = t % NBT;
-        if (a.scale == 2)
-          line_product_symc<P, ROWS, P, H, 2>(S, x * NBT + cl, (cdptr)a.wy, dl, x, h);
-        else
-          line_product_symc<P, ROWS, P, H, 0>(S, x * NBT + cl, (cdptr)a.wy, dl, x, h);
+        if constexpr (CREG) {
+          if (a.scale == 2)
+            line_product_symc<P, ROWS, P, H, 2>(S, x * NBT + cl, creg, dl, x, h);
+          else
+            line_product_symc<P, ROWS, P, H, 0>(S, x * NBT + cl, creg, dl, x, h);
+        } else {
+          if (a.scale == 2)
+            line_product_symc<P, ROWS, P, H, 2>(S, x * NBT + cl, cwy, dl, x, h);
+          else
+            line_product_symc<P, ROWS, P, H, 0>(S, x * NBT + cl, cwy, dl, x, h);
+        }
       }
     } else if constexpr (EXACT && P <= 32) {
       if (tid < ly * nb) {  // x-lines: entries y lx + x, x = 0..lx-1
