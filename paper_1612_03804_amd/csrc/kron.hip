@@ -187,10 +187,12 @@ __device__ __forceinline__ int kron_item(int g) { return (g & ~15) | ((g & 7) <<
 
 // NBT > 0: NBT vectors per workgroup and an exact P x P lattice, fixed at
 // compile time, so that every LDS address of the line products is a base
-// plus an instruction offset and every global load of a thread is in flight
+// plus an instruction offset (with 8 vectors and P <= 20 at most 72 VGPRs,
+// seven wavefronts per SIMD: at 20 x 20 the five workgroups whose blocks fit
+// in LDS are then resident together) and every global load of a thread is in flight
 // before the first is waited for; NBT = 0: sizes from the arguments.
 template <int P, bool EXACT, int NBT>
-__global__ __launch_bounds__(P >= 32 ? 512 : 1024) void k_kron(KronDev a) {
+__global__ __launch_bounds__(P >= 32 ? 512 : 1024) __attribute__((amdgpu_waves_per_eu(NBT == 8 && P <= 20 ? 7 : 1))) void k_kron(KronDev a) {
   extern __shared__ double S[];  // [N][nb], then d_l [2][N] (alternating slices)
   const int lin = kron_item((int)blockIdx.x);
   if (lin >= a.nvb * a.batch) return;
