@@ -99,6 +99,23 @@ def local_fields(model, terms, s):
     return h.reshape(len(terms), L, lx * ly)
 
 
+def local_fields_slice(model, terms, s, l: int):
+    """h[k, i] = h_k((i, l)) at one slice l (1-based): the same partner sums as
+    local_fields, taken only from the slices l and l +- dl that slice l's
+    partners lie on."""
+    L, lx, ly = model.n_slices, model.lx, model.ly
+    s3 = np.asarray(s, dtype=np.float64).reshape(L, ly, lx)
+    h = np.zeros((len(terms), ly, lx))
+    for k, (r, dl) in enumerate(terms):
+        if r == 0 and dl == 0:
+            h[k] = 1.0
+            continue
+        for dx, dy in shell_offsets(r):
+            for sg in ((0,) if dl == 0 else (1, -1)):
+                h[k] += np.roll(s3[(l - 1 + sg * dl) % L], shift=(-dy, -dx), axis=(0, 1))
+    return h.reshape(len(terms), lx * ly)
+
+
 def local_fields_bruteforce(model, terms, s):
     """Same as local_fields, by summing the explicit partner lists (small cases)."""
     n, L = model.n_sites, model.n_slices
@@ -187,8 +204,8 @@ def effective_move(model, terms, lam, s, classes, *, seed, step, move, chain=0, 
     key = (seed, TAG_EFFECTIVE)
     cls = below(len(classes), (0, move, step, chain), key)
     l, sites = classes[cls]
-    hsum = np.tensordot(np.asarray(lam, dtype=np.float64), local_fields(model, terms, s), axes=1)
-    ds = [-2.0 * float(s[l - 1, i]) * float(hsum[l - 1, i]) for i in sites]   # pre-move field
+    hsum = np.tensordot(np.asarray(lam, dtype=np.float64), local_fields_slice(model, terms, s, l), axes=1)
+    ds = [-2.0 * float(s[l - 1, i]) * float(hsum[i]) for i in sites]   # pre-move field
     if net_params is not None:
         from . import net
         ds = [d + net.flip_delta(net_params, model, s, i, l) for d, i in zip(ds, sites)]

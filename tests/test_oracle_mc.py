@@ -93,6 +93,14 @@ def test_local_fields_vectorised_equals_partner_lists():
     a = effective.local_fields(m, terms, s)
     b = effective.local_fields_bruteforce(m, terms, s)
     assert np.array_equal(a, b)
+    for l in range(1, m.n_slices + 1):
+        assert np.array_equal(effective.local_fields_slice(m, terms, s, l), b[:, l - 1])
+    m2 = Model(5, 3, 9, xi=1.0)
+    terms2 = default_terms(9) + [(2, 3), (5, 4)]
+    s2 = iid_field(m2, 22)
+    b2 = effective.local_fields_bruteforce(m2, terms2, s2)
+    for l in range(1, m2.n_slices + 1):
+        assert np.array_equal(effective.local_fields_slice(m2, terms2, s2, l), b2[:, l - 1])
 
 
 def test_flip_delta_equals_action_difference():

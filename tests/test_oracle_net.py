@@ -69,6 +69,44 @@ def test_adam_matches_formula():
     assert np.allclose(p1, p - 0.1 * np.sign(g) * np.abs(g) / (np.abs(g) + 1e-8), atol=1e-12)
 
 
+def test_adam_constant_gradient_steps():
+    """With a constant gradient g and zero initial moments, the bias-corrected
+    moments are exactly g and g^2 at every step t, so each of the first steps
+    moves a parameter by lr * g / (|g| + eps).  A wrong power in either bias
+    correction (e.g. (1 - beta1)^t) breaks this from t = 2 on."""
+    p = np.array([1.0, -2.0, 0.25, 3.0])
+    g = np.array([0.5, -0.1, 2.0, -1e-3])
+    m = np.zeros(4)
+    v = np.zeros(4)
+    lr, eps = 0.05, 1e-8
+    for t in range(1, 6):
+        p_new, m, v = net.adam(p, g, m, v, t, lr=lr, eps=eps)
+        np.testing.assert_allclose(p_new, p - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-13)
+        p = p_new
+
+
+def test_adam_moments_are_weighted_sums():
+    """The moment recursions written out: after steps with gradients g_1..g_t,
+    m_t = (1 - b1) sum_k b1^(t-k) g_k and v_t = (1 - b2) sum_k b2^(t-k) g_k^2;
+    the update divides them by 1 - b^t.  Checked over five steps of changing
+    gradients (signs and sizes differ from step to step)."""
+    b1, b2, lr, eps = 0.9, 0.999, 1e-2, 1e-8
+    gs = [np.array([0.3, -1.0]), np.array([-0.7, 0.2]), np.array([1.5, 0.0]), np.array([0.1, 4.0]),
+          np.array([-2.0, -0.5])]
+    p = np.array([0.0, 1.0])
+    m = np.zeros(2)
+    v = np.zeros(2)
+    for t in range(1, 6):
+        p_new, m, v = net.adam(p, gs[t - 1], m, v, t, lr=lr, beta1=b1, beta2=b2, eps=eps)
+        ms = (1 - b1) * sum(b1 ** (t - k) * gs[k - 1] for k in range(1, t + 1))
+        vs = (1 - b2) * sum(b2 ** (t - k) * gs[k - 1] ** 2 for k in range(1, t + 1))
+        np.testing.assert_allclose(m, ms, rtol=1e-14, atol=1e-16)
+        np.testing.assert_allclose(v, vs, rtol=1e-14, atol=1e-16)
+        step = lr * (ms / (1 - b1 ** t)) / (np.sqrt(vs / (1 - b2 ** t)) + eps)
+        np.testing.assert_allclose(p_new, p - step, rtol=0, atol=1e-14)
+        p = p_new
+
+
 def test_single_flip_delta():
     m = Model(5, 5, 6)
     p = net_init(6, scale=1.5)
