@@ -56,7 +56,9 @@ enum {
 enum {
   SLQ_ST_BAD_SPIN = 1,    /* a field entry is not +-1 */
   SLQ_ST_NONFINITE = 2,   /* a non-finite value appeared in the stabilised chain */
-  SLQ_ST_SINGULAR = 4     /* the final matrix M has a zero pivot (W_f = 0) */
+  SLQ_ST_SINGULAR = 4,    /* the final matrix M has a zero pivot (W_f = 0) */
+  SLQ_ST_PIVOT = 8        /* internal check: an LU pivot index outside the rows below the
+                             diagonal was refused (that interchange skipped); not expected */
 };
 
 /* How the chain product X <- E diag(d_l) X is formed.  The QR/UDV
@@ -92,16 +94,36 @@ const char* slq_version(void);
 const char* slq_last_error(void);
 
 /*
- * slq_plan_create - allocate device workspace for `model` and up to
- * `max_batch` simultaneous fields on the current HIP device, and build
- * E = exp(-dtau K) and E^{-1} there (closed form: K is diagonal in lattice
- * momentum, so E is e^{dtau mu} times the Kronecker product of two circulant
- * 1-D propagators).  Model definition: "Basics of DQMC" (B^tau = exp(dtau K)
- * exp(V)) with the sign conventions at the top of this header.
- * Synchronous.  *out receives the plan; free it with slq_plan_destroy.
- * Errors: SLQ_ERR_ARG (sizes), SLQ_ERR_DEVICE (allocation / launch failure).
+ * Plans.  A plan holds the device workspace for `model` and up to `max_batch`
+ * simultaneous fields: E = exp(-dtau K) and E^{-1} (built there from the
+ * closed form: K is diagonal in lattice momentum, so E is e^{dtau mu} times
+ * the Kronecker product of two circulant 1-D propagators; model definition:
+ * "Basics of DQMC", B^tau = exp(dtau K) exp(V), with the sign conventions at
+ * the top of this header), the chain and factorisation buffers, and, by
+ * flag, the buffers of local sweeps and of the learned action.  No call on a
+ * plan allocates device memory afterwards.
+ *
+ * Flags: SLQ_PLAN_SWEEPS adds the stacked partial products of
+ * slq_sweep_local ((floor((L-1)/n_stab) + 1) * max_batch * (2N^2 + N)
+ * doubles); SLQ_PLAN_NET adds the activations of the network calls
+ * (6 * 8 * L * N * max_batch doubles and small per-field arrays).  Calls that
+ * need a section the plan was created without return SLQ_ERR_WORKSPACE.
+ *
+ * slq_plan_workspace_size - *bytes = the workspace size for (model,
+ * max_batch, flags).  Host only.
+ * slq_plan_create - create the plan on the current HIP device.  With d_work
+ * != NULL the plan lives in that caller-owned device memory (256-byte
+ * aligned, at least the queried size; the caller frees it after
+ * slq_plan_destroy) and the library allocates nothing; with d_work == NULL
+ * the plan allocates the workspace once, here, and frees it in
+ * slq_plan_destroy.  Synchronous (E is built before it returns).  *out
+ * receives the plan.  Errors: SLQ_ERR_ARG (sizes, flags, alignment),
+ * SLQ_ERR_WORKSPACE (work_bytes too small), SLQ_ERR_DEVICE.
  */
-int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out);
+enum { SLQ_PLAN_SWEEPS = 1, SLQ_PLAN_NET = 2 };
+int slq_plan_workspace_size(const slq_model* model, int32_t max_batch, int32_t flags, size_t* bytes);
+int slq_plan_create(const slq_model* model, int32_t max_batch, int32_t flags, void* d_work, size_t work_bytes,
+                    slq_plan** out);
 int slq_plan_destroy(slq_plan* plan);
 /* Device bytes held by the plan. */
 int slq_plan_bytes(const slq_plan* plan, size_t* bytes);
@@ -128,16 +150,28 @@ int slq_plan_set_block_width(slq_plan* plan, int32_t width);
 int slq_kinetic(slq_plan* plan, int32_t inverse, double* d_out, hipStream_t stream);
 
 /*
- * Kernel timing of the chain product, the dominant kernel of every exact
- * evaluation (X <- E diag(d_l) X for all fields of a batch, one launch per
- * slice; Eq. 1's B(beta,0) as products of B^tau).  While enabled, HIP events
- * are recorded on the call's stream around each such launch.  slq_profile_read
- * waits for those events and returns their summed duration in ms, the number
- * of launches and the algorithmic flops (2 N^3 per field per launch), then
- * clears the record.  Enabling also clears it.  Host-side only, synchronous.
+ * Kernel timing of the three parts of every exact evaluation, on the call's
+ * stream (Eq. 1's B(beta,0) as products of B^tau, then stabilised):
+ *   SLQ_PROFILE_CHAIN   the chain products: one launch per block of n_stab
+ *                       slices (structured FP64: 2 N^2 (lx+ly) flops per slice
+ *                       and field) or per slice (dense GEMMs: 2 N^3);
+ *   SLQ_PROFILE_STAB    each stabilisation: the QR of X diag(D) with its
+ *                       explicit Q ((8/3) N^3 flops per field) and the V
+ *                       update (N^3; none for the first block);
+ *   SLQ_PROFILE_FINISH  the final step: with G an LU and two triangular
+ *                       solves ((8/3) N^3), without G a QR of M ((4/3) N^3,
+ *                       (2/3) N^3 where the LU serves, N <= 64).
+ * The flop counts are algorithmic (what the factorisations need), not what
+ * the kernels issue.  While enabled, HIP events are recorded around each
+ * such sequence.  slq_profile_read_part waits for one part's events and
+ * returns their summed duration in ms, the number of sequences and the
+ * flops, then clears that part's record; slq_profile_read is the chain
+ * part.  Enabling also clears the records.  Host-side only, synchronous.
  */
+enum { SLQ_PROFILE_CHAIN = 0, SLQ_PROFILE_STAB = 1, SLQ_PROFILE_FINISH = 2 };
 int slq_profile_enable(slq_plan* plan, int32_t enable);
 int slq_profile_read(slq_plan* plan, double* ms, int64_t* launches, double* flops);
+int slq_profile_read_part(slq_plan* plan, int32_t part, double* ms, int64_t* launches, double* flops);
 
 /*
  * slq_weight - exact fermion weight of Eq. 1 for `batch` fields:
@@ -226,10 +260,9 @@ int slq_group_green(slq_group* group, const int8_t* d_s, double* d_G, double* d_
  * the stabilised product B_l...B_1 (extended block by block as the sweep
  * moves up) with a stabilised B_L...B_{l+1} (built for every boundary when
  * the sweep starts), so a sweep costs O(L N^3) rather than O(L^2 N^3 / n_stab).
- * The first call with a given batch allocates that stack of partial products,
- * (floor((L-1)/n_stab) + 1) * batch * (2N^2 + N) doubles, kept until the plan
- * is destroyed (SLQ_ERR_DEVICE if it cannot); products are FP64 whatever the
- * plan's chain precision.
+ * That stack of partial products lives in the plan's workspace, so the plan
+ * must have been created with SLQ_PLAN_SWEEPS (else SLQ_ERR_WORKSPACE);
+ * products are FP64 whatever the plan's chain precision.
  * u: key (seed, 1), counter (i, l-1, sweep0 + k, chain0 + b) for sweep k.
  * In/out: d_s [batch][L][N]; d_G [batch][N][N] must hold G of the incoming
  * fields (from slq_green) and holds G of the outgoing ones; d_logabs and
@@ -266,10 +299,19 @@ int slq_sweep_local(slq_plan* plan, int32_t batch, int8_t* d_s, double* d_G,
  */
 typedef struct slq_eff slq_eff;
 
-/* Create from host arrays terms [n_terms][2] = (r, dl), lambda [n_terms], c0.
- * Builds the colour classes and copies the tables to the device; synchronous. */
+/* slq_eff_workspace_size - *bytes = device bytes of an effective model with
+ * n_terms terms on `plan` (its tables, and room for an attached network's
+ * parameters and move colouring).  Host only.
+ * slq_eff_create - from host arrays terms [n_terms][2] = (r, dl),
+ * lambda [n_terms], c0.  Builds the colour classes and copies the tables to
+ * the device, into caller-owned device memory d_work (256-byte aligned, at
+ * least the queried size) or, with d_work == NULL, into memory it allocates
+ * once here and frees in slq_eff_destroy.  No later call on the model
+ * allocates.  Synchronous.  Errors: SLQ_ERR_ARG, SLQ_ERR_WORKSPACE
+ * (work_bytes too small), SLQ_ERR_DEVICE. */
+int slq_eff_workspace_size(const slq_plan* plan, int32_t n_terms, size_t* bytes);
 int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms,
-                   const double* lambda, double c0, slq_eff** out);
+                   const double* lambda, double c0, void* d_work, size_t work_bytes, slq_eff** out);
 int slq_eff_destroy(slq_eff* eff);
 /* Number of colour classes (n_colours * L). */
 int slq_eff_classes(const slq_eff* eff, int32_t* n_classes);
@@ -308,6 +350,8 @@ int slq_eff_features(slq_plan* plan, const slq_eff* eff, int32_t batch,
  */
 #define SLQ_NET_PARAMS 1969
 
+/* The network calls below need a plan created with SLQ_PLAN_NET (else
+ * SLQ_ERR_WORKSPACE). */
 /* d_S[b] = S_net(s_b). */
 int slq_net_forward(slq_plan* plan, int32_t net_prec, int32_t batch, const int8_t* d_s,
                     const double* d_params, double* d_S, hipStream_t stream);
@@ -331,6 +375,11 @@ int slq_net_adam(int32_t n, double* d_params, const double* d_grad, double* d_m,
  * sites of a class are disjoint), one class drawn uniformly per move as
  * before; Eq. 4 uses S_net(s') - S_net(s) from full forward passes.  Needs
  * lx, ly, L >= 5.  The colouring is built on the first attach (synchronous).
+ * net_prec must be SLQ_PREC_FP64 (else SLQ_ERR_ARG): the moves keep the
+ * network's activations up to date incrementally, and only in FP64 does a
+ * move and its reverse change the action by negatives up to round-off, which
+ * Eq. 4's acceptance needs to stay exact.  Training and the forward and
+ * gradient calls above may run in FP32.
  */
 int slq_eff_set_net(slq_eff* eff, const double* d_params, int32_t net_prec, hipStream_t stream);
 /* Number of move classes while a network is attached. */
@@ -359,7 +408,10 @@ int slq_cumulative_step(slq_plan* plan, const slq_eff* eff, int32_t batch,
  * [n_samples][L][N].  Writes d_theta [1 + n_terms] = (c0, lambda_1..K) and
  * d_r2 [1] = 1 - sum (y - yhat)^2 / sum (y - ybar)^2 (the paper's R^2 score,
  * "Results").  Needs n_samples >= n_terms + 2.  A singular system leaves
- * d_theta as NaN.  Device work only; does not change `eff`.
+ * d_theta as NaN.  Device work only; does not change `eff`.  Any n_samples:
+ * the features are computed max_batch fields at a time into the plan's
+ * buffers (two passes: sums, then the residuals of R^2), so nothing is
+ * allocated.
  */
 int slq_fit_effective(slq_plan* plan, const slq_eff* eff, int64_t n_samples,
                       const int8_t* d_S, const double* d_logabs,

@@ -103,24 +103,29 @@ int check_batch(const Plan& p, long batch) {
   return SLQ_OK;
 }
 
-// One chain-product launch (a block of X <- E diag(d_l) X), bracketed by events when timing is on.
-template <typename F>
-static int timed_chain(Plan& p, double flops, hipStream_t st, F launch) {
+// A launch sequence of one profiled part, bracketed by events when timing is on.
+int timed_part(Plan& p, int part, double flops, hipStream_t st, const std::function<int()>& launch) {
   if (!p.prof) return launch();
-  if (p.ev_used + 2 > p.ev.size()) {
+  std::vector<hipEvent_t>& ev = p.ev[part];
+  if (p.ev_used[part] + 2 > ev.size()) {
     for (int k = 0; k < 64; ++k) {
       hipEvent_t e;
       SLQ_HIP(hipEventCreate(&e));
-      p.ev.push_back(e);
+      ev.push_back(e);
     }
   }
-  hipEvent_t a = p.ev[p.ev_used], b = p.ev[p.ev_used + 1];
-  p.ev_used += 2;
+  hipEvent_t a = ev[p.ev_used[part]], b = ev[p.ev_used[part] + 1];
+  p.ev_used[part] += 2;
   SLQ_HIP(hipEventRecord(a, st));
   int rc = launch();
   SLQ_HIP(hipEventRecord(b, st));
-  p.prof_flops += flops;
+  p.prof_flops[part] += flops;
   return rc;
+}
+
+template <typename F>
+static int timed_chain(Plan& p, double flops, hipStream_t st, F launch) {
+  return timed_part(p, SLQ_PROFILE_CHAIN, flops, st, launch);
 }
 
 static int timed_chain_gemm(Plan& p, const GemmArgs& g, hipStream_t st) {
@@ -266,19 +271,108 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
       cur = (double*)o32;
       SLQ_TRY(launch_widen(c32, cur, NN * batch, st));
     }
-    if (N > 64) {
-      SLQ_TRY(launch_qr_blocked(p, batch, cur, status, st, kron ? p.xnorm2 : nullptr));
-    } else {
-      SLQ_TRY(launch_qr(p, batch, cur, status, st));
-    }
-    // V <- diag(1/D) triu(R) (Pi^T V)
-    if (!vprev)
-      SLQ_TRY(launch_first_v(p, batch, vnext, st));
-    else
-      SLQ_TRY(launch_v_update(p, batch, vprev, vnext, st));
+    // QR of X diag(D) (R and the explicit Q: (4/3) N^3 + (4/3) N^3 flops per
+    // field), then V <- diag(1/D) triu(R) (Pi^T V) (N^3; a permutation only
+    // for the first block)
+    const double n3 = (double)N * N * N;
+    const double stab_flops = batch * (8.0 / 3.0 * n3 + (vprev ? n3 : 0.0));
+    SLQ_TRY(timed_part(p, SLQ_PROFILE_STAB, stab_flops, st, [&]() -> int {
+      if (N > 64) {
+        SLQ_TRY(launch_qr_blocked(p, batch, cur, status, st, kron ? p.xnorm2 : nullptr));
+      } else {
+        SLQ_TRY(launch_qr(p, batch, cur, status, st));
+      }
+      if (!vprev) return launch_first_v(p, batch, vnext, st);
+      return launch_v_update(p, batch, vprev, vnext, st);
+    }));
     vprev = vnext;
     vnext = (vnext == p.V) ? p.Vt : p.V;
   }
+  return SLQ_OK;
+}
+
+// Byte layout of a plan's workspace, every block 256-byte aligned; with base
+// set, the plan's pointers are placed.  Returns the total size.
+size_t plan_layout(Plan& p, int32_t flags, char* base) {
+  const long N = p.n, NN = N * N, B = p.max_batch;
+  const slq_model* model = &p.m;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t oE32 = take(4 * NN), oE16 = take(2 * NN);
+  const size_t oE = take(8 * NN), oEi = take(8 * NN), oTab = take(8 * (2 * (model->lx + model->ly) + 8)),
+               oC = take(8 * 8);
+  const size_t oXa = take(8 * NN * B), oXb = take(8 * NN * B), oW = take(8 * NN * B), oU = take(8 * NN * B),
+               oV = take(8 * NN * B), oVt = take(8 * NN * B);
+  const size_t oD = take(8 * N * B), oID = take(8 * N * B), oT = take(8 * (N + 32) * 32 * B),
+               oXn = take(8 * N * B);
+  const size_t oPerm = take(4 * N * B), oNref = take(4 * B), oSt = take(4 * B), oNref2 = take(4 * B),
+               oSt2 = take(4 * B);
+  const size_t oSw = take((size_t)p.L * N * B), oDv = take(8 * B), oDv2 = take(8 * B), oIv = take(8 * B);
+  const size_t oX = take(8 * N * SWEEP_KD * B), oY = take(8 * N * SWEEP_KD * B), oA = take(8 * SWEEP_KD * B);
+  const size_t oFo = take(8 * 64 * B), oFn = take(8 * 64 * B), oSg = take(B), oKw = take(8 * 8 * 64);
+  const size_t oFit = take(8 * FIT_ACC_DOUBLES);
+  const size_t oQw = take(N > 64 ? 8 * (size_t)qr_workspace_per_field((int)N) * B : 8);
+  const size_t oStack = (flags & SLQ_PLAN_SWEEPS) ? take(stack_bytes_for(p, B)) : 0;
+  const size_t oNet = (flags & SLQ_PLAN_NET) ? take(net_bytes_for(p)) : 0;
+  if (!base) return off;
+  char* c = base;
+  p.bytes = off;
+  p.base = (double*)base;
+  p.E = (double*)(c + oE);
+  p.Einv = (double*)(c + oEi);
+  p.tabs = (double*)(c + oTab);
+  p.E32 = (float*)(c + oE32);
+  p.E16 = (void*)(c + oE16);
+  p.consts = (double*)(c + oC);
+  p.Xa = (double*)(c + oXa);
+  p.Xb = (double*)(c + oXb);
+  p.W = (double*)(c + oW);
+  p.U = (double*)(c + oU);
+  p.V = (double*)(c + oV);
+  p.Vt = (double*)(c + oVt);
+  p.D = (double*)(c + oD);
+  p.invD = (double*)(c + oID);
+  p.Tblk = (double*)(c + oT);
+  p.perm = (int32_t*)(c + oPerm);
+  p.xnorm2 = (double*)(c + oXn);
+  p.nref = (int32_t*)(c + oNref);
+  p.status = (int32_t*)(c + oSt);
+  p.nref2 = (int32_t*)(c + oNref2);
+  p.status2 = (int32_t*)(c + oSt2);
+  p.s_work = (int8_t*)(c + oSw);
+  p.dvec = (double*)(c + oDv);
+  p.dvec2 = (double*)(c + oDv2);
+  p.ivec = (int64_t*)(c + oIv);
+  p.dX = (double*)(c + oX);
+  p.dY = (double*)(c + oY);
+  p.dA = (double*)(c + oA);
+  p.F_old = (double*)(c + oFo);
+  p.F_new = (double*)(c + oFn);
+  p.sgn_work = (int8_t*)(c + oSg);
+  p.kron_w = (double*)(c + oKw);
+  p.fit_acc = (double*)(c + oFit);
+  p.qrws = (double*)(c + oQw);
+  p.stack = (flags & SLQ_PLAN_SWEEPS) ? (double*)(c + oStack) : nullptr;
+  p.stack_batch = (flags & SLQ_PLAN_SWEEPS) ? (int)B : 0;
+  p.net_base = (flags & SLQ_PLAN_NET) ? (void*)(c + oNet) : nullptr;
+  p.kron_P = kron_line_size(model->lx, model->ly);
+  return off;
+}
+
+// Build E, E^{-1}, the structured-product windows and the reduced-precision
+// copies of E in the placed workspace, and the host view of the network
+// buffers (asynchronous on st).
+int plan_init(Plan& p, hipStream_t st) {
+  const long NN = (long)p.n * p.n;
+  SLQ_TRY(launch_kinetic(p, st));
+  SLQ_TRY(launch_kron_windows(p, st));
+  SLQ_TRY(launch_narrow(p.E, p.E32, NN, st));
+  SLQ_TRY(launch_to_bf16(p.E32, p.E16, NN, st));
+  if (p.net_base) SLQ_TRY(bind_net(p));
   return SLQ_OK;
 }
 
@@ -306,11 +400,31 @@ extern "C" {
 const char* slq_version(void) { return "libslq 0.1 (gfx950)"; }
 const char* slq_last_error(void) { return g_err.c_str(); }
 
-int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
-  if (!out) return fail(SLQ_ERR_ARG, "out is NULL");
-  *out = nullptr;
+int slq_plan_workspace_size(const slq_model* model, int32_t max_batch, int32_t flags, size_t* bytes) {
+  if (!bytes) return fail(SLQ_ERR_ARG, "bytes is NULL");
+  *bytes = 0;
   SLQ_TRY(check_model(model));
   if (max_batch < 1) return fail(SLQ_ERR_ARG, "max_batch must be >= 1");
+  if (flags & ~(SLQ_PLAN_SWEEPS | SLQ_PLAN_NET)) return fail(SLQ_ERR_ARG, "unknown plan flags");
+  Plan p{};
+  p.m = *model;
+  p.n = model->lx * model->ly;
+  p.L = model->n_slices;
+  p.max_batch = max_batch;
+  *bytes = plan_layout(p, flags, nullptr);
+  return SLQ_OK;
+}
+
+int slq_plan_create(const slq_model* model, int32_t max_batch, int32_t flags, void* d_work, size_t work_bytes,
+                    slq_plan** out) {
+  if (!out) return fail(SLQ_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  SLQ_TRY(slq_plan_workspace_size(model, max_batch, flags, &need));
+  if (d_work && work_bytes < need)
+    return fail(SLQ_ERR_WORKSPACE, "workspace of " + std::to_string(work_bytes) + " bytes is smaller than the " +
+                                       std::to_string(need) + " the plan needs");
+  if (d_work && ((uintptr_t)d_work & 255)) return fail(SLQ_ERR_ARG, "d_work must be 256-byte aligned");
   int dev = 0, ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(SLQ_ERR_DEVICE, "no HIP device");
   SLQ_HIP(hipGetDevice(&dev));
@@ -322,74 +436,21 @@ int slq_plan_create(const slq_model* model, int32_t max_batch, slq_plan** out) {
   p.L = model->n_slices;
   p.max_batch = max_batch;
   p.device = dev;
-  const long N = p.n, NN = N * N, B = max_batch;
-  // byte layout, every block 256-byte aligned
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    size_t o = off;
-    off += (bytes + 255) / 256 * 256;
-    return o;
-  };
-  const size_t oE32 = take(4 * NN), oE16 = take(2 * NN);
-  const size_t oE = take(8 * NN), oEi = take(8 * NN), oTab = take(8 * (2 * (model->lx + model->ly) + 8)),
-               oC = take(8 * 8);
-  const size_t oXa = take(8 * NN * B), oXb = take(8 * NN * B), oW = take(8 * NN * B), oU = take(8 * NN * B),
-               oV = take(8 * NN * B), oVt = take(8 * NN * B);
-  const size_t oD = take(8 * N * B), oID = take(8 * N * B), oT = take(8 * (N + 32) * 32 * B),
-               oXn = take(8 * N * B);
-  const size_t oPerm = take(4 * N * B), oNref = take(4 * B), oSt = take(4 * B);
-  const size_t oSw = take((size_t)p.L * N * B), oDv = take(8 * B), oDv2 = take(8 * B), oIv = take(8 * B);
-  const size_t oX = take(8 * N * SWEEP_KD * B), oY = take(8 * N * SWEEP_KD * B), oA = take(8 * SWEEP_KD * B);
-  const size_t oFo = take(8 * 64 * B), oFn = take(8 * 64 * B), oSg = take(B), oKw = take(8 * 8 * 64);
-  const size_t oQw = take(N > 64 ? 8 * (size_t)qr_workspace_per_field((int)N) * B : 8);
-  p.bytes = off;
-  void* base = nullptr;
-  if (hipMalloc(&base, off) != hipSuccess) {
-    delete h;
-    return fail(SLQ_ERR_DEVICE, "hipMalloc of " + std::to_string(off) + " bytes failed");
+  void* base = d_work;
+  if (!base) {
+    if (hipMalloc(&base, need) != hipSuccess) {
+      (void)hipGetLastError();
+      delete h;
+      return fail(SLQ_ERR_DEVICE, "hipMalloc of " + std::to_string(need) + " bytes failed");
+    }
+    p.owns_base = true;
   }
-  char* c = (char*)base;
-  p.base = (double*)base;
-  p.E = (double*)(c + oE);
-  p.Einv = (double*)(c + oEi);
-  p.tabs = (double*)(c + oTab);
-  p.E32 = (float*)(c + oE32);
-  p.E16 = (void*)(c + oE16);
-  p.consts = (double*)(c + oC);
-  p.Xa = (double*)(c + oXa);
-  p.Xb = (double*)(c + oXb);
-  p.W = (double*)(c + oW);
-  p.U = (double*)(c + oU);
-  p.V = (double*)(c + oV);
-  p.Vt = (double*)(c + oVt);
-  p.D = (double*)(c + oD);
-  p.invD = (double*)(c + oID);
-  p.Tblk = (double*)(c + oT);
-  p.perm = (int32_t*)(c + oPerm);
-  p.xnorm2 = (double*)(c + oXn);
-  p.nref = (int32_t*)(c + oNref);
-  p.status = (int32_t*)(c + oSt);
-  p.s_work = (int8_t*)(c + oSw);
-  p.dvec = (double*)(c + oDv);
-  p.dvec2 = (double*)(c + oDv2);
-  p.ivec = (int64_t*)(c + oIv);
-  p.dX = (double*)(c + oX);
-  p.dY = (double*)(c + oY);
-  p.dA = (double*)(c + oA);
-  p.F_old = (double*)(c + oFo);
-  p.F_new = (double*)(c + oFn);
-  p.sgn_work = (int8_t*)(c + oSg);
-  p.kron_w = (double*)(c + oKw);
-  p.qrws = (double*)(c + oQw);
-  p.kron_P = kron_line_size(model->lx, model->ly);
-  int rc = launch_kinetic(p, 0);
-  if (rc == SLQ_OK) rc = launch_kron_windows(p, 0);
-
-  if (rc == SLQ_OK) rc = launch_narrow(p.E, p.E32, NN, 0);
-  if (rc == SLQ_OK) rc = launch_to_bf16(p.E32, p.E16, NN, 0);
+  plan_layout(p, flags, (char*)base);
+  int rc = plan_init(p, 0);
   if (rc == SLQ_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(SLQ_ERR_DEVICE, "kinetic build failed");
   if (rc != SLQ_OK) {
-    hipFree(base);
+    release_net(p);
+    if (p.owns_base) hipFree(base);
     delete h;
     return rc;
   }
@@ -411,38 +472,45 @@ int slq_magnetization(slq_plan* plan, int32_t batch, const int8_t* d_s, int64_t*
 int slq_profile_enable(slq_plan* plan, int32_t enable) {
   if (!plan) return fail(SLQ_ERR_ARG, "plan is NULL");
   plan->p.prof = enable != 0;
-  plan->p.ev_used = 0;
-  plan->p.prof_flops = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    plan->p.ev_used[k] = 0;
+    plan->p.prof_flops[k] = 0.0;
+  }
+  return SLQ_OK;
+}
+
+int slq_profile_read_part(slq_plan* plan, int32_t part, double* ms, int64_t* launches, double* flops) {
+  if (!plan || !ms || !launches || !flops) return fail(SLQ_ERR_ARG, "NULL argument");
+  if (part < SLQ_PROFILE_CHAIN || part > SLQ_PROFILE_FINISH) return fail(SLQ_ERR_ARG, "unknown profile part");
+  Plan& p = plan->p;
+  SLQ_HIP(hipSetDevice(p.device));
+  double tot = 0.0;
+  for (size_t k = 0; k + 1 < p.ev_used[part]; k += 2) {
+    SLQ_HIP(hipEventSynchronize(p.ev[part][k + 1]));
+    float t = 0.f;
+    SLQ_HIP(hipEventElapsedTime(&t, p.ev[part][k], p.ev[part][k + 1]));
+    tot += t;
+  }
+  *ms = tot;
+  *launches = (int64_t)(p.ev_used[part] / 2);
+  *flops = p.prof_flops[part];
+  p.ev_used[part] = 0;
+  p.prof_flops[part] = 0.0;
   return SLQ_OK;
 }
 
 int slq_profile_read(slq_plan* plan, double* ms, int64_t* launches, double* flops) {
-  if (!plan || !ms || !launches || !flops) return fail(SLQ_ERR_ARG, "NULL argument");
-  Plan& p = plan->p;
-  SLQ_HIP(hipSetDevice(p.device));
-  double tot = 0.0;
-  for (size_t k = 0; k + 1 < p.ev_used; k += 2) {
-    SLQ_HIP(hipEventSynchronize(p.ev[k + 1]));
-    float t = 0.f;
-    SLQ_HIP(hipEventElapsedTime(&t, p.ev[k], p.ev[k + 1]));
-    tot += t;
-  }
-  *ms = tot;
-  *launches = (int64_t)(p.ev_used / 2);
-  *flops = p.prof_flops;
-  p.ev_used = 0;
-  p.prof_flops = 0.0;
-  return SLQ_OK;
+  return slq_profile_read_part(plan, SLQ_PROFILE_CHAIN, ms, launches, flops);
 }
 
 int slq_plan_destroy(slq_plan* plan) {
   if (!plan) return SLQ_OK;
   hipSetDevice(plan->p.device);
   hipDeviceSynchronize();
-  for (hipEvent_t e : plan->p.ev) hipEventDestroy(e);
+  for (int k = 0; k < 3; ++k)
+    for (hipEvent_t e : plan->p.ev[k]) hipEventDestroy(e);
   release_net(plan->p);
-  release_stack(plan->p);
-  hipFree(plan->p.base);
+  if (plan->p.owns_base) hipFree(plan->p.base);
   delete plan;
   return SLQ_OK;
 }

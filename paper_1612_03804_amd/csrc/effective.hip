@@ -403,47 +403,78 @@ int launch_accept(Plan& p, const Eff& e, int batch, int8_t* s, const int8_t* spr
 
 // -------------------------------------------------------------- fit ----
 // OLS with an intercept on centred features: lambda = (Fc^T Fc)^{-1} Fc^T yc,
-// c0 = ybar - Fbar . lambda; R^2 from the explicit residuals.  One workgroup,
-// fixed summation order (deterministic).
+// c0 = ybar - Fbar . lambda; R^2 from the explicit residuals.  The samples
+// arrive in chunks (their features computed into the plan's buffer one chunk
+// at a time), so the sums are kept about a shift, the means of the first
+// chunk (z = (F, y) - c):  sum (z_k - zbar_k)(z_l - zbar_l) =
+// sum z_k z_l - (sum z_k)(sum z_l) / n, with small sums because the shift
+// sits near the means.  Each sum has one owner thread that adds the rows in
+// order: the result does not depend on the chunking's timing (deterministic).
 constexpr int FIT_THREADS = 1024;
+constexpr int FA_K1 = MAX_TERMS + 1;          // features and y
+constexpr int FA_N = 0;                       // samples so far
+constexpr int FA_SHIFT = 1;                   // [FA_K1]
+constexpr int FA_SUM = FA_SHIFT + FA_K1;      // [FA_K1] sum of z
+constexpr int FA_GRAM = FA_SUM + FA_K1;       // [FA_K1][FA_K1] sum of z_k z_l (k <= l)
+constexpr int FA_YBAR = FA_GRAM + FA_K1 * FA_K1;
+constexpr int FA_SSR = FA_YBAR + 1, FA_SST = FA_SSR + 1;
+constexpr int FA_TOTAL = FA_SST + 1;
+static_assert(FA_TOTAL <= FIT_ACC_DOUBLES, "fit accumulators exceed their buffer");
 
-__global__ __launch_bounds__(FIT_THREADS) void k_fit(long n, int K, const double* __restrict__ F,
-                                                     const double* __restrict__ y, double* theta, double* r2) {
-  __shared__ double mean[MAX_TERMS + 1];
-  __shared__ double A[MAX_TERMS][MAX_TERMS + 1];
-  __shared__ double rhs[MAX_TERMS];
-  __shared__ double red[FIT_THREADS / 64];
-  __shared__ int bad;
+__global__ __launch_bounds__(FIT_THREADS) void k_fit_acc(int first, long rows, int K, const double* __restrict__ F,
+                                                         const double* __restrict__ y, double* acc) {
   const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  // means (one thread per column, sequential over samples)
-  for (int k = tid; k <= K; k += FIT_THREADS) {
-    double s = 0.0;
-    for (long i = 0; i < n; ++i) s += (k < K) ? F[i * K + k] : y[i];
-    mean[k] = s / (double)n;
+  auto z = [&](long i, int k) { return k < K ? F[i * K + k] : y[i]; };
+  if (first) {
+    for (int k = tid; k <= K; k += FIT_THREADS) {
+      double s = 0.0;
+      for (long i = 0; i < rows; ++i) s += z(i, k);
+      acc[FA_SHIFT + k] = s / (double)rows;
+      acc[FA_SUM + k] = 0.0;
+    }
+    for (int e = tid; e < FA_K1 * FA_K1; e += FIT_THREADS) acc[FA_GRAM + e] = 0.0;
+    if (tid == 0) acc[FA_N] = 0.0;
+    __syncthreads();
   }
-  __syncthreads();
-  // centred Gram matrix and right-hand side
-  const int npair = K * (K + 1) / 2;
-  for (int pr = tid; pr < npair + K; pr += FIT_THREADS) {
+  const double* c = acc + FA_SHIFT;
+  const int npair = (K + 1) * (K + 2) / 2;
+  for (int pr = tid; pr < npair + K + 1; pr += FIT_THREADS) {
     if (pr < npair) {
       int k1 = 0, rem = pr;
-      while (rem >= K - k1) {
-        rem -= K - k1;
+      while (rem >= K + 1 - k1) {
+        rem -= K + 1 - k1;
         ++k1;
       }
       const int k2 = k1 + rem;
-      double s = 0.0;
-      for (long i = 0; i < n; ++i) s += (F[i * K + k1] - mean[k1]) * (F[i * K + k2] - mean[k2]);
-      A[k1][k2] = s;
-      A[k2][k1] = s;
+      double s = acc[FA_GRAM + k1 * FA_K1 + k2];
+      for (long i = 0; i < rows; ++i) s += (z(i, k1) - c[k1]) * (z(i, k2) - c[k2]);
+      acc[FA_GRAM + k1 * FA_K1 + k2] = s;
     } else {
       const int k = pr - npair;
-      double s = 0.0;
-      for (long i = 0; i < n; ++i) s += (F[i * K + k] - mean[k]) * (y[i] - mean[K]);
-      rhs[k] = s;
+      double s = acc[FA_SUM + k];
+      for (long i = 0; i < rows; ++i) s += z(i, k) - c[k];
+      acc[FA_SUM + k] = s;
     }
   }
+  if (tid == 0) acc[FA_N] += (double)rows;
+}
+
+__global__ __launch_bounds__(FIT_THREADS) void k_fit_solve(int K, double* acc, double* theta) {
+  __shared__ double mean[MAX_TERMS + 1];
+  __shared__ double A[MAX_TERMS][MAX_TERMS + 1];
+  __shared__ double rhs[MAX_TERMS];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const double n = acc[FA_N];
+  const double* S = acc + FA_SUM;
+  const double* Gm = acc + FA_GRAM;
+  if (tid == 0) bad = 0;
+  for (int k = tid; k <= K; k += FIT_THREADS) mean[k] = acc[FA_SHIFT + k] + S[k] / n;
+  for (int e = tid; e < K * K; e += FIT_THREADS) {
+    const int k1 = e / K, k2 = e % K, a = min(k1, k2), b = max(k1, k2);
+    A[k1][k2] = Gm[a * FA_K1 + b] - S[a] * S[b] / n;
+  }
+  for (int k = tid; k < K; k += FIT_THREADS) rhs[k] = Gm[k * FA_K1 + K] - S[k] * S[K] / n;
   __syncthreads();
   // Cholesky A = L L^T in place (lower part)
   for (int j = 0; j < K; ++j) {
@@ -465,14 +496,14 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit(long n, int K, const double
     __syncthreads();
   }
   if (tid == 0) {
-    double z[MAX_TERMS];
+    double zz[MAX_TERMS];
     for (int i = 0; i < K; ++i) {
       double v = rhs[i];
-      for (int m = 0; m < i; ++m) v -= A[i][m] * z[m];
-      z[i] = v / A[i][i];
+      for (int m = 0; m < i; ++m) v -= A[i][m] * zz[m];
+      zz[i] = v / A[i][i];
     }
     for (int i = K - 1; i >= 0; --i) {
-      double v = z[i];
+      double v = zz[i];
       for (int m = i + 1; m < K; ++m) v -= A[m][i] * rhs[m];
       rhs[i] = v / A[i][i];  // lambda_i (rhs reused, filled from the back)
     }
@@ -480,37 +511,70 @@ __global__ __launch_bounds__(FIT_THREADS) void k_fit(long n, int K, const double
     for (int k = 0; k < K; ++k) c0 -= mean[k] * rhs[k];
     theta[0] = bad ? NAN : c0;
     for (int k = 0; k < K; ++k) theta[1 + k] = bad ? NAN : rhs[k];
+    acc[FA_YBAR] = mean[K];
+    acc[FA_SSR] = 0.0;
+    acc[FA_SST] = 0.0;
   }
-  __syncthreads();
-  // R^2 from explicit residuals
+}
+
+// explicit residuals of one chunk, added to the running sums in chunk order
+__global__ __launch_bounds__(FIT_THREADS) void k_fit_resid(long rows, int K, const double* __restrict__ F,
+                                                           const double* __restrict__ y, const double* theta,
+                                                           double* acc) {
+  __shared__ double red[2][FIT_THREADS / 64];
+  const int tid = threadIdx.x;
+  const double ybar = acc[FA_YBAR];
   double ssr = 0.0, sst = 0.0;
-  for (long i = tid; i < n; i += FIT_THREADS) {
+  for (long i = tid; i < rows; i += FIT_THREADS) {
     double yh = theta[0];
     for (int k = 0; k < K; ++k) yh += theta[1 + k] * F[i * K + k];
-    const double e = y[i] - yh, c = y[i] - mean[K];
+    const double e = y[i] - yh, c = y[i] - ybar;
     ssr += e * e;
     sst += c * c;
   }
   ssr = wave_sum(ssr);
   sst = wave_sum(sst);
-  __syncthreads();
-  if ((tid & 63) == 0) red[tid >> 6] = ssr;
-  __syncthreads();
-  double tssr = 0.0;
-  for (int w = 0; w < FIT_THREADS / 64; ++w) tssr += red[w];
-  __syncthreads();
-  if ((tid & 63) == 0) red[tid >> 6] = sst;
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = ssr;
+    red[1][tid >> 6] = sst;
+  }
   __syncthreads();
   if (tid == 0) {
-    double tsst = 0.0;
-    for (int w = 0; w < FIT_THREADS / 64; ++w) tsst += red[w];
-    r2[0] = 1.0 - tssr / tsst;
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < FIT_THREADS / 64; ++w) {
+      a += red[0][w];
+      b += red[1][w];
+    }
+    acc[FA_SSR] += a;
+    acc[FA_SST] += b;
   }
 }
 
-int launch_fit(Plan& p, const Eff& e, long n, const double* F, const double* y, double* theta, double* r2,
-               hipStream_t st) {
-  k_fit<<<1, FIT_THREADS, 0, st>>>(n, e.n_terms, F, y, theta, r2);
+__global__ void k_fit_r2(const double* acc, double* r2) {
+  if (threadIdx.x == 0) r2[0] = 1.0 - acc[FA_SSR] / acc[FA_SST];
+}
+
+// Regression over n fields s [n][L][N] with targets y [n], in chunks of up to
+// max_batch fields whose features go to the plan's F_old buffer.
+int launch_fit_chunked(Plan& p, const Eff& e, long n, const int8_t* s, const double* y, double* theta, double* r2,
+                       hipStream_t st) {
+  const long per = (long)p.L * p.n, C = p.max_batch;
+  const int K = e.n_terms;
+  for (long c0 = 0; c0 < n; c0 += C) {
+    const long rows = std::min(C, n - c0);
+    SLQ_TRY(launch_features(p, e, rows, s + c0 * per, p.F_old, st));
+    k_fit_acc<<<1, FIT_THREADS, 0, st>>>(c0 == 0, rows, K, p.F_old, y + c0, p.fit_acc);
+    SLQ_LAUNCHED();
+  }
+  k_fit_solve<<<1, FIT_THREADS, 0, st>>>(K, p.fit_acc, theta);
+  SLQ_LAUNCHED();
+  for (long c0 = 0; c0 < n; c0 += C) {
+    const long rows = std::min(C, n - c0);
+    SLQ_TRY(launch_features(p, e, rows, s + c0 * per, p.F_old, st));
+    k_fit_resid<<<1, FIT_THREADS, 0, st>>>(rows, K, p.F_old, y + c0, theta, p.fit_acc);
+    SLQ_LAUNCHED();
+  }
+  k_fit_r2<<<1, 64, 0, st>>>(p.fit_acc, r2);
   SLQ_LAUNCHED();
   return SLQ_OK;
 }
@@ -520,14 +584,51 @@ static int efail(int code, const char* msg) {
   return code;
 }
 
+// Byte layout of an effective model's device tables for N sites and n_terms
+// terms (sizes bounded without the colouring: at most N colours, 25 spatial
+// offsets, two partner relations per offset and term), including the copy of
+// the network's parameters and the move colouring used while one is attached.
+struct EffLayout {
+  size_t terms, theta, sites, off, shoff, shd, pairs, uoff, net, nsites, noff, total;
+};
+static EffLayout eff_layout(int N, int n_terms) {
+  EffLayout l{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    const size_t r = o;
+    o += (b + 255) / 256 * 256;
+    return r;
+  };
+  l.terms = take(8 * (size_t)n_terms);
+  l.theta = take(8 * (size_t)(1 + n_terms));
+  l.sites = take(4 * (size_t)N);
+  l.off = take(4 * (size_t)(N + 1));
+  l.shoff = take(4 * (size_t)(MAX_SHELL + 2));
+  l.shd = take(4 * 50);
+  l.pairs = take(4 * (size_t)n_terms * 50);
+  l.uoff = take(4 * 50);
+  l.net = take(8 * (size_t)SLQ_NET_PARAMS);
+  l.nsites = take(4 * (size_t)N);
+  l.noff = take(4 * (size_t)(N + 1));
+  l.total = o;
+  return l;
+}
+
 }  // namespace slq
 
 using namespace slq;
 
 extern "C" {
 
+int slq_eff_workspace_size(const slq_plan* plan, int32_t n_terms, size_t* bytes) {
+  if (!plan || !bytes) return efail(SLQ_ERR_ARG, "NULL argument");
+  if (n_terms < 1 || n_terms > MAX_TERMS) return efail(SLQ_ERR_ARG, "n_terms must be in [1, 64]");
+  *bytes = eff_layout(plan->p.n, n_terms).total;
+  return SLQ_OK;
+}
+
 int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const double* lambda, double c0,
-                   slq_eff** out) {
+                   void* d_work, size_t work_bytes, slq_eff** out) {
   if (!plan || !out || !terms || !lambda) return efail(SLQ_ERR_ARG, "NULL argument");
   *out = nullptr;
   Plan& p = plan->p;
@@ -613,17 +714,28 @@ int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const 
   e.n_classes = nc * L;
   e.max_class = maxc;
   const size_t b_terms = 8 * n_terms, b_theta = 8 * (1 + n_terms), b_sites = 4 * N, b_off = 4 * (nc + 1),
-               b_shoff = 4 * shoff.size(), b_shd = 4 * shd.size(), b_pairs = 4 * std::max<size_t>(1, pairs.size()),
-               b_uoff = 4 * std::max<size_t>(1, uoff.size());
-  const size_t o1 = 0, o2 = o1 + (b_terms + 255) / 256 * 256, o3 = o2 + (b_theta + 255) / 256 * 256,
-               o4 = o3 + (b_sites + 255) / 256 * 256, o5 = o4 + (b_off + 255) / 256 * 256,
-               o6 = o5 + (b_shoff + 255) / 256 * 256, o7 = o6 + (b_shd + 255) / 256 * 256,
-               o8 = o7 + (b_pairs + 255) / 256 * 256, total = o8 + (b_uoff + 255) / 256 * 256;
-  char* base = nullptr;
-  if (hipSetDevice(p.device) != hipSuccess || hipMalloc((void**)&base, total) != hipSuccess) {
+               b_shoff = 4 * shoff.size(), b_shd = 4 * shd.size();
+  const EffLayout lay = eff_layout(N, n_terms);
+  if (d_work && work_bytes < lay.total) {
+    delete h;
+    return efail(SLQ_ERR_WORKSPACE, "eff workspace smaller than slq_eff_workspace_size");
+  }
+  if (d_work && ((uintptr_t)d_work & 255)) {
+    delete h;
+    return efail(SLQ_ERR_ARG, "d_work must be 256-byte aligned");
+  }
+  char* base = (char*)d_work;
+  if (hipSetDevice(p.device) != hipSuccess || (!base && hipMalloc((void**)&base, lay.total) != hipSuccess)) {
     delete h;
     return efail(SLQ_ERR_DEVICE, "hipMalloc failed");
   }
+  e.base = base;
+  e.owns_base = d_work == nullptr;
+  const size_t o1 = lay.terms, o2 = lay.theta, o3 = lay.sites, o4 = lay.off, o5 = lay.shoff, o6 = lay.shd,
+               o7 = lay.pairs, o8 = lay.uoff;
+  e.d_net = (double*)(base + lay.net);
+  e.d_ncol_sites = (int32_t*)(base + lay.nsites);
+  e.d_ncol_off = (int32_t*)(base + lay.noff);
   e.d_terms = (int32_t*)(base + o1);
   e.d_theta = (double*)(base + o2);
   e.d_col_sites = (int32_t*)(base + o3);
@@ -644,7 +756,7 @@ int slq_eff_create(slq_plan* plan, int32_t n_terms, const int32_t* terms, const 
             hipMemcpy(e.d_shell_off, shoff.data(), b_shoff, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(e.d_shell_dxy, shd.data(), b_shd, hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
-    hipFree(base);
+    if (e.owns_base) hipFree(base);
     delete h;
     return efail(SLQ_ERR_DEVICE, "hipMemcpy failed");
   }
@@ -656,8 +768,7 @@ int slq_eff_destroy(slq_eff* eff) {
   if (!eff) return SLQ_OK;
   hipSetDevice(eff->e.plan->device);
   hipDeviceSynchronize();
-  hipFree(eff->e.d_terms);
-  if (eff->e.d_net) hipFree(eff->e.d_net);
+  if (eff->e.owns_base) hipFree(eff->e.base);
   delete eff;
   return SLQ_OK;
 }
@@ -670,12 +781,17 @@ int slq_eff_set_net(slq_eff* eff, const double* d_params, int32_t net_prec, hipS
     e.net_on = false;
     return SLQ_OK;
   }
-  if (net_prec != SLQ_PREC_FP64 && net_prec != SLQ_PREC_FP32)
-    return efail(SLQ_ERR_ARG, "net_prec must be SLQ_PREC_FP64 or SLQ_PREC_FP32");
+  // Proposals need a move kernel that is reversible with respect to the
+  // action Eq. 4 charges.  The move kernel updates the network's activations
+  // incrementally on every accepted flip; in FP32 those updates round
+  // differently along different paths, so a move and its reverse would not
+  // change the action by exact negatives.  FP64 keeps that to round-off.
+  if (net_prec != SLQ_PREC_FP64)
+    return efail(SLQ_ERR_ARG, "net_prec must be SLQ_PREC_FP64 for proposals (FP32 is for training and forward passes)");
   if (p.m.lx < 5 || p.m.ly < 5 || p.L < 5)
     return efail(SLQ_ERR_ARG, "moves with the learned action need lx, ly and L >= 5");
   SLQ_HIP(hipSetDevice(p.device));
-  if (!e.d_net) {
+  if (e.n_ncolours == 0) {  // first attach: the colouring that separates the network's reach
     // colouring of the graph of dl = 0 couplings plus spatial Chebyshev distance <= 4
     const int lx = p.m.lx, ly = p.m.ly, N = p.n;
     std::vector<std::set<int>> nbr(N);
@@ -716,17 +832,11 @@ int slq_eff_set_net(slq_eff* eff, const double* d_params, int32_t net_prec, hipS
         if (col[i] == c) sites.push_back(i);
     }
     off[nc] = (int32_t)sites.size();
-    const size_t b_prm = 8 * ((SLQ_NET_PARAMS + 31) / 32 * 32), b_sites = 4 * N, b_off = 4 * (nc + 1);
-    char* base = nullptr;
-    if (hipMalloc((void**)&base, b_prm + b_sites + b_off + 64) != hipSuccess)
-      return efail(SLQ_ERR_DEVICE, "hipMalloc failed");
-    e.d_net = (double*)base;
-    e.d_ncol_sites = (int32_t*)(base + b_prm);
-    e.d_ncol_off = (int32_t*)(base + b_prm + b_sites);
-    e.n_ncolours = nc;
+    const size_t b_sites = 4 * N, b_off = 4 * (nc + 1);
     if (hipMemcpy(e.d_ncol_sites, sites.data(), b_sites, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(e.d_ncol_off, off.data(), b_off, hipMemcpyHostToDevice) != hipSuccess)
       return efail(SLQ_ERR_DEVICE, "hipMemcpy failed");
+    e.n_ncolours = nc;
   }
   int rc = copy_f64(d_params, e.d_net, SLQ_NET_PARAMS, stream);
   if (rc != SLQ_OK) return rc;
@@ -737,7 +847,7 @@ int slq_eff_set_net(slq_eff* eff, const double* d_params, int32_t net_prec, hipS
 
 int slq_eff_net_classes(const slq_eff* eff, int32_t* n_classes) {
   if (!eff || !n_classes) return efail(SLQ_ERR_ARG, "NULL argument");
-  if (!eff->e.d_net) return efail(SLQ_ERR_ARG, "no network attached");
+  if (eff->e.n_ncolours == 0) return efail(SLQ_ERR_ARG, "no network attached");
   *n_classes = eff->e.n_ncolours * eff->e.plan->L;
   return SLQ_OK;
 }
@@ -811,13 +921,7 @@ int slq_fit_effective(slq_plan* plan, const slq_eff* eff, int64_t n_samples, con
   if (e.plan != &p) return efail(SLQ_ERR_ARG, "eff belongs to another plan");
   if (n_samples < e.n_terms + 2) return efail(SLQ_ERR_ARG, "n_samples must be >= n_terms + 2");
   SLQ_HIP(hipSetDevice(p.device));
-  double* F = nullptr;
-  if (hipMallocAsync((void**)&F, sizeof(double) * n_samples * e.n_terms, stream) != hipSuccess)
-    return efail(SLQ_ERR_DEVICE, "hipMallocAsync of the feature matrix failed");
-  int rc = launch_features(p, e, n_samples, d_S, F, stream);
-  if (rc == SLQ_OK) rc = launch_fit(p, e, n_samples, F, d_logabs, d_theta, d_r2, stream);
-  hipFreeAsync(F, stream);
-  return rc;
+  return launch_fit_chunked(p, e, n_samples, d_S, d_logabs, d_theta, d_r2, stream);
 }
 
 }  // extern "C"

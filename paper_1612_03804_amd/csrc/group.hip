@@ -302,7 +302,7 @@ int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out)
   for (size_t q = 0; q < members.size() && rc == SLQ_OK; ++q) {
     SubPlan sp;
     sp.nb = (int)members[q].size();
-    rc = slq_plan_create(&models[rep[q]], sp.nb, &sp.plan);
+    rc = slq_plan_create(&models[rep[q]], sp.nb, 0, nullptr, 0, &sp.plan);
     if (rc != SLQ_OK) break;
     std::vector<int32_t> ids(members[q].begin(), members[q].end()), first(sp.nb);
     std::vector<int64_t> so(sp.nb), go(sp.nb), lead(sp.nb);

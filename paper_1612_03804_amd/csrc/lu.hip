@@ -13,6 +13,7 @@
 // trailing update runs over (column, 16-row) work items so that every thread
 // keeps a block of loads in flight).
 #include "slq_internal.h"
+#include "lu_interchange.h"
 
 namespace slq {
 
@@ -166,13 +167,13 @@ __global__ __launch_bounds__(FN_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
   double* P = lds;                                           // [NB][N] panel, or the transpose tile
   double* redv = P + max(NB * N, FN_TW * (FN_TS + 1));       // [FN_WAVES]
   int* redi = (int*)(redv + FN_WAVES);                       // [FN_WAVES]
-  int* flag = redi + FN_WAVES;                               // [1] a zero pivot was met
-  int* nsl = flag + 1;                                       // [1] rows touched by a panel's interchanges
+  int* flag = redi + FN_WAVES;                               // [2] a zero pivot / a refused pivot index
+  int* nsl = flag + 2;                                       // [1] rows touched by a panel's interchanges
   int* srow = nsl + 1;                                       // [2 NB] those rows, the panel's own first
   int* ssrc = srow + 2 * NB;                                 // [2 NB] row whose entries each one receives
   uint16_t* ipiv = (uint16_t*)(ssrc + 2 * NB);               // [N] pivot rows
   uint16_t* orow = ipiv + N;                                 // [N] row permutation of the solves
-  if (tid == 0) flag[0] = 0;
+  if (tid == 0) flag[0] = flag[1] = 0;
 
   // ---- M = D_b^{-1} U^T + D_s V
   transpose_scaled(N, U, D, V, W, P, nullptr);
@@ -254,26 +255,10 @@ __global__ __launch_bounds__(FN_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
       W[(long)(j0 + r) * N + j0 + c] = P[c * ldp + r];
     }
     // the panel's row interchanges as one permutation of the rows they touch
+    // (a pivot outside the rows below the diagonal is refused and reported)
     if (tid == 0) {
-      int ns = nbw;
-      for (int k = 0; k < nbw; ++k) srow[k] = ssrc[k] = j0 + k;
-      for (int c = 0; c < nbw; ++c) {
-        const int pr = ipiv[j0 + c];
-        int k2 = -1;
-        if (pr < j0 + nbw) {
-          k2 = pr - j0;
-        } else {
-          for (int k = nbw; k < ns; ++k)
-            if (srow[k] == pr) k2 = k;
-          if (k2 < 0) {
-            k2 = ns++;
-            srow[k2] = ssrc[k2] = pr;
-          }
-        }
-        const int t = ssrc[c];
-        ssrc[c] = ssrc[k2];
-        ssrc[k2] = t;
-      }
+      int ns = 0;
+      if (lu_panel_permutation(N, j0, nbw, ipiv, srow, ssrc, &ns)) flag[1] = 1;
       nsl[0] = ns;
     }
     __syncthreads();
@@ -332,6 +317,7 @@ __global__ __launch_bounds__(FN_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     }
     const bool sing = flag[0] != 0;
     if (sing && a.status) a.status[b] |= SLQ_ST_SINGULAR;
+    if (flag[1] && a.status) a.status[b] |= SLQ_ST_PIVOT;
     if (!isfinite(tot) && !sing && a.status) a.status[b] |= SLQ_ST_NONFINITE;
     a.logabs[b] = sing ? -INFINITY : tot;
     a.sign[b] = sing ? 0 : (pp ? -1 : 1);
@@ -420,11 +406,24 @@ __global__ __launch_bounds__(FN_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 static size_t finish_lds(int N, int nb) {
   size_t panel = (size_t)nb * N;
   if (panel < (size_t)FN_TW * (FN_TS + 1)) panel = (size_t)FN_TW * (FN_TS + 1);
-  return sizeof(double) * (panel + FN_WAVES) + sizeof(int) * (FN_WAVES + 2 + 4 * nb) + sizeof(uint16_t) * 2 * N;
+  return sizeof(double) * (panel + FN_WAVES) + sizeof(int) * (FN_WAVES + 3 + 4 * nb) + sizeof(uint16_t) * 2 * N;
 }
 
 int launch_finish(Plan& p, int batch, const UdvRef& f, double* G, double* logabs, int8_t* sign, int32_t* status,
                   hipStream_t st) {
+  // without G the determinant comes from a QR of M on the matrix cores
+  // ((4/3) N^3 flops per field for R), with G from an LU ((2/3) N^3) and the
+  // two triangular solves (2 N^3)
+  const double n3 = (double)p.n * p.n * p.n;
+  if (!G && use_det_qr(p, f))
+    return timed_part(p, SLQ_PROFILE_FINISH, batch * 4.0 / 3.0 * n3, st,
+                      [&]() { return launch_det_qr(p, batch, f, logabs, sign, status, st); });
+  return timed_part(p, SLQ_PROFILE_FINISH, batch * (G ? 8.0 / 3.0 : 2.0 / 3.0) * n3, st,
+                    [&]() { return launch_finish_lu(p, batch, f, G, logabs, sign, status, st); });
+}
+
+int launch_finish_lu(Plan& p, int batch, const UdvRef& f, double* G, double* logabs, int8_t* sign, int32_t* status,
+                     hipStream_t st) {
   FinishArgs a;
   a.N = p.n;
   a.U = f.U;

@@ -298,17 +298,12 @@ static NetWork& net_work(Plan& p) {
   return *reinterpret_cast<NetWork*>(p.net_state);
 }
 
-static int ensure_net(Plan& p) {
-  if (p.net_state) return SLQ_OK;
-  NetWork* w = new (std::nothrow) NetWork();
-  if (!w) {
-    set_error("host allocation failed");
-    return SLQ_ERR_DEVICE;
-  }
-  w->LN = (long)p.L * p.n;
-  w->batch = p.max_batch;
-  w->nblk = (int)((w->LN + NET_BLOCK - 1) / NET_BLOCK);
-  const long B = p.max_batch, act = (long)NC * w->LN * B;
+// Layout of the network buffers for max_batch fields (in doubles); with d
+// set, w's pointers are placed.
+static size_t net_layout(const Plan& p, NetWork* w, double* d) {
+  const long LN = (long)p.L * p.n;
+  const int nblk = (int)((LN + NET_BLOCK - 1) / NET_BLOCK);
+  const long B = p.max_batch, act = (long)NC * LN * B;
   size_t off = 0;
   auto take = [&](size_t n) {
     const size_t o = off;
@@ -316,37 +311,54 @@ static int ensure_net(Plan& p) {
     return o;
   };
   const size_t o1 = take(act), o2 = take(act), o3 = take(act), o4 = take(act), o5 = take(act), o6 = take(act);
-  const size_t op = take((size_t)B * w->nblk * NC), opl = take(B * NC), ow = take((size_t)B * WG_CHUNKS * P_W3);
+  const size_t op = take((size_t)B * nblk * NC), opl = take(B * NC), ow = take((size_t)B * WG_CHUNKS * P_W3);
   const size_t oS = take(B), oS2 = take(B), og = take(B), oF = take(B * 64);
-  w->bytes = off * sizeof(double);
-  if (hipMalloc(&w->base, w->bytes) != hipSuccess) {
-    delete w;
-    set_error("hipMalloc of the network workspace failed");
+  if (w && d) {
+    w->LN = LN;
+    w->batch = (int)B;
+    w->nblk = nblk;
+    w->base = d;
+    w->bytes = off * sizeof(double);
+    w->a1 = d + o1;
+    w->h1 = d + o2;
+    w->a2 = d + o3;
+    w->h2 = d + o4;
+    w->dz1 = d + o5;
+    w->dz2 = d + o6;
+    w->part = d + op;
+    w->pool = d + opl;
+    w->wpart = d + ow;
+    w->S = d + oS;
+    w->S2 = d + oS2;
+    w->gS = d + og;
+    w->F = d + oF;
+  }
+  return off;
+}
+
+size_t net_bytes_for(const Plan& p) { return sizeof(double) * net_layout(p, nullptr, nullptr); }
+
+int bind_net(Plan& p) {
+  if (p.net_state) return SLQ_OK;
+  NetWork* w = new (std::nothrow) NetWork();
+  if (!w) {
+    set_error("host allocation failed");
     return SLQ_ERR_DEVICE;
   }
-  double* d = (double*)w->base;
-  w->a1 = d + o1;
-  w->h1 = d + o2;
-  w->a2 = d + o3;
-  w->h2 = d + o4;
-  w->dz1 = d + o5;
-  w->dz2 = d + o6;
-  w->part = d + op;
-  w->pool = d + opl;
-  w->wpart = d + ow;
-  w->S = d + oS;
-  w->S2 = d + oS2;
-  w->gS = d + og;
-  w->F = d + oF;
+  net_layout(p, w, (double*)p.net_base);
   p.net_state = w;
   return SLQ_OK;
 }
 
+static int ensure_net(Plan& p) {
+  if (p.net_state) return SLQ_OK;
+  set_error("the plan was created without SLQ_PLAN_NET (no room for the network's activations)");
+  return SLQ_ERR_WORKSPACE;
+}
+
 void release_net(Plan& p) {
   if (!p.net_state) return;
-  NetWork* w = reinterpret_cast<NetWork*>(p.net_state);
-  hipFree(w->base);
-  delete w;
+  delete reinterpret_cast<NetWork*>(p.net_state);
   p.net_state = nullptr;
 }
 
@@ -553,10 +565,8 @@ int launch_eff_sweep_net(Plan& p, const Eff& e, int batch, int8_t* s, int n_move
   a.accepts = accepts;
   a.dS_out = dS;
   const EffDev ed = eff_dev_view(p, e);
-  if (e.net_prec == SLQ_PREC_FP64)
-    k_eff_sweep_net<double><<<batch, NM_THREADS, 0, st>>>(ed, a, s, w.a1, w.h1, w.a2);
-  else
-    k_eff_sweep_net<float><<<batch, NM_THREADS, 0, st>>>(ed, a, s, (float*)w.a1, (float*)w.h1, (float*)w.a2);
+  // FP64 state only (slq_eff_set_net refuses other precisions for proposals)
+  k_eff_sweep_net<double><<<batch, NM_THREADS, 0, st>>>(ed, a, s, w.a1, w.h1, w.a2);
   SLQ_LAUNCHED();
   return SLQ_OK;
 }

@@ -436,24 +436,66 @@ __global__ __launch_bounds__(PQ_THREADS) __attribute__((amdgpu_waves_per_eu(NB =
   }
 }
 
-// panel width and register rows per lane by matrix size
-template <int NB>
-struct PanelShape;
-template <>
-struct PanelShape<32> {
-  static constexpr int RPL = 7;  // N <= 448
-  static constexpr bool CACHE = true;
+// panel width and register rows per lane by matrix size: the widest panel
+// whose columns fit the registers of one workgroup (RPL rows per lane and
+// column, 64 * RPL >= N)
+template <int NB, int RPL>
+struct PanelShape {
+  static constexpr bool CACHE = RPL <= 18;  // keep the published reflector in registers too
 };
-template <>
-struct PanelShape<16> {
-  static constexpr int RPL = 18;  // N <= 1152
-  static constexpr bool CACHE = true;
-};
-template <>
-struct PanelShape<8> {
-  static constexpr int RPL = 38;  // N <= 2432
-  static constexpr bool CACHE = false;
-};
+
+// Compact-WY factor of a whole outer block, Q_O = Q_1 ... Q_P = I - V_O T_O V_O^T,
+// from the panels' own factors T_p (on T_O's diagonal, written by k_panel)
+// and the Gram matrix S = V_O^T V_O of the block's reflectors:
+//     T_O[0:s, P] = -T_O[0:s, 0:s] S[0:s, P] T_P,  s = first column of panel P,
+// panel by panel (the usual recursive form of T_O = [[T_A, -T_A V_A^T V_B T_B],
+// [0, T_B]]).  One workgroup per field; T_O is built in LDS and written back.
+constexpr int TB_THREADS = 256;
+constexpr int TB_LT = QR_NBO + 1;  // padded row stride of T in LDS
+constexpr int TB_CH = 8;           // columns of a panel per step
+
+__global__ __launch_bounds__(TB_THREADS) void k_tbuild(int wo, int nb, double* __restrict__ TOall, long strideT,
+                                                       const double* __restrict__ Sall, long strideS) {
+  extern __shared__ double lds[];
+  double* T = lds;                    // [QR_NBO][TB_LT]
+  double* Y = T + QR_NBO * TB_LT;     // [QR_NBO][TB_CH]
+  const long b = blockIdx.x;
+  double* Tg = TOall + b * strideT;
+  const double* S = Sall + b * strideS;
+  const int tid = threadIdx.x;
+  // the panels' diagonal blocks, zeros elsewhere
+  for (int e = tid; e < wo * wo; e += TB_THREADS) {
+    const int i = e / wo, j = e % wo;
+    T[i * TB_LT + j] = (i / nb == j / nb && i <= j) ? Tg[(long)i * QR_NBO + j] : 0.0;
+  }
+  __syncthreads();
+  for (int s0 = nb; s0 < wo; s0 += nb) {
+    const int nbw = min(nb, wo - s0);
+    for (int c0 = 0; c0 < nbw; c0 += TB_CH) {
+      const int nc = min(TB_CH, nbw - c0);
+      // Y[k][c] = sum_d S[k][s0 + d] T[s0 + d][s0 + c0 + c], k < s0 (T_P upper triangular)
+      for (int e = tid; e < s0 * nc; e += TB_THREADS) {
+        const int k = e / nc, c = e % nc;
+        double y = 0.0;
+        for (int d = 0; d <= c0 + c; ++d) y += S[(long)k * QR_NBO + s0 + d] * T[(s0 + d) * TB_LT + s0 + c0 + c];
+        Y[k * TB_CH + c] = y;
+      }
+      __syncthreads();
+      // T[i][s0 + c0 + c] = -sum_{k = i}^{s0 - 1} T[i][k] Y[k][c]
+      for (int e = tid; e < s0 * nc; e += TB_THREADS) {
+        const int i = e % s0, c = e / s0;
+        double t = 0.0;
+        for (int k = i; k < s0; ++k) t += T[i * TB_LT + k] * Y[k * TB_CH + c];
+        T[i * TB_LT + s0 + c0 + c] = -t;
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = tid; e < wo * wo; e += TB_THREADS) {
+    const int i = e / wo, j = e % wo;
+    Tg[(long)i * QR_NBO + j] = T[i * TB_LT + j];
+  }
+}
 
 __global__ void k_zero_i32(int32_t* x, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = 0;
@@ -470,9 +512,9 @@ __global__ void k_zero_i32(int32_t* x, int n) {
 // the large updates have row and column counts that are multiples of the
 // 128 x 64 tiles (N = 400: 384 x 256 and 256 x 128 instead of 400 x 272 and
 // 272 x 144).
-template <int NB>
+template <int NB, int RPL>
 static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st,
-                       const double* norm2) {
+                       const double* norm2, bool form_q) {
   const int N = p.n;
   const long NN = (long)N * N;
   constexpr int NBO = QR_NBO;
@@ -534,24 +576,42 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
       const int nbw = std::min(NB, J0 + wo - j0), m = N - j0, sft = j0 - J0;
       double* Tp = Tb + (long)sft * NBO + sft;
       PanelArgs a{N, j0, nbw, p.W, Vbuf, J0, Tp, sW, NBO, wo - sft, o.D, p.invD, o.nref, status};
-      constexpr int RPL = PanelShape<NB>::RPL;
       const size_t lds = sizeof(double) * ((size_t)NB * 65 + 2 * 64 * RPL + 2 * NB * (NB + 1) + NB);
-      constexpr bool CACHE = PanelShape<NB>::CACHE;
+      constexpr bool CACHE = PanelShape<NB, RPL>::CACHE;
       allow_max_lds((const void*)k_panel<NB, RPL, CACHE>);
       k_panel<NB, RPL, CACHE><<<batch, PQ_THREADS, lds, st>>>(a);
       SLQ_LAUNCHED();
       const int nin = wo - sft - nbw;  // rest of the outer block
       if (nin > 0) SLQ_TRY(apply(Vbuf + (long)j0 * N + j0, Tp, nbw, p.W + (long)j0 * N + j0 + nbw, m, nin, true));
-      if (sft > 0) {  // T_O[0:sft, sft:sft+nbw] = -T_O[0:sft, 0:sft] (V_A^T V_B) T_B, rows j0.. only
-        SLQ_TRY(gemm(sft, nbw, m, Vbuf + (long)j0 * N + J0, N, NN, true, Vbuf + (long)j0 * N + j0, N, NN, Gb, NBO,
-                     sW, 1.0, 0.0));
-        SLQ_TRY(gemm(sft, nbw, nbw, Gb, NBO, sW, false, Tp, NBO, sW, Wt2, N, sW, 1.0, 0.0));
-        SLQ_TRY(gemm(sft, nbw, sft, Tb, NBO, sW, false, Wt2, N, sW, Tb + sft, NBO, sW, -1.0, 0.0));
-      }
+    }
+    if (wo > NB) {  // T_O of the whole block from its Gram matrix (rows J0.. of V_O)
+      GemmArgs gg{};
+      gg.M = wo;
+      gg.N = wo;
+      gg.K = N - J0;
+      gg.A = Vbuf + (long)J0 * N + J0;
+      gg.lda = N;
+      gg.strideA = NN;
+      gg.B = gg.A;
+      gg.ldb = N;
+      gg.strideB = NN;
+      gg.C = Gb;
+      gg.ldc = NBO;
+      gg.strideC = sW;
+      gg.alpha = 1.0;
+      gg.beta = 0.0;
+      gg.batch = batch;
+      gg.cfg = GEMM_32x64;
+      SLQ_TRY(launch_gemm(gg, true, false, st));
+      const size_t tl = sizeof(double) * ((size_t)QR_NBO * TB_LT + QR_NBO * TB_CH);
+      allow_max_lds((const void*)k_tbuild);
+      k_tbuild<<<batch, TB_THREADS, tl, st>>>(wo, NB, Tb, sW, Gb, sW);
+      SLQ_LAUNCHED();
     }
     if (J0 + wo < N)
       SLQ_TRY(apply(Vbuf + (long)J0 * N + J0, Tb, wo, p.W + (long)J0 * N + J0 + wo, N - J0, N - J0 - wo, true));
   }
+  if (!form_q) return SLQ_OK;
   // explicit Q, backwards: U[J0:, J0:] <- Q_O U[J0:, J0:] = U - V_O (T_O (V_O^T U)),
   // starting from U = I.  Columns J0..J0+wo-1 of U still hold [I; 0] there (later
   // blocks only touch columns beyond), so for them V_O^T U = V_top^T, the unit
@@ -596,15 +656,13 @@ long qr_workspace_per_field(int N) {
   return (nout + 1) * QR_NBO * QR_NBO + 2L * QR_NBO * N;
 }
 
-int qr_blocked_width(int N) { return N <= 448 ? 32 : (N <= 1152 ? 16 : 8); }
-
 int launch_qr_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st,
-                      const double* norm2) {
-  switch (qr_blocked_width(p.n)) {
-    case 32: return run_blocked<32>(p, batch, X, o, status, st, norm2);
-    case 16: return run_blocked<16>(p, batch, X, o, status, st, norm2);
-    default: return run_blocked<8>(p, batch, X, o, status, st, norm2);
-  }
+                      const double* norm2, bool form_q) {
+  if (p.n <= 448) return run_blocked<32, 7>(p, batch, X, o, status, st, norm2, form_q);
+  if (p.n <= 1152) return run_blocked<16, 18>(p, batch, X, o, status, st, norm2, form_q);
+  // (16 columns at 38 rows per lane would need more than the 256 registers a
+  // wave of a 512-thread workgroup can hold)
+  return run_blocked<8, 38>(p, batch, X, o, status, st, norm2, form_q);
 }
 
 }  // namespace slq

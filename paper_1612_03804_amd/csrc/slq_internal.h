@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -170,6 +171,21 @@ __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_move<DPP_ROW_ROR8>(v));
   return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
 }
+// Larger of a and b, NaN if either is NaN (fmax returns the other operand and
+// would hide a non-finite value from a max-reduction).
+__device__ __forceinline__ double nan_max(double a, double b) {
+  if (a != a) return a;
+  if (b != b) return b;
+  return a > b ? a : b;
+}
+// wave_max that propagates NaN: any lane's NaN reaches every lane.
+__device__ __forceinline__ double wave_max_nan(double v) {
+  v = nan_max(v, dpp_move<DPP_QUAD_XOR1>(v));
+  v = nan_max(v, dpp_move<DPP_QUAD_XOR2>(v));
+  v = nan_max(v, dpp_move<DPP_ROW_ROR4>(v));
+  v = nan_max(v, dpp_move<DPP_ROW_ROR8>(v));
+  return nan_max(nan_max(read_lane(v, 0), read_lane(v, 16)), nan_max(read_lane(v, 32), read_lane(v, 48)));
+}
 
 // ------------------------------------------------------------------ plan ----
 struct Plan {
@@ -192,8 +208,9 @@ struct Plan {
   double *D, *invD, *Tblk;  // D, 1/D: [N]; compact-WY T blocks: (N + 32) * 32 per field
   int32_t* perm;            // [N]
   double* xnorm2;           // [N]: squared column norms of a structured block product
-  int32_t* nref;            // [1] reflectors with tau != 0 in the latest QR
+  int32_t* nref;            // [max_batch] reflectors with tau != 0 in the latest QR
   int32_t* status;          // [max_batch] scratch status when caller passes NULL
+  int32_t *nref2, *status2; // [max_batch] each: reflector count and status of the QR of M (det_qr.hip)
   int8_t* s_work;           // [max_batch][L][N] proposal fields
   double* dvec;             // [max_batch] scratch doubles
   double* dvec2;            // [max_batch] scratch doubles
@@ -205,12 +222,19 @@ struct Plan {
   double *F_old, *F_new;    // [max_batch][64] effective-action features
   int8_t* sgn_work;         // [max_batch]
   // optional event timing of the chain-product GEMM launches
+  // parts: SLQ_PROFILE_CHAIN, SLQ_PROFILE_STAB, SLQ_PROFILE_FINISH
   bool prof = false;
-  std::vector<hipEvent_t> ev;  // start/stop pairs
-  size_t ev_used = 0;
-  double prof_flops = 0.0;
-  // learned-action workspace, allocated on first use
+  std::vector<hipEvent_t> ev[3];  // start/stop pairs per part
+  size_t ev_used[3] = {0, 0, 0};
+  double prof_flops[3] = {0.0, 0.0, 0.0};
+  // learned-action buffers (SLQ_PLAN_NET): device region in the workspace and
+  // the host-side view of it
+  void* net_base = nullptr;
   void* net_state = nullptr;
+  // the workspace was allocated by slq_plan_create (d_work NULL) and is freed with the plan
+  bool owns_base = false;
+  // accumulators of the chunked regression (FIT_ACC_DOUBLES)
+  double* fit_acc = nullptr;
   // tile configuration of the FP64 chain GEMM chosen by the autotuner (-1: default)
   int gemm_cfg = -1;
   // structured (Kronecker) slice products: register line length (0: lattice
@@ -226,8 +250,8 @@ struct Plan {
   // blocked QR workspace: outer compact-WY factors, Gram blocks, V^T A products
   double* qrws = nullptr;
 
-  // stabilised partial products kept by local sweeps, allocated on first use
-  // for stack_batch fields (see sweep_stacked)
+  // stabilised partial products kept by local sweeps (SLQ_PLAN_SWEEPS) for
+  // stack_batch = max_batch fields (see sweep_stacked)
   double* stack = nullptr;
   int stack_batch = 0;
 };
@@ -245,6 +269,8 @@ struct Eff {
   int32_t* d_shell_off;  // shell offset table [6 + 1]
   int32_t* d_shell_dxy;  // [total][2]
   std::vector<int32_t> h_terms;  // host copy of the terms
+  void* base = nullptr;           // device tables (caller-owned unless owns_base)
+  bool owns_base = false;
   // learned action (optional)
   bool net_on = false;
   int net_prec = 0;
@@ -298,6 +324,7 @@ __device__ __forceinline__ int local_field_dev(const EffDev& d, const int8_t* __
   return h;
 }
 
+constexpr int MAX_TERMS_ABI = 64;  // terms of an effective model
 constexpr int QR_NB = 16;     // Householder / LU panel width
 constexpr int QR_NBO = 128;   // outer block of the blocked QR
 long qr_workspace_per_field(int N);  // doubles per field of Plan::qrws
@@ -429,8 +456,10 @@ inline UdvRef plan_udv(Plan& p) { return UdvRef{p.U, p.D, p.V, p.nref}; }
 // and Vt, dX, dY as scratch).
 int launch_qr(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st);
 // norm2 (optional): squared 2-norms of the columns of X, [batch][N]
+// form_q = false leaves o.U untouched (R, |diag R|, the permutation and the
+// reflector count only).
 int launch_qr_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st,
-                      const double* norm2 = nullptr);
+                      const double* norm2 = nullptr, bool form_q = true);
 inline int launch_qr(Plan& p, int batch, const double* X, int32_t* status, hipStream_t st) {
   return launch_qr(p, batch, X, plan_udv(p), status, st);
 }
@@ -447,13 +476,23 @@ int launch_v_update(Plan& p, int batch, const double* V_in, double* V_out, hipSt
 // scratch.
 int launch_finish(Plan& p, int batch, const UdvRef& f, double* G, double* logabs, int8_t* sign, int32_t* status,
                   hipStream_t st);
+int launch_finish_lu(Plan& p, int batch, const UdvRef& f, double* G, double* logabs, int8_t* sign, int32_t* status,
+                     hipStream_t st);
 inline int launch_finish(Plan& p, int batch, double* G, double* logabs, int8_t* sign, int32_t* status,
                          hipStream_t st) {
   return launch_finish(p, batch, plan_udv(p), G, logabs, sign, status, st);
 }
 int launch_check_spins(Plan& p, int batch, const int8_t* s, int32_t* status, hipStream_t st);
+// log|det(1 + U D V)| and sign from an R-only blocked QR of M (no G); uses Xa,
+// Xb, W, Vt, perm, invD, qrws, nref2, status2.  use_det_qr: N > 64 and f
+// lies outside those buffers.
+bool use_det_qr(const Plan& p, const UdvRef& f);
+int launch_det_qr(Plan& p, int batch, const UdvRef& f, double* logabs, int8_t* sign, int32_t* status,
+                  hipStream_t st);
 
 int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, hipStream_t st);
+// Event timing of one launch sequence of a profiled part (no-op unless enabled).
+int timed_part(Plan& p, int part, double flops, hipStream_t st, const std::function<int()>& launch);
 int check_batch(const Plan& p, long batch);
 int fill_f64(double* x, long n, double v, hipStream_t st);
 int fill_i32(int32_t* x, long n, int32_t v, hipStream_t st);
@@ -464,11 +503,11 @@ int copy_i8(const int8_t* a, int8_t* b, long n, hipStream_t st);
 // Local sweeps
 int launch_flip_slice(Plan& p, int batch, int8_t* s, double* G, double* logabs, int8_t* sign, int slice,
                       uint64_t seed, uint64_t sweep, uint64_t chain0, int64_t* accepts, hipStream_t st);
-int launch_drift(Plan& p, int batch, double* Gw, const double* Gf, double* drift, hipStream_t st);
+int launch_drift(Plan& p, int batch, double* Gw, const double* Gf, double* drift, int32_t* status, hipStream_t st);
 int sweep_stacked(Plan& p, int batch, int8_t* s, double* G, double* logabs, int8_t* sign, int n_sweeps,
                   uint64_t seed, uint64_t sweep0, uint64_t chain0, int64_t* accepts, double* drift,
                   int32_t* status, hipStream_t st);
-void release_stack(Plan& p);
+size_t stack_bytes_for(const Plan& p, long batch);  // bytes of the stacked partial products
 
 // Effective model
 int launch_eff_sweep(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, uint64_t seed, uint64_t step,
@@ -478,8 +517,8 @@ int launch_accept(Plan& p, const Eff& e, int batch, int8_t* s, const int8_t* spr
                   const double* new_logabs, const int8_t* new_sign, const double* F_old, const double* F_new,
                   const double* Sn_old, const double* Sn_new, uint64_t seed, uint64_t step, uint64_t chain0,
                   int8_t* accepted, double* logA, hipStream_t st);
-int launch_fit(Plan& p, const Eff& e, long n, const double* F, const double* y, double* theta, double* r2,
-               hipStream_t st);
+int launch_fit_chunked(Plan& p, const Eff& e, long n, const int8_t* s, const double* y, double* theta, double* r2,
+                       hipStream_t st);
 
 // Learned action
 int net_forward(Plan& p, int prec, int batch, const int8_t* s, const double* prm, double* S, hipStream_t st);
@@ -487,7 +526,14 @@ int launch_eff_sweep_net(Plan& p, const Eff& e, int batch, int8_t* s, int n_move
                          uint64_t chain0, int64_t* accepts, double* dS, hipStream_t st);
 int net_pair(Plan& p, const Eff& e, int batch, const int8_t* s_old, const int8_t* s_new, double** old_out,
              double** new_out, hipStream_t st);
-void release_net(Plan& p);
+void release_net(Plan& p);               // frees the host view only
+size_t net_bytes_for(const Plan& p);     // device bytes of the network buffers for max_batch fields
+int bind_net(Plan& p);                   // host view of the buffers at p.net_base
+
+// Workspace layout and set-up shared by plan creation and the size query.
+constexpr long FIT_ACC_DOUBLES = 2 * (MAX_TERMS_ABI + 2) * (MAX_TERMS_ABI + 2);
+size_t plan_layout(Plan& p, int32_t flags, char* base);
+int plan_init(Plan& p, hipStream_t st);
 
 }  // namespace slq
 

@@ -60,7 +60,7 @@ static dim3 grid_nn(const Plan& p, int batch) {
 // Number of boundaries strictly below L: the entries of the left stack.
 static int n_left(const Plan& p) { return (p.L - 1) / p.m.n_stab; }
 
-static size_t stack_bytes(const Plan& p, long batch) {
+size_t stack_bytes_for(const Plan& p, long batch) {
   const long N = p.n;
   return sizeof(double) * (size_t)(n_left(p) + 1) * batch * (2 * N * N + N) + sizeof(int32_t) * batch;
 }
@@ -76,24 +76,10 @@ static UdvRef entry(Plan& p, int e) {
   return UdvRef{base, base + 2 * B * NN, base + B * NN, nref};
 }
 
-static int ensure_stack(Plan& p, int batch) {
-  if (p.stack && p.stack_batch >= batch) return SLQ_OK;
-  release_stack(p);
-  const size_t bytes = stack_bytes(p, batch);
-  if (hipMalloc((void**)&p.stack, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    p.stack = nullptr;
-    set_error("cannot allocate the " + std::to_string(bytes >> 20) + " MiB of stabilised partial products");
-    return SLQ_ERR_DEVICE;
-  }
-  p.stack_batch = batch;
-  return SLQ_OK;
-}
-
-void release_stack(Plan& p) {
-  if (p.stack) (void)hipFree(p.stack);
-  p.stack = nullptr;
-  p.stack_batch = 0;
+static int need_stack(const Plan& p) {
+  if (p.stack) return SLQ_OK;
+  set_error("the plan was created without SLQ_PLAN_SWEEPS (no room for the stacked partial products)");
+  return SLQ_ERR_WORKSPACE;
 }
 
 // Product of the count slices first, first + step, ... (0-based), the first
@@ -305,7 +291,7 @@ int sweep_stacked(Plan& p, int batch, int8_t* s, double* G, double* logabs, int8
                   int32_t* status, hipStream_t st) {
   const int N = p.n, L = p.L, ns = p.m.n_stab;
   const long NN = (long)N * N;
-  SLQ_TRY(ensure_stack(p, batch));
+  SLQ_TRY(need_stack(p));
   GemmArgs w1{};  // Xa = E diag(d_l) G
   w1.M = N;
   w1.N = N;
@@ -363,7 +349,7 @@ int sweep_stacked(Plan& p, int batch, int8_t* s, double* G, double* logabs, int8
       if (l % ns == 0) {
         SLQ_TRY(extend_right(p, batch, s, l, status, st));
         SLQ_TRY(fresh_green(p, batch, l, status, st));
-        SLQ_TRY(launch_drift(p, batch, G, p.Xa, drift, st));
+        SLQ_TRY(launch_drift(p, batch, G, p.Xa, drift, status, st));
       }
     }
   }

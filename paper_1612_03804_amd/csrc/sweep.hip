@@ -363,9 +363,11 @@ int launch_flip_slice(Plan& p, int batch, int8_t* s, double* G, double* logabs, 
   return SLQ_OK;
 }
 
-// drift[b] = max(drift[b], max |Gw - Gf|); Gw <- Gf
+// drift[b] = max(drift[b], max |Gw - Gf|); Gw <- Gf.  The maximum propagates
+// NaN (a non-finite wrapped G must show in the drift), and a non-finite drift
+// sets SLQ_ST_NONFINITE in status[b].
 __global__ __launch_bounds__(256) void k_drift_replace(int N, double* __restrict__ Gw, const double* __restrict__ Gf,
-                                                       double* drift) {
+                                                       double* drift, int32_t* status) {
   __shared__ double red[4];
   const int b = blockIdx.x;
   const long NN = (long)N * N;
@@ -373,20 +375,22 @@ __global__ __launch_bounds__(256) void k_drift_replace(int N, double* __restrict
   for (long idx = threadIdx.x; idx < NN; idx += 256) {
     const double f = Gf[b * NN + idx];
     const double d = fabs(Gw[b * NN + idx] - f);
-    m = (d > m || d != d) ? d : m;
+    m = nan_max(m, d);
     Gw[b * NN + idx] = f;
   }
-  m = wave_max(m);
+  m = wave_max_nan(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    drift[b] = fmax(drift[b], t);
+    const double t = nan_max(nan_max(red[0], red[1]), nan_max(red[2], red[3]));
+    const double d = nan_max(drift[b], t);
+    drift[b] = d;
+    if (!isfinite(d) && status) status[b] |= SLQ_ST_NONFINITE;
   }
 }
 
-int launch_drift(Plan& p, int batch, double* Gw, const double* Gf, double* drift, hipStream_t st) {
-  k_drift_replace<<<batch, 256, 0, st>>>(p.n, Gw, Gf, drift);
+int launch_drift(Plan& p, int batch, double* Gw, const double* Gf, double* drift, int32_t* status, hipStream_t st) {
+  k_drift_replace<<<batch, 256, 0, st>>>(p.n, Gw, Gf, drift, status);
   SLQ_LAUNCHED();
   return SLQ_OK;
 }

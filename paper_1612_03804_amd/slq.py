@@ -17,13 +17,15 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libslq.so")
 
 SLQ_OK, SLQ_ERR_ARG, SLQ_ERR_DEVICE, SLQ_ERR_WORKSPACE, SLQ_ERR_NUMERIC = 0, -1, -2, -3, -4
-SLQ_ST_BAD_SPIN, SLQ_ST_NONFINITE, SLQ_ST_SINGULAR = 1, 2, 4
+SLQ_ST_BAD_SPIN, SLQ_ST_NONFINITE, SLQ_ST_SINGULAR, SLQ_ST_PIVOT = 1, 2, 4, 8
+SLQ_PLAN_SWEEPS, SLQ_PLAN_NET = 1, 2
 SLQ_PREC_FP64, SLQ_PREC_FP32, SLQ_PREC_BF16, SLQ_PREC_FP64_DENSE = 0, 1, 2, 3
 
 # every exported symbol of include/slq.h
 EXPORTS = (
-    "slq_version", "slq_last_error", "slq_plan_create", "slq_plan_destroy", "slq_plan_bytes", "slq_kinetic",
-    "slq_profile_enable", "slq_profile_read",
+    "slq_version", "slq_last_error", "slq_plan_workspace_size", "slq_plan_create", "slq_plan_destroy",
+    "slq_plan_bytes", "slq_kinetic", "slq_eff_workspace_size",
+    "slq_profile_enable", "slq_profile_read", "slq_profile_read_part",
     "slq_weight", "slq_green", "slq_udv", "slq_sweep_local", "slq_eff_create", "slq_eff_destroy",
     "slq_eff_classes", "slq_eff_set_theta", "slq_eff_sweep", "slq_eff_features", "slq_cumulative_step",
     "slq_fit_effective", "slq_group_create", "slq_group_destroy", "slq_group_layout", "slq_group_describe",
@@ -63,7 +65,9 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "slq_version": ([], C.c_char_p),
         "slq_last_error": ([], C.c_char_p),
-        "slq_plan_create": ([C.POINTER(slq_model), i32, C.POINTER(P)], C.c_int),
+        "slq_plan_workspace_size": ([C.POINTER(slq_model), i32, i32, C.POINTER(C.c_size_t)], C.c_int),
+        "slq_plan_create": ([C.POINTER(slq_model), i32, i32, P, C.c_size_t, C.POINTER(P)], C.c_int),
+        "slq_eff_workspace_size": ([P, i32, C.POINTER(C.c_size_t)], C.c_int),
         "slq_plan_destroy": ([P], C.c_int),
         "slq_plan_bytes": ([P, C.POINTER(C.c_size_t)], C.c_int),
         "slq_plan_tune": ([P, i32, C.POINTER(i32), P], C.c_int),
@@ -71,11 +75,13 @@ def load_library(path: str = LIB_PATH):
         "slq_kinetic": ([P, i32, P, P], C.c_int),
         "slq_profile_enable": ([P, i32], C.c_int),
         "slq_profile_read": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int),
+        "slq_profile_read_part": ([P, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)],
+                                  C.c_int),
         "slq_weight": ([P, i32, P, P, P, P, P], C.c_int),
         "slq_green": ([P, i32, P, P, P, P, P, P], C.c_int),
         "slq_udv": ([P, i32, P, i32, P, P, P, P, P], C.c_int),
         "slq_sweep_local": ([P, i32, P, P, P, P, i32, u64, u64, u64, P, P, P, P], C.c_int),
-        "slq_eff_create": ([P, i32, P, P, dbl, C.POINTER(P)], C.c_int),
+        "slq_eff_create": ([P, i32, P, P, dbl, P, C.c_size_t, C.POINTER(P)], C.c_int),
         "slq_eff_destroy": ([P], C.c_int),
         "slq_eff_classes": ([P, C.POINTER(i32)], C.c_int),
         "slq_eff_set_theta": ([P, P, P], C.c_int),
@@ -130,19 +136,35 @@ def _need(t, dtype, shape, name):
 
 
 # ------------------------------------------------------------------ plan ----
-class Plan:
-    """Owns an slq_plan (device workspace for one model and max_batch fields)."""
+def slq_plan_workspace_size(model, max_batch: int, chain_prec: int = 0, flags: int = 0) -> int:
+    v = C.c_size_t()
+    m = slq_model.of(model, chain_prec)
+    _check(load_library().slq_plan_workspace_size(C.byref(m), int(max_batch), int(flags), C.byref(v)))
+    return v.value
 
-    def __init__(self, model, max_batch: int, chain_prec: int = 0):
+
+class Plan:
+    """Owns an slq_plan (device workspace for one model and max_batch fields).
+
+    sweeps / net add the sections of local sweeps and of the network calls.
+    workspace: a caller-owned uint8 device tensor of at least
+    slq_plan_workspace_size bytes (256-byte aligned), or None for a plan that
+    allocates its own at creation."""
+
+    def __init__(self, model, max_batch: int, chain_prec: int = 0, sweeps: bool = False, net: bool = False,
+                 workspace=None):
         lib = load_library()
         self.model = model
         self.n = model.lx * model.ly
         self.L = model.n_slices
         self.max_batch = max_batch
         self.chain_prec = int(chain_prec)
+        self.flags = (SLQ_PLAN_SWEEPS if sweeps else 0) | (SLQ_PLAN_NET if net else 0)
         self._m = slq_model.of(model, chain_prec)
+        self.workspace = workspace   # kept alive as long as the plan
+        ptr, nbytes = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
         h = C.c_void_p()
-        _check(lib.slq_plan_create(C.byref(self._m), max_batch, C.byref(h)))
+        _check(lib.slq_plan_create(C.byref(self._m), max_batch, self.flags, ptr, nbytes, C.byref(h)))
         self.handle = h
 
     def close(self):
@@ -163,8 +185,9 @@ class Plan:
         return v.value
 
 
-def slq_plan_create(model, max_batch: int, chain_prec: int = 0) -> Plan:
-    return Plan(model, max_batch, chain_prec)
+def slq_plan_create(model, max_batch: int, chain_prec: int = 0, sweeps: bool = False, net: bool = False,
+                    workspace=None) -> Plan:
+    return Plan(model, max_batch, chain_prec, sweeps, net, workspace)
 
 
 def slq_plan_destroy(plan: Plan):
@@ -200,10 +223,14 @@ def slq_profile_enable(plan: Plan, enable: bool = True):
     _check(load_library().slq_profile_enable(plan.handle, int(bool(enable))))
 
 
-def slq_profile_read(plan: Plan):
-    """(summed ms, launches, algorithmic flops) of the timed chain-product GEMMs."""
+SLQ_PROFILE_CHAIN, SLQ_PROFILE_STAB, SLQ_PROFILE_FINISH = 0, 1, 2
+
+
+def slq_profile_read(plan: Plan, part: int = SLQ_PROFILE_CHAIN):
+    """(summed ms, launch sequences, algorithmic flops) of one profiled part:
+    chain products, stabilisations or the final step."""
     ms, n, fl = C.c_double(), C.c_int64(), C.c_double()
-    _check(load_library().slq_profile_read(plan.handle, C.byref(ms), C.byref(n), C.byref(fl)))
+    _check(load_library().slq_profile_read_part(plan.handle, int(part), C.byref(ms), C.byref(n), C.byref(fl)))
     return ms.value, n.value, fl.value
 
 
@@ -256,7 +283,7 @@ def slq_sweep_local(plan: Plan, s, G, logabs, sign, n_sweeps: int, seed: int, sw
 class Eff:
     """Owns an slq_eff (terms, couplings and colour classes on the device)."""
 
-    def __init__(self, plan: Plan, terms, lam, c0: float = 0.0):
+    def __init__(self, plan: Plan, terms, lam, c0: float = 0.0, workspace=None):
         import numpy as np
         lib = load_library()
         self.plan = plan
@@ -265,9 +292,11 @@ class Eff:
         lm = np.ascontiguousarray(np.asarray(lam, dtype=np.float64).reshape(-1))
         if len(lm) != len(self.terms):
             raise SlqError("lambda must have one entry per term")
+        self.workspace = workspace
+        ptr, nbytes = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
         h = C.c_void_p()
         _check(lib.slq_eff_create(plan.handle, len(self.terms), t.ctypes.data_as(C.c_void_p),
-                                  lm.ctypes.data_as(C.c_void_p), float(c0), C.byref(h)))
+                                  lm.ctypes.data_as(C.c_void_p), float(c0), ptr, nbytes, C.byref(h)))
         self.handle = h
         self.n_terms = len(self.terms)
 
@@ -289,8 +318,14 @@ class Eff:
             pass
 
 
-def slq_eff_create(plan: Plan, terms, lam, c0: float = 0.0) -> Eff:
-    return Eff(plan, terms, lam, c0)
+def slq_eff_workspace_size(plan: Plan, n_terms: int) -> int:
+    v = C.c_size_t()
+    _check(load_library().slq_eff_workspace_size(plan.handle, int(n_terms), C.byref(v)))
+    return v.value
+
+
+def slq_eff_create(plan: Plan, terms, lam, c0: float = 0.0, workspace=None) -> Eff:
+    return Eff(plan, terms, lam, c0, workspace)
 
 
 def slq_eff_destroy(eff: Eff):

@@ -36,7 +36,7 @@ def test_forward_matches_oracle(slq, prec, tol):
     m = Model(6, 5, 7)
     p = params_for_test(1)
     fields = iid_fields(m, 3, 50)
-    plan = slq.Plan(m, 3)
+    plan = slq.Plan(m, 3, net=True)
     S = torch.empty(3, dtype=torch.float64, device="cuda")
     slq.slq_net_forward(plan, prec, dev(fields), dev(p), S)
     got = host(S)
@@ -55,7 +55,7 @@ def test_gradient_matches_oracle(slq, prec, tol):
     y = np.array([stable.weight(m, f)[0] for f in fields])
     lam = np.random.default_rng(3).normal(scale=0.05, size=len(terms))
     c0 = float(np.mean(y))
-    plan = slq.Plan(m, 4)
+    plan = slq.Plan(m, 4, net=True)
     eff = slq.Eff(plan, terms, lam, c0)
     g = torch.empty(net.N_PARAMS, dtype=torch.float64, device="cuda")
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -88,7 +88,7 @@ def test_moves_with_learned_action_match_oracle(slq):
     lam = np.random.default_rng(4).normal(scale=0.1, size=len(terms))
     p = params_for_test(5)
     fields = iid_fields(m, 2, 70)
-    plan = slq.Plan(m, 2)
+    plan = slq.Plan(m, 2, net=True)
     eff = slq.Eff(plan, terms, lam)
     slq.slq_eff_set_net(eff, dev(p), 0)
     classes = effective.colour_classes(m, terms, 4)
@@ -116,7 +116,7 @@ def test_cumulative_steps_with_learned_action_match_oracle(slq):
     p = params_for_test(6)
     p[1960:1968] *= 0.1
     fields = iid_fields(m, 2, 90)
-    plan = slq.Plan(m, 2)
+    plan = slq.Plan(m, 2, net=True)
     eff = slq.Eff(plan, terms, lam, c0)
     slq.slq_eff_set_net(eff, dev(p), 0)
     classes = effective.colour_classes(m, terms, 4)
@@ -152,7 +152,7 @@ def test_trained_network_gains_over_linear_model(slq):
     terms = [t for t in default_terms(10) if t != (0, 0)]
     n_tr, n_te, B = 768, 256, 64
     fields = iid_fields(m, n_tr + n_te, 100)
-    plan = slq.Plan(m, 256)
+    plan = slq.Plan(m, 256, net=True)
     s_all = dev(fields)
     y = torch.empty(n_tr + n_te, dtype=torch.float64, device="cuda")
     sg = torch.empty(256, dtype=torch.int8, device="cuda")
@@ -190,3 +190,20 @@ def test_trained_network_gains_over_linear_model(slq):
     trained = test_loss(prm)
     print(f"held-out MSE: linear {base:.3e}, linear + network {trained:.3e}, linear R2 {host(r2)[0]:.6f}")
     assert np.isfinite(trained) and trained < 0.8 * base
+
+
+def test_fp32_network_is_refused_for_proposals(slq):
+    """Proposals with the learned action keep the network's activations up to
+    date incrementally; only FP64 keeps a move and its reverse exact negatives
+    (to round-off), which Eq. 4 needs, so attaching in FP32 is an error."""
+    from tests.gpu_util import dev
+    m = Model(6, 5, 6)
+    terms = default_terms(6)
+    plan = slq.Plan(m, 1)
+    eff = slq.Eff(plan, terms, np.zeros(len(terms)))
+    with pytest.raises(slq.SlqError):
+        slq.slq_eff_set_net(eff, dev(params_for_test(5)), slq.SLQ_PREC_FP32)
+    slq.slq_eff_set_net(eff, dev(params_for_test(5)), slq.SLQ_PREC_FP64)
+    slq.slq_eff_set_net(eff, None)
+    eff.close()
+    plan.close()
