@@ -186,6 +186,25 @@ int slq_weight(slq_plan* plan, int32_t batch, const int8_t* d_s,
                double* d_logabs, int8_t* d_sign, int32_t* d_status, hipStream_t stream);
 
 /*
+ * slq_weight_static - slq_weight without a plan and without allocating
+ * anything, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * plan's workspace is laid out in a file-scope device array of
+ * SLQ_STATIC_SCRATCH_BYTES, one per GPU the library runs on (held until the
+ * process ends); E and E^{-1} are rebuilt in it on every call, nothing is
+ * carried over from an earlier call.  Every call on one GPU shares that
+ * array: calls that overlap in time on one GPU race (serialise them, e.g. on
+ * one stream).  FP64 chains (SLQ_PREC_FP64, SLQ_PREC_FP64_DENSE) only.
+ * Arguments and results as slq_weight, for `batch` fields of `model`.
+ * Errors: SLQ_ERR_ARG, SLQ_ERR_WORKSPACE (the model and batch need more
+ * than SLQ_STATIC_SCRATCH_BYTES: slq_plan_workspace_size with flags 0 tells
+ * how much), SLQ_ERR_DEVICE.
+ */
+#define SLQ_STATIC_SCRATCH_BYTES (64u << 20)
+int slq_weight_static(const slq_model* model, int32_t batch, const int8_t* d_s, double* d_logabs,
+                      int8_t* d_sign, int32_t* d_status, hipStream_t stream);
+
+/*
  * slq_green - as slq_weight, and also the equal-time Green's function
  * d_G[b] = (1 + B_L...B_1)^{-1}, FP64 [batch][N][N] row-major.
  */

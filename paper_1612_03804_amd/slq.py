@@ -31,6 +31,7 @@ EXPORTS = (
     "slq_fit_effective", "slq_group_create", "slq_group_destroy", "slq_group_layout", "slq_group_describe",
     "slq_group_weight", "slq_group_green", "slq_magnetization", "slq_net_forward", "slq_net_gradient",
     "slq_net_adam", "slq_eff_set_net", "slq_eff_net_classes", "slq_plan_tune", "slq_plan_set_block_width",
+    "slq_weight_static",
 )
 SLQ_NET_PARAMS = 1969
 
@@ -101,6 +102,7 @@ def load_library(path: str = LIB_PATH):
         "slq_net_adam": ([i32, P, P, P, P, i64, dbl, dbl, dbl, dbl, P], C.c_int),
         "slq_eff_set_net": ([P, P, i32, P], C.c_int),
         "slq_eff_net_classes": ([P, C.POINTER(i32)], C.c_int),
+        "slq_weight_static": ([C.POINTER(slq_model), i32, P, P, P, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
