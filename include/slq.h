@@ -436,6 +436,66 @@ int slq_fit_effective(slq_plan* plan, const slq_eff* eff, int64_t n_samples,
                       const int8_t* d_S, const double* d_logabs,
                       double* d_theta, double* d_r2, hipStream_t stream);
 
+/*
+ * The paper's own workload ("Results", Eq. 6): spin-1/2 fermions on a bilayer
+ * (intralayer hopping t, chemical potential mu of the plan's model) coupled
+ * by H_sf = -xi sum_i s^z_i (sigma^z_{i1} - sigma^z_{i2}) to transverse-field
+ * Ising spins H_s = -J sum_<ij> s^z s^z - h sum_i s^x.  The field s_{i,l}
+ * (int8 [batch][L][N], one spin per site of the layer pair and slice) has the
+ * sign-free weight
+ *   omega(s) = phi(s) [W_f(s) W_f(-s)]^2,
+ * W_f the single-flavour determinant of this header (two of the four flavours
+ * see xi s, two -xi s), and phi the weight of the Ising spins alone (Eq. 1's
+ * bare part), from the quantum-to-classical mapping of H_s:
+ *   ln phi = dtau J sum_l sum_<ij> s_{i,l} s_{j,l} + K_tau sum_{i,l} s_{i,l} s_{i,l+1},
+ *   K_tau = -1/2 ln tanh(dtau h)   (up to a constant; bonds as in K).
+ * Every call evaluates 2 batch fields [s ; -s], so the plan's max_batch must
+ * be >= 2 batch (else SLQ_ERR_WORKSPACE); FP64 chains only; h > 0;
+ * lx, ly, L >= 2.
+ */
+typedef struct slq_bilayer {
+  double J;  /* ferromagnetic Ising coupling */
+  double h;  /* transverse field, > 0 */
+} slq_bilayer;
+
+/* d_logw[b] = ln omega(s_b) (-inf when a determinant vanishes). */
+int slq_bilayer_weight(slq_plan* plan, const slq_bilayer* bl, int32_t batch, const int8_t* d_s,
+                       double* d_logw, int32_t* d_status, hipStream_t stream);
+/* As slq_bilayer_weight, and d_G FP64 [2 batch][N][N]: G of s_b at b and of
+ * -s_b at batch + b (the chain B_L ... B_1). */
+int slq_bilayer_green(slq_plan* plan, const slq_bilayer* bl, int32_t batch, const int8_t* d_s, double* d_G,
+                      double* d_logw, int32_t* d_status, hipStream_t stream);
+/*
+ * slq_bilayer_sweep_local - local-update sweeps of the bilayer weight
+ * ("Basics of DQMC") in place: sites ascending within slices 1..L; the flip
+ * of s_{i,l} has ratio phi'/phi (R_a R_b)^2, R_a = 1 + delta_a (1 - G_a,ii),
+ * delta_a = exp(2 dtau xi s_{i,l}) - 1 from the G of s, R_b likewise from the
+ * G of -s with delta_b = exp(-2 dtau xi s_{i,l}) - 1; accepted iff u < ratio,
+ * u from key (seed, 1), counter (i, l-1, sweep0 + k, chain0 + b); both
+ * Green's functions then take their Sherman-Morrison update (undelayed),
+ * are wrapped after each slice and recomputed from the cyclic chain every
+ * n_stab slices, recording the drift.
+ * d_G [2 batch][N][N] holds the incoming Green's functions (slq_bilayer_green)
+ * and the outgoing ones; d_logw is advanced by ln ratio of accepted flips.
+ * Out (may be NULL): d_accepts int64 [batch], d_drift FP64 [batch], d_status.
+ */
+int slq_bilayer_sweep_local(slq_plan* plan, const slq_bilayer* bl, int32_t batch, int8_t* d_s, double* d_G,
+                            double* d_logw, int32_t n_sweeps, uint64_t seed, uint64_t sweep0, uint64_t chain0,
+                            int64_t* d_accepts, double* d_drift, int32_t* d_status, hipStream_t stream);
+/*
+ * slq_bilayer_cumulative_step - one cumulative update (Eq. 4) of each chain
+ * with the bilayer weight as the judge: effective moves as slq_eff_sweep
+ * (same counters as slq_cumulative_step), logA = [ln omega(s') - ln omega(s)]
+ * - [S_eff(s') - S_eff(s)], accepted iff ln u < min(0, logA) (u from key
+ * (seed, 3), counter (0, 0, step, chain0 + b)); on acceptance s and d_logw
+ * are replaced.  d_logw must hold ln omega of the incoming fields.
+ * Out (may be NULL): d_accepted int8 [batch], d_logA FP64 [batch], d_status.
+ */
+int slq_bilayer_cumulative_step(slq_plan* plan, const slq_eff* eff, const slq_bilayer* bl, int32_t batch,
+                                int8_t* d_s, double* d_logw, int32_t n_moves, uint64_t seed, uint64_t step,
+                                uint64_t chain0, int8_t* d_accepted, double* d_logA, int32_t* d_status,
+                                hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

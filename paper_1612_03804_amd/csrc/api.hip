@@ -313,7 +313,8 @@ size_t plan_layout(Plan& p, int32_t flags, char* base) {
                oSt2 = take(4 * B);
   const size_t oSw = take((size_t)p.L * N * B), oDv = take(8 * B), oDv2 = take(8 * B), oIv = take(8 * B);
   const size_t oX = take(8 * N * SWEEP_KD * B), oY = take(8 * N * SWEEP_KD * B), oA = take(8 * SWEEP_KD * B);
-  const size_t oFo = take(8 * 64 * B), oFn = take(8 * 64 * B), oSg = take(B), oKw = take(8 * 8 * 64);
+  const size_t oFo = take(8 * 64 * B), oFn = take(8 * 64 * B), oSg = take(B), oSg2 = take(B),
+               oKw = take(8 * 8 * 64);
   const size_t oFit = take(8 * FIT_ACC_DOUBLES);
   const size_t oQw = take(N > 64 ? 8 * (size_t)qr_workspace_per_field((int)N) * B : 8);
   const size_t oStack = (flags & SLQ_PLAN_SWEEPS) ? take(stack_bytes_for(p, B)) : 0;
@@ -353,6 +354,7 @@ size_t plan_layout(Plan& p, int32_t flags, char* base) {
   p.F_old = (double*)(c + oFo);
   p.F_new = (double*)(c + oFn);
   p.sgn_work = (int8_t*)(c + oSg);
+  p.sgn_work2 = (int8_t*)(c + oSg2);
   p.kron_w = (double*)(c + oKw);
   p.fit_acc = (double*)(c + oFit);
   p.qrws = (double*)(c + oQw);

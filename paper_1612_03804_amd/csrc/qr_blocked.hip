@@ -218,8 +218,9 @@ struct PanelArgs {
 // forms and publishes reflector c+1 at once, into the other of two buffers)
 // and adds the Gram entries v_i . v_c of its finished columns i < c.  T
 // (Q_panel = I - V T V^T) follows from the Gram matrix at the end.
-template <int NB, int RPL, bool CACHE_V>
-__global__ __launch_bounds__(PQ_THREADS) __attribute__((amdgpu_waves_per_eu(NB == 32 ? 4 : 1))) void k_panel(PanelArgs a) {
+template <int NB, int RPL, bool CACHE_V, int TH>
+__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(TH == 1024 ? 4 : (NB == 32 ? 4 : 1)))) void k_panel(PanelArgs a) {
+  constexpr int PQ_THREADS = TH, PQ_WAVES = TH / 64;
   extern __shared__ double lds[];
   constexpr int CPW = NB >= PQ_WAVES ? NB / PQ_WAVES : 1;  // columns per wave
   constexpr int LT = NB + 1;                 // padded row stride of T and the Gram matrix
@@ -512,7 +513,7 @@ __global__ void k_zero_i32(int32_t* x, int n) {
 // the large updates have row and column counts that are multiples of the
 // 128 x 64 tiles (N = 400: 384 x 256 and 256 x 128 instead of 400 x 272 and
 // 272 x 144).
-template <int NB, int RPL>
+template <int NB, int RPL, int TH = PQ_THREADS>
 static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st,
                        const double* norm2, bool form_q) {
   const int N = p.n;
@@ -566,6 +567,13 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     if (rc == SLQ_OK) rc = gemm(m, n, k, Vp, N, NN, false, Wt2, N, sW, Bp, N, NN, -1.0, 1.0);
     return rc;
   };
+  // How T_O grows panel by panel: with narrow panels (many per block) from one
+  // Gram product V_O^T V_O and k_tbuild after the block's panels (at N = 2304,
+  // 8-column panels: 36 ms per 64-field evaluation against 150 ms of thin
+  // products), with wide ones by three small products per panel (at N = 400,
+  // 32-column panels over 512 fields the one-workgroup-per-CU k_tbuild takes
+  // 7.8 ms per evaluation, the products less)
+  constexpr bool GRAM_T = NB <= 8;
   const int rr = N % NBO;  // width of the short first block (0: none)
   auto bstart = [&](int ob) { return rr == 0 ? ob * NBO : (ob == 0 ? 0 : rr + (ob - 1) * NBO); };
   auto bwidth = [&](int ob) { return rr == 0 ? NBO : (ob == 0 ? rr : NBO); };
@@ -578,13 +586,19 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
       PanelArgs a{N, j0, nbw, p.W, Vbuf, J0, Tp, sW, NBO, wo - sft, o.D, p.invD, o.nref, status};
       const size_t lds = sizeof(double) * ((size_t)NB * 65 + 2 * 64 * RPL + 2 * NB * (NB + 1) + NB);
       constexpr bool CACHE = PanelShape<NB, RPL>::CACHE;
-      allow_max_lds((const void*)k_panel<NB, RPL, CACHE>);
-      k_panel<NB, RPL, CACHE><<<batch, PQ_THREADS, lds, st>>>(a);
+      allow_max_lds((const void*)k_panel<NB, RPL, CACHE, TH>);
+      k_panel<NB, RPL, CACHE, TH><<<batch, TH, lds, st>>>(a);
       SLQ_LAUNCHED();
       const int nin = wo - sft - nbw;  // rest of the outer block
       if (nin > 0) SLQ_TRY(apply(Vbuf + (long)j0 * N + j0, Tp, nbw, p.W + (long)j0 * N + j0 + nbw, m, nin, true));
+      if (!GRAM_T && sft > 0) {  // T_O[0:sft, sft:sft+nbw] = -T_O[0:sft, 0:sft] (V_A^T V_B) T_B, rows j0.. only
+        SLQ_TRY(gemm(sft, nbw, m, Vbuf + (long)j0 * N + J0, N, NN, true, Vbuf + (long)j0 * N + j0, N, NN, Gb, NBO,
+                     sW, 1.0, 0.0));
+        SLQ_TRY(gemm(sft, nbw, nbw, Gb, NBO, sW, false, Tp, NBO, sW, Wt2, N, sW, 1.0, 0.0));
+        SLQ_TRY(gemm(sft, nbw, sft, Tb, NBO, sW, false, Wt2, N, sW, Tb + sft, NBO, sW, -1.0, 0.0));
+      }
     }
-    if (wo > NB) {  // T_O of the whole block from its Gram matrix (rows J0.. of V_O)
+    if (GRAM_T && wo > NB) {  // T_O of the whole block from its Gram matrix (rows J0.. of V_O)
       GemmArgs gg{};
       gg.M = wo;
       gg.N = wo;
@@ -660,8 +674,8 @@ int launch_qr_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int3
                       const double* norm2, bool form_q) {
   if (p.n <= 448) return run_blocked<32, 7>(p, batch, X, o, status, st, norm2, form_q);
   if (p.n <= 1152) return run_blocked<16, 18>(p, batch, X, o, status, st, norm2, form_q);
-  // (16 columns at 38 rows per lane would need more than the 256 registers a
-  // wave of a 512-thread workgroup can hold)
+  // (16 columns at 38 rows per lane spill registers both as two columns per
+  // wave of 512 threads and as one per wave of 1024)
   return run_blocked<8, 38>(p, batch, X, o, status, st, norm2, form_q);
 }
 

@@ -221,6 +221,7 @@ struct Plan {
   // cumulative updates
   double *F_old, *F_new;    // [max_batch][64] effective-action features
   int8_t* sgn_work;         // [max_batch]
+  int8_t* sgn_work2;        // [max_batch]
   // optional event timing of the chain-product GEMM launches
   // parts: SLQ_PROFILE_CHAIN, SLQ_PROFILE_STAB, SLQ_PROFILE_FINISH
   bool prof = false;

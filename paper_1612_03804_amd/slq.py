@@ -31,6 +31,7 @@ EXPORTS = (
     "slq_fit_effective", "slq_group_create", "slq_group_destroy", "slq_group_layout", "slq_group_describe",
     "slq_group_weight", "slq_group_green", "slq_magnetization", "slq_net_forward", "slq_net_gradient",
     "slq_net_adam", "slq_eff_set_net", "slq_eff_net_classes", "slq_plan_tune", "slq_plan_set_block_width",
+    "slq_bilayer_weight", "slq_bilayer_green", "slq_bilayer_sweep_local", "slq_bilayer_cumulative_step",
     "slq_weight_static",
 )
 SLQ_NET_PARAMS = 1969
@@ -48,6 +49,10 @@ class slq_model(C.Structure):
     @classmethod
     def of(cls, m, chain_prec: int = 0) -> "slq_model":
         return cls(m.lx, m.ly, m.n_slices, m.n_stab, m.t, m.mu, m.dtau, m.xi, int(chain_prec))
+
+
+class slq_bilayer(C.Structure):
+    _fields_ = [("J", C.c_double), ("h", C.c_double)]
 
 
 _lib = None
@@ -103,6 +108,12 @@ def load_library(path: str = LIB_PATH):
         "slq_eff_set_net": ([P, P, i32, P], C.c_int),
         "slq_eff_net_classes": ([P, C.POINTER(i32)], C.c_int),
         "slq_weight_static": ([C.POINTER(slq_model), i32, P, P, P, P, P], C.c_int),
+        "slq_bilayer_weight": ([P, C.POINTER(slq_bilayer), i32, P, P, P, P], C.c_int),
+        "slq_bilayer_green": ([P, C.POINTER(slq_bilayer), i32, P, P, P, P, P], C.c_int),
+        "slq_bilayer_sweep_local": ([P, C.POINTER(slq_bilayer), i32, P, P, P, i32, u64, u64, u64, P, P, P, P],
+                                    C.c_int),
+        "slq_bilayer_cumulative_step": ([P, P, C.POINTER(slq_bilayer), i32, P, P, i32, u64, u64, u64, P, P, P, P],
+                                        C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -474,3 +485,46 @@ def slq_eff_net_classes(eff: Eff) -> int:
     v = C.c_int32()
     _check(load_library().slq_eff_net_classes(eff.handle, C.byref(v)))
     return v.value
+
+
+# ------------------------------------------------------ bilayer workload ----
+def _bl(J: float, h: float):
+    return C.byref(slq_bilayer(float(J), float(h)))
+
+
+def slq_bilayer_weight(plan: Plan, J: float, h: float, s, logw, status=None, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(logw, torch.float64, (b,), "logw")
+    _check(load_library().slq_bilayer_weight(plan.handle, _bl(J, h), b, _ptr(s), _ptr(logw), _ptr(status),
+                                             _stream(stream)))
+
+
+def slq_bilayer_green(plan: Plan, J: float, h: float, s, G, logw, status=None, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(G, torch.float64, (2 * b, plan.n, plan.n), "G")
+    _need(logw, torch.float64, (b,), "logw")
+    _check(load_library().slq_bilayer_green(plan.handle, _bl(J, h), b, _ptr(s), _ptr(G), _ptr(logw), _ptr(status),
+                                            _stream(stream)))
+
+
+def slq_bilayer_sweep_local(plan: Plan, J: float, h: float, s, G, logw, n_sweeps: int, seed: int, sweep0: int,
+                            chain0: int, accepts=None, drift=None, status=None, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(G, torch.float64, (2 * b, plan.n, plan.n), "G")
+    _need(logw, torch.float64, (b,), "logw")
+    _check(load_library().slq_bilayer_sweep_local(plan.handle, _bl(J, h), b, _ptr(s), _ptr(G), _ptr(logw),
+                                                  int(n_sweeps), seed, sweep0, chain0, _ptr(accepts), _ptr(drift),
+                                                  _ptr(status), _stream(stream)))
+
+
+def slq_bilayer_cumulative_step(plan: Plan, eff: Eff, J: float, h: float, s, logw, n_moves: int, seed: int,
+                                step: int, chain0: int, accepted=None, logA=None, status=None, stream=None):
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(logw, torch.float64, (b,), "logw")
+    _check(load_library().slq_bilayer_cumulative_step(plan.handle, eff.handle, _bl(J, h), b, _ptr(s), _ptr(logw),
+                                                      int(n_moves), seed, step, chain0, _ptr(accepted), _ptr(logA),
+                                                      _ptr(status), _stream(stream)))

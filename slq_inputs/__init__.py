@@ -57,6 +57,18 @@ DQMC_20x20 = Model(20, 20, 80, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=10)
 MIXED_40x40 = Model(40, 40, 100, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=10)
 LEARNED_48x48 = Model(48, 48, 100, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=10)
 
+# The paper's own workload ("Results"): bilayer, beta = 1, dtau = 0.05 (M = 20
+# slices), xi = 1, at the finite-temperature critical field h = 2.774 quoted
+# for J = 1.  t and mu are not given; t = 1, mu = -0.5 as elsewhere here.
+BILAYER_J = 1.0
+BILAYER_H = 2.774
+
+
+def bilayer_model(linear: int, n_stab: int = 10) -> "Model":
+    """linear x linear layers, L = 20 slices of dtau = 0.05, xi = 1."""
+    return Model(linear, linear, 20, t=1.0, mu=-0.5, dtau=0.05, xi=1.0, n_stab=n_stab)
+
+
 WORKLOADS = {
     "small_4x4": SMALL_4x4,
     "dqmc_20x20": DQMC_20x20,
