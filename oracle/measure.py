@@ -18,13 +18,19 @@ Susceptibility of the Ising spins ("Results"):
         = dtau^2 <M^2> / (beta^2 N),   M = sum_{i,l} s_{i,l},
 (the integral as a sum over slices, time-translation averaged).
 
+Time-displaced Green's function of one configuration:
+    G(tau_l, 0) = <c(tau_l) c^dag(0)> = B_l ... B_1 G,   1 <= l <= L,
+the plain product (valid while it stays well inside the FP64 range, i.e. at
+small beta).
+
 Test infrastructure only.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .lattice import hopping_matrix
+from . import stable
+from .lattice import hopping_matrix, chain_product
 
 
 def equal_time(model, g) -> np.ndarray:
@@ -47,3 +53,9 @@ def equal_time(model, g) -> np.ndarray:
 def susceptibility(model, m2: float) -> float:
     """chi from <M^2> of the total magnetisation M = sum_{i,l} s_{i,l}."""
     return model.dtau ** 2 * m2 / (model.beta ** 2 * model.n_sites)
+
+
+def green_displaced(model, s, l: int) -> np.ndarray:
+    """G(tau_l, 0) = B_l ... B_1 G (plain product; small beta only)."""
+    _, _, g = stable.green(model, s)
+    return chain_product(model, s, range(1, l + 1)) @ g

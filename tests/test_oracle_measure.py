@@ -59,3 +59,20 @@ def test_susceptibility_of_an_ordered_field_is_n():
     m = Model(3, 5, 20, dtau=0.05)
     mtot = m.n_sites * m.n_slices              # s = +1 everywhere
     assert abs(measure.susceptibility(m, float(mtot) ** 2) - m.n_sites) < 1e-12
+
+
+def test_displaced_green_is_the_spacetime_inverse_block():
+    """Block (l-1, L-1) of the inverse of the space-time matrix is
+    -G(tau_l, 0) for l < L, an independent route to the same object; and
+    G(beta, 0) = 1 - G."""
+    from oracle import lattice
+    m = Model(3, 2, 6, t=1.0, mu=-0.3, dtau=0.2, xi=1.1, n_stab=3)
+    s = iid_field(m, 4)
+    n, L = m.n_sites, m.n_slices
+    rhs = np.zeros((n * L, n))
+    rhs[(L - 1) * n:, :] = np.eye(n)
+    col = np.linalg.solve(lattice.spacetime_matrix(m, s), rhs)
+    for l in range(1, L):
+        np.testing.assert_allclose(measure.green_displaced(m, s, l), -col[(l - 1) * n:l * n], atol=1e-13)
+    _, _, g = stable.green(m, s)
+    np.testing.assert_allclose(measure.green_displaced(m, s, L), np.eye(n) - g, atol=1e-13)
