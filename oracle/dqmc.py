@@ -13,7 +13,7 @@ and on acceptance (Sherman-Morrison)
 After all sites of slice l: G_l = B_l G_{l-1} B_l^{-1} (wrap).  Every n_stab
 slices G is recomputed from scratch and the wrap drift max|G - G_fresh| kept.
 
-Build's readings where the paper is silent: Metropolis on |R| with strict
+Readings where the paper is silent: Metropolis on |R| with strict
 u < |R|; slices ascending 1..L, sites ascending 0..N-1; recompute at
 l % n_stab == 0; uniform u from Philox with key (seed, TAG_LOCAL) and counter
 (site, slice-1, sweep, chain).
@@ -62,7 +62,7 @@ def sweep(model, s, g, logabs, sign, *, seed: int, sweep_index: int, chain: int 
         d = field_diagonal(s[l - 1], model.dtau, model.xi)
         g[:, :] = e @ ((d[:, None] * g) / d[None, :]) @ einv
         if l % model.n_stab == 0:
-            fresh = stable.green_at_slice(model, s, l)
+            fresh = stable.green_at_slice(model, s, l, e=e)
             drift = max(drift, float(np.max(np.abs(g - fresh))))
             g[:, :] = fresh
     if want_trace:

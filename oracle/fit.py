@@ -1,7 +1,7 @@
 """Self-learning fit of the effective action (Eq. 3 and the R^2 score of "Results").
 
 Eq. (3) sets -beta H_eff[C] = ln omega[C]; the couplings come from a
-multi-linear regression over the training configurations.  Build's reading:
+multi-linear regression over the training configurations.  Reading taken:
 unweighted ordinary least squares with an intercept on y_n = ln|W_f(s_n)|,
 design rows [1, F_1(s_n), ..., F_K(s_n)], solved by SciPy's least squares.
 R^2 = 1 - sum (y - yhat)^2 / sum (y - ybar)^2, which equals the paper's

@@ -3,7 +3,7 @@
 Follows "Basics of DQMC", Eq. (1): for one auxiliary-field configuration
 C = {s_{i,l}} the fermion weight is det(1 + B(beta,0;C)) with
 B(beta,0) = B^L ... B^1, and each slice matrix is the kinetic propagator times
-the exponential of the field coupling.  Sign conventions (the build's reading):
+the exponential of the field coupling.  Sign conventions (the reading taken):
 
     K_ij = -t for nearest neighbours (bond multiplicity kept on Lx=2), K_ii = -mu
     E    = exp(-dtau K),   d_l = exp(-dtau xi s_{., l}),   B_l = E diag(d_l)

@@ -2,7 +2,7 @@
 (J. K. Salmon, M. A. Moraes, R. O. Dror, D. E. Shaw, "Parallel random numbers:
 as easy as 1, 2, 3", SC'11).  Pure-Python integers; test infrastructure only.
 
-The paper does not say which random numbers it draws; this build's convention
+The paper does not say which random numbers it draws; the convention here
 (shared with the GPU side, which implements the same definition independently):
 
     key = (seed, stream_tag), counter = 4 x uint64 chosen per decision,

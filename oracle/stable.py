@@ -70,9 +70,9 @@ def green(model, s):
     return udv_finish(*udv_chain(model, s))
 
 
-def green_at_slice(model, s, m: int):
+def green_at_slice(model, s, m: int, e=None):
     """G_m = (1 + B_m...B_1 B_L...B_{m+1})^{-1}, stabilised, from the cyclic
-    chain that starts at slice m+1."""
+    chain that starts at slice m+1 (kinetic factor e, default exp(-dtau K))."""
     L = model.n_slices
     order = list(range(m + 1, L + 1)) + list(range(1, m + 1))
-    return udv_finish(*udv_chain(model, s, order))[2]
+    return udv_finish(*udv_chain(model, s, order, e=e))[2]
