@@ -70,12 +70,24 @@ enum {
  * SLQ_PREC_FP64_DENSE: FP64 dense GEMMs with E on the matrix cores.
  * SLQ_PREC_FP32 / SLQ_PREC_BF16: dense GEMMs with E and X rounded to the
  *   operand type at every GEMM, FP32 accumulation on the matrix cores, X kept
- *   in FP32 between slices. */
+ *   in FP32 between slices.
+ * SLQ_PREC_CHECKERBOARD: FP64 with the checkerboard split in place of E
+ *   (the sparse slice matrices behind the beta N^2 chain cost of "Formalism of
+ *   SLDQMC"): the bonds of the torus in four groups of disjoint bonds, x bonds
+ *   from even / odd x (A / B) and y bonds from even / odd y (C / D), and
+ *   E_cb = e^{dtau mu} A' B' C' D C' B' A' with X' the half-step factor
+ *   exp(-dtau K_X / 2) (a 2 x 2 rotation cosh + sinh sigma_x on each bond).
+ *   A different discretisation of the same model: E_cb - E = O(dtau^3), so the
+ *   weight differs from SLQ_PREC_FP64's by O(dtau^2) at fixed beta.  22 N
+ *   flops per vector and slice.  Needs even lx and ly (else SLQ_ERR_ARG);
+ *   slq_kinetic returns E_cb and E_cb^{-1}, and every product of the plan
+ *   (chains, local sweeps, bilayer, measurements) uses them. */
 enum {
   SLQ_PREC_FP64 = 0,
   SLQ_PREC_FP32 = 1,
   SLQ_PREC_BF16 = 2,
-  SLQ_PREC_FP64_DENSE = 3
+  SLQ_PREC_FP64_DENSE = 3,
+  SLQ_PREC_CHECKERBOARD = 4
 };
 
 typedef struct slq_model {
@@ -194,7 +206,8 @@ int slq_weight(slq_plan* plan, int32_t batch, const int8_t* d_s,
  * process ends); E and E^{-1} are rebuilt in it on every call, nothing is
  * carried over from an earlier call.  Every call on one GPU shares that
  * array: calls that overlap in time on one GPU race (serialise them, e.g. on
- * one stream).  FP64 chains (SLQ_PREC_FP64, SLQ_PREC_FP64_DENSE) only.
+ * one stream).  FP64 chains (SLQ_PREC_FP64, SLQ_PREC_FP64_DENSE,
+ * SLQ_PREC_CHECKERBOARD) only.
  * Arguments and results as slq_weight, for `batch` fields of `model`.
  * Errors: SLQ_ERR_ARG, SLQ_ERR_WORKSPACE (the model and batch need more
  * than SLQ_STATIC_SCRATCH_BYTES: slq_plan_workspace_size with flags 0 tells
@@ -229,6 +242,34 @@ int slq_udv(slq_plan* plan, int32_t batch, const int8_t* d_s, int32_t slice0,
  * "Basics of DQMC").  d_s int8 [batch][L][N].
  */
 int slq_magnetization(slq_plan* plan, int32_t batch, const int8_t* d_s, int64_t* d_M, hipStream_t stream);
+
+/*
+ * slq_measure_equal_time - equal-time observables of each Green's function
+ * d_G FP64 [batch][N][N] (G[i][j] = <c_i c_j^dag> as slq_green returns it;
+ * for a given field the fermions are free, so Wick's theorem gives
+ * <c_i^dag c_j> = delta_ij - G_ji and <n_i n_j> = (1 - G_ii)(1 - G_jj) +
+ * (delta_ij - G_ji) G_ij).  d_out FP64 [batch][3]: the density
+ * (1/N) sum_i (1 - G_ii), the hopping energy per site
+ * (1/N) sum_{i != j} K_ij <c_i^dag c_j> (K of "Basics of DQMC" without mu),
+ * and S(pi, pi) = (1/N) sum_ij (-1)^(x_i+y_i+x_j+y_j) <n_i n_j>.  Their Monte
+ * Carlo averages over configurations are the measured observables.
+ * batch may be any size (no workspace).  Errors: SLQ_ERR_ARG.
+ */
+int slq_measure_equal_time(slq_plan* plan, int32_t batch, const double* d_G, double* d_out, hipStream_t stream);
+
+/*
+ * slq_green_displaced - the time-displaced Green's function
+ *   d_Gt[b] = G(tau_l, 0) = <c(tau_l) c^dag(0)> = B_l ... B_1 G,  l = slice,
+ * 1 <= slice <= L, FP64 [batch][N][N] (G(beta, 0) = 1 - G): G from the
+ * stabilised chain, then the slice products applied to it.  Those products
+ * scale G's columns by up to exp(tau ||K + V||), so the result is accurate
+ * while that factor stays far inside the FP64 range relative to G's entries
+ * (beta of a few units at the workloads' couplings); a two-sided stabilised
+ * form is not provided.  Uses the plan's workspace; FP64 products.
+ * Errors: SLQ_ERR_ARG, SLQ_ERR_WORKSPACE, SLQ_ERR_DEVICE.
+ */
+int slq_green_displaced(slq_plan* plan, int32_t batch, const int8_t* d_s, int32_t slice, double* d_Gt,
+                        int32_t* d_status, hipStream_t stream);
 
 /*
  * Groups of independent chains of uneven size.  slq_group_create takes one

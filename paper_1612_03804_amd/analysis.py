@@ -27,16 +27,51 @@ def autocorrelation_chains(m: np.ndarray) -> np.ndarray:
 
 
 def tau_int_chains(m: np.ndarray, c: float = 5.0) -> float:
+    """tau_int with the automatic window, not clamped: a series whose
+    successive values are anticorrelated (e.g. local sweeps that flip most
+    spins) has tau_int < 1/2, i.e. more than one effective sample per step."""
     rho = autocorrelation_chains(m)
     tau = 0.5
     for w in range(1, len(rho)):
         tau += rho[w]
-        if w >= c * tau:
+        if w >= c * max(tau, 0.0):
             break
-    return float(max(tau, 0.5))
+    return float(tau)
 
 
-def effective_samples(m: np.ndarray, c: float = 5.0) -> float:
+def tau_int_window(m: np.ndarray, c: float = 5.0) -> dict:
+    """tau_int with its window W and whether the window condition W >= c tau
+    was met before the lags ran out (T/2); when it was not, tau is a lower
+    bound of the series' integrated autocorrelation time."""
+    rho = autocorrelation_chains(m)
+    tau = 0.5
+    for w in range(1, len(rho)):
+        tau += rho[w]
+        if w >= c * max(tau, 0.0):
+            return {"tau_int": float(tau), "window": w, "converged": True}
+    return {"tau_int": float(tau), "window": len(rho) - 1, "converged": False}
+
+
+def effective_samples(m: np.ndarray, c: float = 5.0) -> float | None:
+    """n / (2 tau_int), None when tau_int is not positive (too short a series)."""
     m = np.asarray(m)
-    n = m.size
-    return n / (2.0 * tau_int_chains(m, c))
+    tau = tau_int_chains(m, c)
+    return m.size / (2.0 * tau) if tau > 0 else None
+
+
+def mean_and_error(x: np.ndarray, c: float = 5.0) -> tuple[float, float]:
+    """Mean of a series [chains, T] and its standard error, the variance of
+    the mean inflated by 2 tau_int (at least the naive error: tau_int is
+    floored at 1/2 here, so an anticorrelated series is not credited with an
+    error below the independent-sample one)."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[None, :]
+    var = float(x.var())
+    tau = max(tau_int_chains(x, c), 0.5) if var > 0 else 0.5
+    return float(x.mean()), float(np.sqrt(var * 2.0 * tau / x.size))
+
+
+def agree(a: tuple[float, float], b: tuple[float, float], sigmas: float = 2.0) -> bool:
+    """Two (mean, error) estimates agree within `sigmas` combined standard errors."""
+    return abs(a[0] - b[0]) <= sigmas * float(np.hypot(a[1], b[1])) + 1e-12 * max(abs(a[0]), abs(b[0]), 1.0)

@@ -90,8 +90,12 @@ static int check_model(const slq_model* m) {
   if (!(m->dtau > 0.0) || !std::isfinite(m->dtau)) return fail(SLQ_ERR_ARG, "dtau must be positive and finite");
   if (!std::isfinite(m->t) || !std::isfinite(m->mu) || !std::isfinite(m->xi))
     return fail(SLQ_ERR_ARG, "t, mu and xi must be finite");
-  if (m->chain_prec < SLQ_PREC_FP64 || m->chain_prec > SLQ_PREC_FP64_DENSE)
-    return fail(SLQ_ERR_ARG, "chain_prec must be SLQ_PREC_FP64, SLQ_PREC_FP32, SLQ_PREC_BF16 or SLQ_PREC_FP64_DENSE");
+  if (m->chain_prec < SLQ_PREC_FP64 || m->chain_prec > SLQ_PREC_CHECKERBOARD)
+    return fail(SLQ_ERR_ARG,
+                "chain_prec must be SLQ_PREC_FP64, SLQ_PREC_FP32, SLQ_PREC_BF16, SLQ_PREC_FP64_DENSE or "
+                "SLQ_PREC_CHECKERBOARD");
+  if (m->chain_prec == SLQ_PREC_CHECKERBOARD && (m->lx % 2 || m->ly % 2))
+    return fail(SLQ_ERR_ARG, "the checkerboard split needs even lx and ly");
   return SLQ_OK;
 }
 
@@ -134,7 +138,10 @@ static int timed_chain_gemm(Plan& p, const GemmArgs& g, hipStream_t st) {
 }
 
 static int timed_chain_kron(Plan& p, const KronArgs& k, hipStream_t st) {
-  const double flops = 2.0 * (double)p.n * p.n * (p.m.lx + p.m.ly) * k.count * k.batch;
+  // circulant lines: 2N (lx + ly) per vector and slice; checkerboard: 7 bond
+  // groups of N/2 rotations (6 flops each) and the diagonal factor, 22 N
+  const double per = p.cb ? 22.0 * p.n : 2.0 * (double)(p.m.lx + p.m.ly);
+  const double flops = per * p.n * k.count * k.batch;
   return timed_chain(p, flops, st, [&]() { return launch_kron(p, k, st); });
 }
 
@@ -197,7 +204,7 @@ int run_chain(Plan& p, int batch, const int8_t* s, int slice0, int32_t* status, 
   h.consts = p.consts;
   h.batch = batch;
   const bool lp = p.m.chain_prec == SLQ_PREC_FP32 || p.m.chain_prec == SLQ_PREC_BF16;
-  const bool kron = p.m.chain_prec == SLQ_PREC_FP64 && p.kron_P > 0;
+  const bool kron = structured_chain(p);
   for (int j0 = 0; j0 < L; j0 += ns) {
     const int jend = std::min(j0 + ns, L);
     double* cur = p.Xa;
@@ -362,6 +369,7 @@ size_t plan_layout(Plan& p, int32_t flags, char* base) {
   p.stack_batch = (flags & SLQ_PLAN_SWEEPS) ? (int)B : 0;
   p.net_base = (flags & SLQ_PLAN_NET) ? (void*)(c + oNet) : nullptr;
   p.kron_P = kron_line_size(model->lx, model->ly);
+  p.cb = model->chain_prec == SLQ_PREC_CHECKERBOARD;
   return off;
 }
 
@@ -372,6 +380,7 @@ int plan_init(Plan& p, hipStream_t st) {
   const long NN = (long)p.n * p.n;
   SLQ_TRY(launch_kinetic(p, st));
   SLQ_TRY(launch_kron_windows(p, st));
+  if (p.cb) SLQ_TRY(launch_cb_dense(p, st));
   SLQ_TRY(launch_narrow(p.E, p.E32, NN, st));
   SLQ_TRY(launch_to_bf16(p.E32, p.E16, NN, st));
   if (p.net_base) SLQ_TRY(bind_net(p));
@@ -528,7 +537,7 @@ int slq_plan_tune(slq_plan* plan, int32_t batch, int32_t* chosen, hipStream_t st
     SLQ_HIP(hipSetDevice(p.device));
     return tune_chain_gemm(p, batch, stream, nullptr);
   }
-  if (p.m.chain_prec != SLQ_PREC_FP64) return SLQ_OK;
+  if (p.m.chain_prec != SLQ_PREC_FP64 && !p.cb) return SLQ_OK;
   SLQ_HIP(hipSetDevice(p.device));
   SLQ_TRY(tune_kron(p, batch, stream, nullptr));
   if (chosen) *chosen = p.kron_nb;
@@ -542,8 +551,7 @@ int slq_plan_set_block_width(slq_plan* plan, int32_t width) {
     p.kron_nb = 0;
     return SLQ_OK;
   }
-  if (p.m.chain_prec != SLQ_PREC_FP64 || p.kron_P == 0)
-    return fail(SLQ_ERR_ARG, "the plan has no structured chain product");
+  if (!structured_chain(p)) return fail(SLQ_ERR_ARG, "the plan has no structured chain product");
   if (!kron_width_ok(p, width))
     return fail(SLQ_ERR_ARG, "block width must be a power of two <= 32 whose workgroup fits the lattice");
   p.kron_nb = width;

@@ -74,39 +74,71 @@ __global__ void k_pair_merge(int B, const int32_t* st2, const double* d2, int32_
 // One slice of the local update of the bilayer weight, one workgroup per
 // chain: for sites i = 0..N-1 in order, the ratio phi'/phi (R_a R_b)^2 from
 // the two Green's functions (of s: G[b], of -s: G[B+b]), Metropolis with the
-// draw at counter (i, slice, sweep, chain), and on acceptance both rank-1
-// updates G -= (delta / R) (e_i - G[:, i]) G[i, :] (no delay: N is small on
-// this workload) and the flip in s and in the paired copies.
+// draw at counter (i, slice, sweep, chain), and on acceptance the flip in s
+// and in the paired copies and the Sherman-Morrison update
+//     G <- G - x y^T,  x = (delta / R)(e_i - G[:, i]),  y = G[i, :]
+// of both, delayed: the pairs (x, y) of up to FB_KD accepted flips are kept
+// in X [N][KD] and Y [KD][N], the current G is G0 - X Y (its diagonal and,
+// for an accepted site, its row and column are formed from G0 and the
+// pairs), and G0 takes the whole rank-k update once per FB_KD flips and at
+// the end of the slice.  G0 is then read and written once per FB_KD accepted
+// flips instead of once per flip.
 struct FlipBArgs {
   int lx, ly, L, N, B, slice;
   double a, dtJ, kt;
   int8_t* s;       // [B][L][N] the chains' fields
   int8_t* pair;    // [2B][L][N] their copies [s ; -s]
   double* G;       // [2B][N][N]
+  double* X;       // [2B][N][FB_KD]
+  double* Y;       // [2B][FB_KD][N]
   double* logw;    // [B]
   int64_t* accepts;
   uint64_t seed, sweep, chain0;
 };
 
 constexpr int FB_THREADS = 512;
+constexpr int FB_KD = 16;
+
+// G0 -= X Y for the k pending pairs (all threads; rows split across threads)
+__device__ __forceinline__ void fb_flush(double* G0, const double* X, const double* Y, int N, int k) {
+  for (long e = threadIdx.x; e < (long)N * N; e += FB_THREADS) {
+    const int r = (int)(e / N), c = (int)(e - (long)r * N);
+    double acc = 0.0;
+    for (int q = 0; q < k; ++q) acc += X[(long)r * FB_KD + q] * Y[(long)q * N + c];
+    G0[e] -= acc;
+  }
+}
 
 __global__ __launch_bounds__(FB_THREADS) void k_flip_bilayer(FlipBArgs f) {
-  extern __shared__ double lds[];
   const int N = f.N;
   const long NN = (long)N * N;
-  const int b = blockIdx.x, tid = threadIdx.x;
-  double* colA = lds;        // [N] e_i - G_a[:, i]
-  double* rowA = colA + N;   // [N] G_a[i, :]
-  double* colB = rowA + N;
-  double* rowB = colB + N;
-  __shared__ double fa, fb, lr;
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double fa, fb, lr, gda, gdb;
   __shared__ int take;
   double* Ga = f.G + (long)b * NN;
   double* Gb = f.G + (long)(f.B + b) * NN;
+  double* Xa = f.X + (long)b * N * FB_KD;
+  double* Xb = f.X + (long)(f.B + b) * N * FB_KD;
+  double* Ya = f.Y + (long)b * FB_KD * N;
+  double* Yb = f.Y + (long)(f.B + b) * FB_KD * N;
   int8_t* s = f.s + (long)b * f.L * N;
   const int l = f.slice;
   long long acc = 0;
+  int k = 0;  // pending pairs (uniform)
   for (int i = 0; i < N; ++i) {
+    // the current diagonals G_ii = G0_ii - sum_q X[i][q] Y[q][i]: wave 0 for G_a, wave 1 for G_b
+    if (wave < 2) {
+      const double* G0 = wave == 0 ? Ga : Gb;
+      const double* X = wave == 0 ? Xa : Xb;
+      const double* Y = wave == 0 ? Ya : Yb;
+      double v = lane < k ? X[(long)i * FB_KD + lane] * Y[(long)lane * N + i] : 0.0;
+      v = wave_sum(v);
+      if (lane == 0) {
+        if (wave == 0) gda = G0[(long)i * N + i] - v;
+        else gdb = G0[(long)i * N + i] - v;
+      }
+    }
+    __syncthreads();
     if (tid == 0) {
       const int xi = i % f.lx, yi = i / f.lx;
       const int si = s[(long)l * N + i];
@@ -117,8 +149,8 @@ __global__ __launch_bounds__(FB_THREADS) void k_flip_bilayer(FlipBArgs f) {
       const int tn = s[(long)((l + 1) % f.L) * N + i] + s[(long)((l - 1 + f.L) % f.L) * N + i];
       const double bare = exp(-2.0 * si * (f.dtJ * nb + f.kt * tn));
       const double da = exp(2.0 * f.a * si) - 1.0, db = exp(-2.0 * f.a * si) - 1.0;
-      const double ra = 1.0 + da * (1.0 - Ga[(long)i * N + i]);
-      const double rb = 1.0 + db * (1.0 - Gb[(long)i * N + i]);
+      const double ra = 1.0 + da * (1.0 - gda);
+      const double rb = 1.0 + db * (1.0 - gdb);
       const double r = bare * (ra * rb) * (ra * rb);
       const double u = philox_uniform((uint64_t)i, (uint64_t)l, f.sweep, f.chain0 + b, f.seed, TAG_LOCAL);
       const int ok = u < r;
@@ -129,18 +161,24 @@ __global__ __launch_bounds__(FB_THREADS) void k_flip_bilayer(FlipBArgs f) {
     }
     __syncthreads();
     if (take) {
-      for (int j = tid; j < N; j += FB_THREADS) {
-        colA[j] = (j == i ? 1.0 : 0.0) - Ga[(long)j * N + i];
-        rowA[j] = Ga[(long)i * N + j];
-        colB[j] = (j == i ? 1.0 : 0.0) - Gb[(long)j * N + i];
-        rowB[j] = Gb[(long)i * N + j];
-      }
-      __syncthreads();
+      // new pair k of each G from the current column and row i
       const double ca = fa, cb = fb;
-      for (long e = tid; e < NN; e += FB_THREADS) {
-        const int r = (int)(e / N), c = (int)(e % N);
-        Ga[e] -= ca * colA[r] * rowA[c];
-        Gb[e] -= cb * colB[r] * rowB[c];
+      for (int j = tid; j < 2 * N; j += FB_THREADS) {
+        const bool second = j >= N;
+        const int jj = second ? j - N : j;
+        const double* G0 = second ? Gb : Ga;
+        const double* X = second ? Xb : Xa;
+        const double* Y = second ? Yb : Ya;
+        double col = G0[(long)jj * N + i], row = G0[(long)i * N + jj];
+        for (int q = 0; q < k; ++q) {
+          col -= X[(long)jj * FB_KD + q] * Y[(long)q * N + i];
+          row -= X[(long)i * FB_KD + q] * Y[(long)q * N + jj];
+        }
+        const double c = second ? cb : ca;
+        double* Xw = second ? Xb : Xa;
+        double* Yw = second ? Yb : Ya;
+        Xw[(long)jj * FB_KD + k] = c * ((jj == i ? 1.0 : 0.0) - col);
+        Yw[(long)k * N + jj] = row;
       }
       if (tid == 0) {
         const long x = (long)l * N + i;
@@ -152,8 +190,19 @@ __global__ __launch_bounds__(FB_THREADS) void k_flip_bilayer(FlipBArgs f) {
         f.logw[b] += lr;
         ++acc;
       }
+      ++k;
+      __syncthreads();
+      if (k == FB_KD) {
+        fb_flush(Ga, Xa, Ya, N, k);
+        fb_flush(Gb, Xb, Yb, N, k);
+        k = 0;
+        __syncthreads();
+      }
     }
-    __syncthreads();
+  }
+  if (k > 0) {
+    fb_flush(Ga, Xa, Ya, N, k);
+    fb_flush(Gb, Xb, Yb, N, k);
   }
   if (tid == 0 && f.accepts) f.accepts[b] += acc;
 }
@@ -182,7 +231,8 @@ static int check_bilayer(const Plan& p, const slq_bilayer* bl, long batch) {
     set_error("the bilayer weight evaluates 2 batch fields: the plan's max_batch must be >= 2 batch");
     return SLQ_ERR_WORKSPACE;
   }
-  if (p.m.chain_prec != SLQ_PREC_FP64 && p.m.chain_prec != SLQ_PREC_FP64_DENSE) {
+  if (p.m.chain_prec != SLQ_PREC_FP64 && p.m.chain_prec != SLQ_PREC_FP64_DENSE &&
+      p.m.chain_prec != SLQ_PREC_CHECKERBOARD) {
     set_error("the bilayer workload runs FP64 chains only");
     return SLQ_ERR_ARG;
   }
@@ -279,12 +329,12 @@ int slq_bilayer_sweep_local(slq_plan* plan, const slq_bilayer* bl, int32_t batch
   f.s = d_s;
   f.pair = p.s_work;
   f.G = d_G;
+  f.X = p.dX;
+  f.Y = p.dY;
   f.logw = d_logw;
   f.accepts = acc;
   f.seed = seed;
   f.chain0 = chain0;
-  const size_t flds = sizeof(double) * 4 * (size_t)N;
-  allow_max_lds((const void*)k_flip_bilayer);
   // wrap of both Green's functions: G <- E diag(d_l) G diag(1/d_l) E^{-1}
   KronArgs k1{};
   k1.in = d_G;
@@ -329,9 +379,9 @@ int slq_bilayer_sweep_local(slq_plan* plan, const slq_bilayer* bl, int32_t batch
     f.sweep = sweep0 + k;
     for (int l = 1; l <= L; ++l) {
       f.slice = l - 1;
-      k_flip_bilayer<<<B, FB_THREADS, flds, st>>>(f);
+      k_flip_bilayer<<<B, FB_THREADS, 0, st>>>(f);
       SLQ_LAUNCHED();
-      if (p.kron_P > 0) {
+      if (has_structured(p)) {
         k1.slice0 = l - 1;
         k2.slice0 = l - 1;
         SLQ_TRY(launch_kron(p, k1, st));

@@ -95,8 +95,10 @@ __global__ void k_scatter_g(long NN, const int64_t* __restrict__ goff, const dou
 // the structured product and the QR pass through exactly).
 static bool same_but_length(const slq_model& a, const slq_model& b) {
   return a.lx == b.lx && a.ly == b.ly && a.n_stab == b.n_stab && a.t == b.t && a.mu == b.mu && a.dtau == b.dtau &&
-         a.xi == b.xi && a.chain_prec == SLQ_PREC_FP64 && b.chain_prec == SLQ_PREC_FP64 &&
-         kron_line_size(a.lx, a.ly) > 0 && (a.n_slices - b.n_slices) % a.n_stab == 0;
+         a.xi == b.xi && a.chain_prec == b.chain_prec &&
+         ((a.chain_prec == SLQ_PREC_FP64 && kron_line_size(a.lx, a.ly) > 0) ||
+          a.chain_prec == SLQ_PREC_CHECKERBOARD) &&
+         (a.n_slices - b.n_slices) % a.n_stab == 0;
 }
 
 static bool same_model(const slq_model& a, const slq_model& b) {
@@ -115,7 +117,8 @@ static int autotune_kron(Group& g, SubPlan& sp) {
   g.tuned_kind.push_back(1);
   g.tuned_cfg.push_back(p.kron_nb);
   const int cnt = std::min(p.m.n_stab, p.L);
-  g.tuned_tflops.push_back(2.0 * (double)p.n * p.n * (p.m.lx + p.m.ly) * cnt * sp.nb / (ms * 1e-3) / 1e12);
+  const double per = p.cb ? 22.0 * p.n : 2.0 * (double)(p.m.lx + p.m.ly);
+  g.tuned_tflops.push_back(per * p.n * cnt * sp.nb / (ms * 1e-3) / 1e12);
   return SLQ_OK;
 }
 
@@ -124,7 +127,7 @@ static int autotune_kron(Group& g, SubPlan& sp) {
 static int autotune(Group& g, SubPlan& sp) {
   Plan& p = sp.plan->p;
   const int N = p.n;
-  if (p.m.chain_prec == SLQ_PREC_FP64 && p.kron_P > 0) return p.kron_nb > 0 ? SLQ_OK : autotune_kron(g, sp);
+  if (structured_chain(p)) return p.kron_nb > 0 ? SLQ_OK : autotune_kron(g, sp);
   if ((p.m.chain_prec != SLQ_PREC_FP64 && p.m.chain_prec != SLQ_PREC_FP64_DENSE) || p.gemm_cfg >= 0)
     return SLQ_OK;
   float best_ms = 0.f;

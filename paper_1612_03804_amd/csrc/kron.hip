@@ -178,12 +178,6 @@ constexpr int kron_lanes_per_line(int P, int nbt) { return 2 * P * nbt <= (P >= 
 // and its workgroup size
 constexpr int kron_fixed_threads(int P, int nbt) { return (P * nbt * kron_lanes_per_line(P, nbt) + 63) / 64 * 64; }
 
-// Workgroup-to-block order, XCD-aware: the hardware deals workgroups to the
-// 8 XCDs in turn, so hardware ids g and g + 8 run side by side on one XCD;
-// they take the vector blocks 2p and 2p + 1, which share every 128-byte line
-// of the field's rows in that XCD's L2 (each line is then fetched once, not
-// once per half).  A permutation within each aligned group of 16 ids.
-__device__ __forceinline__ int kron_item(int g) { return (g & ~15) | ((g & 7) << 1) | ((g >> 3) & 1); }
 
 // NBT > 0: NBT vectors per workgroup and an exact P x P lattice, fixed at
 // compile time, so that every LDS address of the line products is a base
@@ -443,6 +437,7 @@ static size_t kron_lds(const Plan& p, int nb) {
 }
 
 int kron_default_nb(const Plan& p) {
+  if (p.cb) return cb_default_nb(p);
   const int m = std::max(p.m.lx, p.m.ly);
   for (int nb = 32; nb > 1; nb /= 2)
     if (kron_lds(p, nb) <= 80 * 1024 && m * nb <= kron_max_threads(p.kron_P)) return nb;
@@ -474,12 +469,14 @@ static void launch_p(const KronDev& d, bool exact, int nb, bool fixed, dim3 grid
 }
 
 bool kron_width_ok(const Plan& p, int nb) {
+  if (p.cb) return cb_width_ok(p, nb);
   const int m = std::max(p.m.lx, p.m.ly);
   return nb >= 1 && nb <= 32 && (nb & (nb - 1)) == 0 && m * nb <= kron_max_threads(p.kron_P) &&
          kron_lds(p, nb) <= 160 * 1024;
 }
 
 int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
+  if (p.cb) return launch_cb(p, a, st);
   if (a.batch <= 0 || a.count <= 0) return SLQ_OK;
   if (p.kron_P == 0) {
     set_error("structured slice products need lx, ly <= 64");
@@ -544,7 +541,7 @@ int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
 // on `batch` fields of the plan's workspace (fields of +1 spins written into
 // s_work) and keep the fastest in the plan.  Synchronous on st.
 int tune_kron(Plan& p, int batch, hipStream_t st, float* best_ms_out) {
-  if (p.kron_P == 0) return SLQ_OK;
+  if (!has_structured(p)) return SLQ_OK;
   const int N = p.n;
   int rc = fill_i32((int32_t*)p.s_work, (long)batch * p.L * N / 4, 0x01010101, st);
   if (rc != SLQ_OK) return rc;

@@ -244,6 +244,10 @@ struct Plan {
   int kron_P = 0;
   double* kron_w = nullptr;
   int kron_nb = 0;
+  // checkerboard split of the kinetic factor (SLQ_PREC_CHECKERBOARD): E and
+  // E^{-1} hold E_cb and its inverse, and the structured products apply it
+  // bond group by bond group (kron_nb is then its vectors per workgroup)
+  bool cb = false;
   // [max_batch] or null: the first stabilisation block of each field's chain
   // (earlier blocks leave U D V = I 1 I; set by groups that batch chains of
   // several lengths, structured products only; device memory the plan does not own)
@@ -256,6 +260,11 @@ struct Plan {
   double* stack = nullptr;
   int stack_batch = 0;
 };
+
+// Slice products through launch_kron are available (circulant lines or
+// checkerboard bonds) / are the chain's own products.
+inline bool has_structured(const Plan& p) { return p.cb || p.kron_P > 0; }
+inline bool structured_chain(const Plan& p) { return p.cb || (p.m.chain_prec == SLQ_PREC_FP64 && p.kron_P > 0); }
 
 struct Eff {
   Plan* plan;
@@ -430,6 +439,18 @@ struct KronArgs {
   int block = 0;                         // stabilisation block of the launch (first_block only)
 };
 int kron_line_size(int lx, int ly);
+// Workgroup-to-block order, XCD-aware: the hardware deals workgroups to the
+// 8 XCDs in turn, so hardware ids g and g + 8 run side by side on one XCD;
+// they take the vector blocks 2p and 2p + 1, which share every 128-byte line
+// of the field's rows in that XCD's L2 (each line is then fetched once, not
+// once per half).  A permutation within each aligned group of 16 ids.
+__device__ __forceinline__ int kron_item(int g) { return (g & ~15) | ((g & 7) << 1) | ((g >> 3) & 1); }
+// Checkerboard products (SLQ_PREC_CHECKERBOARD): launch_kron hands them to
+// launch_cb, which takes the same arguments.
+int launch_cb(Plan& p, const KronArgs& a, hipStream_t st);
+int launch_cb_dense(Plan& p, hipStream_t st);
+bool cb_width_ok(const Plan& p, int nb);
+int cb_default_nb(const Plan& p);
 int kron_default_nb(const Plan& p);
 bool kron_width_ok(const Plan& p, int nb);
 int launch_kron_windows(Plan& p, hipStream_t st);

@@ -94,7 +94,7 @@ static int block_product(Plan& p, int batch, const int8_t* s, int first, int cou
   const int N = p.n;
   const long NN = (long)N * N;
   const long strideS = (long)p.L * N;
-  if (p.kron_P > 0) {  // structured products, the whole block in one launch
+  if (has_structured(p)) {  // structured products, the whole block in one launch
     KronArgs k{};
     k.in = start;
     k.strideIn = NN;
@@ -335,7 +335,7 @@ int sweep_stacked(Plan& p, int batch, int8_t* s, double* G, double* logabs, int8
     if (L > ns) SLQ_TRY(build_left(p, batch, s, status, st));
     for (int l = 1; l <= L; ++l) {
       SLQ_TRY(launch_flip_slice(p, batch, s, G, logabs, sign, l - 1, seed, sweep0 + k, chain0, accepts, st));
-      if (p.kron_P > 0) {
+      if (has_structured(p)) {
         k1.slice0 = l - 1;
         k2.slice0 = l - 1;
         SLQ_TRY(launch_kron(p, k1, st));

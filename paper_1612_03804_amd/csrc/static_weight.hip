@@ -59,7 +59,8 @@ int slq_weight_static(const slq_model* model, int32_t batch, const int8_t* d_s, 
     set_error("d_s, d_logabs and d_sign must not be NULL");
     return SLQ_ERR_ARG;
   }
-  if (model->chain_prec != SLQ_PREC_FP64 && model->chain_prec != SLQ_PREC_FP64_DENSE) {
+  if (model->chain_prec != SLQ_PREC_FP64 && model->chain_prec != SLQ_PREC_FP64_DENSE &&
+      model->chain_prec != SLQ_PREC_CHECKERBOARD) {
     set_error("slq_weight_static evaluates FP64 chains only");
     return SLQ_ERR_ARG;
   }

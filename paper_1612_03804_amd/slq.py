@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libslq.so")
 SLQ_OK, SLQ_ERR_ARG, SLQ_ERR_DEVICE, SLQ_ERR_WORKSPACE, SLQ_ERR_NUMERIC = 0, -1, -2, -3, -4
 SLQ_ST_BAD_SPIN, SLQ_ST_NONFINITE, SLQ_ST_SINGULAR, SLQ_ST_PIVOT = 1, 2, 4, 8
 SLQ_PLAN_SWEEPS, SLQ_PLAN_NET = 1, 2
-SLQ_PREC_FP64, SLQ_PREC_FP32, SLQ_PREC_BF16, SLQ_PREC_FP64_DENSE = 0, 1, 2, 3
+SLQ_PREC_FP64, SLQ_PREC_FP32, SLQ_PREC_BF16, SLQ_PREC_FP64_DENSE, SLQ_PREC_CHECKERBOARD = 0, 1, 2, 3, 4
 
 # every exported symbol of include/slq.h
 EXPORTS = (
@@ -32,7 +32,7 @@ EXPORTS = (
     "slq_group_weight", "slq_group_green", "slq_magnetization", "slq_net_forward", "slq_net_gradient",
     "slq_net_adam", "slq_eff_set_net", "slq_eff_net_classes", "slq_plan_tune", "slq_plan_set_block_width",
     "slq_bilayer_weight", "slq_bilayer_green", "slq_bilayer_sweep_local", "slq_bilayer_cumulative_step",
-    "slq_weight_static",
+    "slq_weight_static", "slq_measure_equal_time", "slq_green_displaced",
 )
 SLQ_NET_PARAMS = 1969
 
@@ -108,6 +108,8 @@ def load_library(path: str = LIB_PATH):
         "slq_eff_set_net": ([P, P, i32, P], C.c_int),
         "slq_eff_net_classes": ([P, C.POINTER(i32)], C.c_int),
         "slq_weight_static": ([C.POINTER(slq_model), i32, P, P, P, P, P], C.c_int),
+        "slq_measure_equal_time": ([P, i32, P, P, P], C.c_int),
+        "slq_green_displaced": ([P, i32, P, i32, P, P, P], C.c_int),
         "slq_bilayer_weight": ([P, C.POINTER(slq_bilayer), i32, P, P, P, P], C.c_int),
         "slq_bilayer_green": ([P, C.POINTER(slq_bilayer), i32, P, P, P, P, P], C.c_int),
         "slq_bilayer_sweep_local": ([P, C.POINTER(slq_bilayer), i32, P, P, P, i32, u64, u64, u64, P, P, P, P],
@@ -528,3 +530,20 @@ def slq_bilayer_cumulative_step(plan: Plan, eff: Eff, J: float, h: float, s, log
     _check(load_library().slq_bilayer_cumulative_step(plan.handle, eff.handle, _bl(J, h), b, _ptr(s), _ptr(logw),
                                                       int(n_moves), seed, step, chain0, _ptr(accepted), _ptr(logA),
                                                       _ptr(status), _stream(stream)))
+
+
+def slq_measure_equal_time(plan: Plan, G, out, stream=None):
+    """out [batch][3] = (density, hopping energy per site, S(pi, pi)) of each G."""
+    b = G.shape[0]
+    _need(G, torch.float64, (b, plan.n, plan.n), "G")
+    _need(out, torch.float64, (b, 3), "out")
+    _check(load_library().slq_measure_equal_time(plan.handle, b, _ptr(G), _ptr(out), _stream(stream)))
+
+
+def slq_green_displaced(plan: Plan, s, slice: int, Gt, status=None, stream=None):
+    """Gt [batch][N][N] = G(tau_slice, 0) = B_slice ... B_1 G of each field."""
+    b = s.shape[0]
+    _need(s, torch.int8, (b, plan.L, plan.n), "s")
+    _need(Gt, torch.float64, (b, plan.n, plan.n), "Gt")
+    _check(load_library().slq_green_displaced(plan.handle, b, _ptr(s), int(slice), _ptr(Gt), _ptr(status),
+                                              _stream(stream)))

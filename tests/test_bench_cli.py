@@ -29,10 +29,13 @@ def test_no_gpu_is_reported():
     assert "no GPU" in r.stderr
 
 
-def test_traffic_table_names_compile_time_widths():
+def test_traffic_table_is_keyed_by_workload_and_batch():
+    """Stabilisation HBM bytes are quoted only for the (workload, batch) they
+    were counted on; at least the QR's own operand traffic (the pivoted copy
+    of X written and read, Q written) per field."""
     sys.path.insert(0, ROOT)
     import bench
-    assert bench.KRON_TRAFFIC_BATCH == 512
-    assert set(bench.KRON_TRAFFIC) <= {8, 16}
-    # bytes per launch lie between the algorithmic 1.2325 GB and 5 % above it
-    assert all(1.2325e9 <= v <= 1.05 * 1.2325e9 for v in bench.KRON_TRAFFIC.values())
+    from slq_inputs import WORKLOADS
+    for (workload, batch), v in bench.STAB_TRAFFIC.items():
+        m = WORKLOADS[workload]
+        assert batch > 0 and v > 3 * 8 * m.n_sites ** 2 * batch

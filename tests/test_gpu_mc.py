@@ -259,12 +259,14 @@ def test_magnetization_matches_sum(slq, model):
     plan.close()
 
 
-def _cumulative_parity(slq, m, terms, c0, lam, fields, n_moves, steps, step0=0):
+def _cumulative_parity(slq, m, terms, c0, lam, fields, n_moves, steps, step0=0, chain_prec=0, weight_fn=None):
     """Cumulative updates of len(fields) chains on the GPU, each checked
-    decision by decision against the oracle."""
+    decision by decision against the oracle (weight_fn: the oracle's exact
+    weight of the plan's discretisation, stable.weight by default)."""
+    wfn = weight_fn or (lambda x: stable.weight(m, x))
     from tests.gpu_util import dev, host
     nb = len(fields)
-    plan = slq.Plan(m, nb)
+    plan = slq.Plan(m, nb, chain_prec)
     eff = make_eff(slq, plan, m, terms, lam, c0)
     s = dev(np.stack(fields))
     la = _t(nb, torch.float64)
@@ -274,7 +276,7 @@ def _cumulative_parity(slq, m, terms, c0, lam, fields, n_moves, steps, step0=0):
     accd = _t(nb, torch.int8)
     logA = _t(nb, torch.float64)
     ref_s = [f.copy() for f in fields]
-    ref_w = [stable.weight(m, f) for f in fields]
+    ref_w = [wfn(f) for f in fields]
     gla0 = host(la)
     for b in range(nb):
         assert abs(gla0[b] - ref_w[b][0]) < 1e-10 * max(1, abs(ref_w[b][0]))
@@ -286,7 +288,7 @@ def _cumulative_parity(slq, m, terms, c0, lam, fields, n_moves, steps, step0=0):
         ga, gl, gs, gla, gst = host(accd), host(logA), host(s), host(la), host(st)
         for b in range(nb):
             ref_s[b], lw, sgn, ok, la_ref = effective.cumulative_step(
-                m, terms, c0, lam, ref_s[b], ref_w[b][0], ref_w[b][1], n_moves, lambda x: stable.weight(m, x),
+                m, terms, c0, lam, ref_s[b], ref_w[b][0], ref_w[b][1], n_moves, wfn,
                 seed=SEED, step=step, chain=b, classes=classes)
             ref_w[b] = (lw, sgn)
             u = philox.uniform((0, 0, step, b), (SEED, philox.TAG_CUMULATIVE))
