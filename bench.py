@@ -45,8 +45,9 @@ COPY_CALIBRATION_BYTES = 1 << 30
 # V update, over the batch), by (workload, batch): rocprofv3 --pmc
 # FETCH_SIZE, then WRITE_SIZE, summed over the stabilisation kernels of an
 # evaluation, divided by its 10 stabilisations, each scaled by what the same
-# counter reads for the 1 GiB copy of --copy-calibration.
-STAB_TRAFFIC = {}
+# counter reads for the 1 GiB copy of --copy-calibration (FETCH_SIZE reads
+# half of the copied bytes, WRITE_SIZE all of them).
+STAB_TRAFFIC = {("learned_48x48", 256): 6.83026e11 + 2.39184e11}
 
 
 def oracle_cumulative_step_seconds(model, terms, theta, field, threads, seed):
@@ -415,7 +416,8 @@ def headline(slq, args, workload):
     B = args.batch or (256 if workload == "learned_48x48" else 512)
     seed = 0x5D0C + (5 if workload == "learned_48x48" else 2)
     dev = torch.device("cuda")
-    plan = slq.Plan(model, B)
+    cb = args.chain == "checkerboard"
+    plan = slq.Plan(model, B, slq.SLQ_PREC_CHECKERBOARD if cb else slq.SLQ_PREC_FP64)
     if args.block_width:
         slq.slq_plan_set_block_width(plan, args.block_width)
         kron_nb = args.block_width
@@ -485,6 +487,8 @@ def headline(slq, args, workload):
                    "n_stab": model.n_stab, "chains": B, "effective_moves_per_step": n_moves,
                    "proposals_per_step": int(model.n_sites * model.n_slices), "terms": len(terms),
                    "judge": "FP64 (structured slice products, blocked Householder QR/UDV, QR determinant)",
+                   "kinetic_factor": ("checkerboard split E_cb (a different Trotter discretisation)" if cb
+                                      else "exact exp(-dtau K)"),
                    "chain_block_vectors_per_workgroup": kron_nb},
         "roofline": {"bound": "mfma", "achieved": stab["tflops"], "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": stab["frac_of_fp64_peak"], "traffic": STAB_TRAFFIC.get((workload, B)),
@@ -499,8 +503,10 @@ def headline(slq, args, workload):
                "status_ok": ok,
                "parts": {"stabilisation": stab,
                          "chain": {**part_info("chain", FP64_PEAK_TFLOPS),
-                                   "note": "structured FP64 slice products (vector FMA): 2 N^2 (lx+ly) flops per "
-                                           "slice and field"},
+                                   "note": ("checkerboard FP64 slice products (bond rotations in registers, edge "
+                                            "exchanges in LDS): 22 N^2 flops per slice and field" if cb else
+                                            "structured FP64 slice products (vector FMA): 2 N^2 (lx+ly) flops per "
+                                            "slice and field")},
                          "final": {**part_info("final", FP64_PEAK_TFLOPS),
                                    "note": "QR of M for the determinant: (4/3) N^3 per field"}}}
     return out, details, plan, eff, s, logabs, sign, status, theta_h, fields, model, terms, seed
@@ -732,6 +738,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=0, help="chains (0: 256 at 48x48, 512 at 20x20)")
     ap.add_argument("--workload", choices=("learned_48x48", "dqmc_20x20"), default="learned_48x48")
+    ap.add_argument("--chain", choices=("exact", "checkerboard"), default="exact",
+                    help="kinetic factor of the timed chains: exact exp(-dtau K) (circulant lines) or the "
+                         "checkerboard split E_cb")
     ap.add_argument("--block-width", type=int, default=0,
                     help="vectors per workgroup of the chain-block kernel (0: tuned on the plan)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
