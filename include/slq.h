@@ -295,12 +295,14 @@ int slq_group_describe(const slq_group* group, char* buf, size_t len);
  * slq_group_weight / slq_group_green - Eq. 1's exact weight (and G) of every
  * chain: d_logabs, d_sign, d_status [n_chains], d_G packed as above.  The
  * batches are dealt to up to four streams of the group (largest estimated
- * work first, each to the least loaded stream); each stream's part of the
- * evaluation (gathers, the stabilised chains, QRs and LU of its batches,
- * scatters) is recorded once as a HIP graph for a given set of pointers and
- * replayed as one launch afterwards, and the streams run side by side.  The
- * evaluation is ordered after prior work on `stream`, and later work on
- * `stream` waits for all of it.  Calls on one group must not overlap in time.
+ * work first, each to the least loaded stream); the whole evaluation (per
+ * stream: gathers, the stabilised chains, QRs and final steps of its
+ * batches, scatters) is recorded once, for a given set of pointers, as one
+ * HIP graph whose parallel branches are the streams' parts, and replayed as
+ * one graph launch afterwards (the first call with new pointers also runs it
+ * eagerly).  The evaluation is ordered after prior work on `stream`, and
+ * later work on `stream` waits for all of it.  Calls on one group must not
+ * overlap in time.
  */
 int slq_group_weight(slq_group* group, const int8_t* d_s, double* d_logabs, int8_t* d_sign,
                      int32_t* d_status, hipStream_t stream);

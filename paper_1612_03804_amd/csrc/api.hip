@@ -140,7 +140,7 @@ static int timed_chain_gemm(Plan& p, const GemmArgs& g, hipStream_t st) {
 static int timed_chain_kron(Plan& p, const KronArgs& k, hipStream_t st) {
   // circulant lines: 2N (lx + ly) per vector and slice; checkerboard: 7 bond
   // groups of N/2 rotations (6 flops each) and the diagonal factor, 22 N
-  const double per = p.cb ? 22.0 * p.n : 2.0 * (double)(p.m.lx + p.m.ly);
+  const double per = (p.cb ? 22.0 : 2.0 * (double)(p.m.lx + p.m.ly)) * p.n;  // per vector and slice
   const double flops = per * p.n * k.count * k.batch;
   return timed_chain(p, flops, st, [&]() { return launch_kron(p, k, st); });
 }

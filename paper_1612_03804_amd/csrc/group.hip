@@ -43,16 +43,17 @@ struct Group {
   std::vector<double> tuned_tflops;
   void* dmem = nullptr;
   hipStream_t gs = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr;
   // the sub-batches are dealt to up to kLanes streams (largest estimated work
-  // first, each to the least loaded lane); every lane records its own graph,
-  // and the lanes run side by side
+  // first, each to the least loaded lane); one graph holds every lane as a
+  // parallel branch (forked from and joined back to gs during its capture), so
+  // an evaluation is one graph launch
   static constexpr int kLanes = 4;
   std::vector<std::vector<int>> lane_subs;
   std::vector<hipStream_t> lane_st;
   std::vector<hipEvent_t> lane_ev;
-  std::vector<hipGraph_t> lane_graph;
-  std::vector<hipGraphExec_t> lane_exec;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   const void* key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -117,7 +118,7 @@ static int autotune_kron(Group& g, SubPlan& sp) {
   g.tuned_kind.push_back(1);
   g.tuned_cfg.push_back(p.kron_nb);
   const int cnt = std::min(p.m.n_stab, p.L);
-  const double per = p.cb ? 22.0 * p.n : 2.0 * (double)(p.m.lx + p.m.ly);
+  const double per = (p.cb ? 22.0 : 2.0 * (double)(p.m.lx + p.m.ly)) * p.n;  // per vector and slice
   g.tuned_tflops.push_back(per * p.n * cnt * sp.nb / (ms * 1e-3) / 1e12);
   return SLQ_OK;
 }
@@ -167,13 +168,38 @@ static int enqueue(Group& g, int lane, hipStream_t st, const int8_t* d_s, double
   return SLQ_OK;
 }
 
-static void drop_graphs(Group& g) {
-  for (size_t k = 0; k < g.lane_exec.size(); ++k) {
-    if (g.lane_exec[k]) hipGraphExecDestroy(g.lane_exec[k]);
-    if (g.lane_graph[k]) hipGraphDestroy(g.lane_graph[k]);
-    g.lane_exec[k] = nullptr;
-    g.lane_graph[k] = nullptr;
+static void drop_graph(Group& g) {
+  if (g.exec) hipGraphExecDestroy(g.exec);
+  if (g.graph) hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+}
+
+// Record the evaluation as one graph: the capture starts on gs, forks to the
+// lane streams through ev_fork and joins them back through their events.
+static int record_graph(Group& g, const int8_t* d_s, double* d_G, double* d_logabs, int8_t* d_sign,
+                        int32_t* d_status) {
+  SLQ_HIP(hipStreamBeginCapture(g.gs, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipEventRecord(g.ev_fork, g.gs);
+  int rc = e == hipSuccess ? SLQ_OK : SLQ_ERR_DEVICE;
+  for (size_t k = 0; k < g.lane_st.size(); ++k) {
+    hipStream_t ls = g.lane_st[k];
+    if (e == hipSuccess) e = hipStreamWaitEvent(ls, g.ev_fork, 0);
+    if (e == hipSuccess && rc == SLQ_OK) rc = enqueue(g, (int)k, ls, d_s, d_G, d_logabs, d_sign, d_status);
+    if (e == hipSuccess) e = hipEventRecord(g.lane_ev[k], ls);
+    if (e == hipSuccess) e = hipStreamWaitEvent(g.gs, g.lane_ev[k], 0);
   }
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(g.gs, &graph);
+  if (rc != SLQ_OK || e != hipSuccess || ee != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    if (rc != SLQ_OK) return rc;
+    set_error(std::string("graph capture of the group: ") + hipGetErrorString(e != hipSuccess ? e : ee));
+    return SLQ_ERR_DEVICE;
+  }
+  g.graph = graph;
+  SLQ_HIP(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+  return SLQ_OK;
 }
 
 static int group_eval(Group& g, const int8_t* d_s, double* d_G, double* d_logabs, int8_t* d_sign, int32_t* d_status,
@@ -181,38 +207,24 @@ static int group_eval(Group& g, const int8_t* d_s, double* d_G, double* d_logabs
   SLQ_HIP(hipSetDevice(g.device));
   SLQ_HIP(hipEventRecord(g.ev_in, stream));
   const void* key[5] = {d_s, d_G, d_logabs, d_sign, d_status};
-  const bool record = !g.lane_exec[0] || memcmp(key, g.key, sizeof(key)) != 0;
-  if (record) {
-    drop_graphs(g);
+  if (!g.exec || memcmp(key, g.key, sizeof(key)) != 0) {
+    drop_graph(g);
     memset(g.key, 0, sizeof(g.key));
-  }
-  for (size_t k = 0; k < g.lane_st.size(); ++k) {
-    hipStream_t ls = g.lane_st[k];
-    SLQ_HIP(hipStreamWaitEvent(ls, g.ev_in, 0));
-    if (record) {
-      // one eager pass (sets kernel attributes), then record the lane's graph
-      int rc = enqueue(g, (int)k, ls, d_s, d_G, d_logabs, d_sign, d_status);
-      if (rc != SLQ_OK) return rc;
-      SLQ_HIP(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
-      rc = enqueue(g, (int)k, ls, d_s, d_G, d_logabs, d_sign, d_status);
-      hipGraph_t graph = nullptr;
-      hipError_t e = hipStreamEndCapture(ls, &graph);
-      if (rc != SLQ_OK) {
-        if (graph) hipGraphDestroy(graph);
-        return rc;
-      }
-      if (e != hipSuccess) {
-        set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-        return SLQ_ERR_DEVICE;
-      }
-      g.lane_graph[k] = graph;
-      SLQ_HIP(hipGraphInstantiate(&g.lane_exec[k], graph, nullptr, nullptr, 0));
+    // one eager pass on the lanes (sets the kernel attributes), then the capture
+    for (size_t k = 0; k < g.lane_st.size(); ++k) {
+      hipStream_t ls = g.lane_st[k];
+      SLQ_HIP(hipStreamWaitEvent(ls, g.ev_in, 0));
+      SLQ_TRY(enqueue(g, (int)k, ls, d_s, d_G, d_logabs, d_sign, d_status));
+      SLQ_HIP(hipEventRecord(g.lane_ev[k], ls));
+      SLQ_HIP(hipStreamWaitEvent(g.gs, g.lane_ev[k], 0));
     }
-    SLQ_HIP(hipGraphLaunch(g.lane_exec[k], ls));
-    SLQ_HIP(hipEventRecord(g.lane_ev[k], ls));
-    SLQ_HIP(hipStreamWaitEvent(stream, g.lane_ev[k], 0));
+    SLQ_TRY(record_graph(g, d_s, d_G, d_logabs, d_sign, d_status));
+    memcpy(g.key, key, sizeof(key));
   }
-  if (record) memcpy(g.key, key, sizeof(key));
+  SLQ_HIP(hipStreamWaitEvent(g.gs, g.ev_in, 0));
+  SLQ_HIP(hipGraphLaunch(g.exec, g.gs));
+  SLQ_HIP(hipEventRecord(g.ev_out, g.gs));
+  SLQ_HIP(hipStreamWaitEvent(stream, g.ev_out, 0));
   return SLQ_OK;
 }
 
@@ -221,7 +233,7 @@ static void release(Group& g) {
   if (g.gs) hipStreamSynchronize(g.gs);
   for (hipStream_t ls : g.lane_st)
     if (ls) hipStreamSynchronize(ls);
-  drop_graphs(g);
+  drop_graph(g);
   for (hipEvent_t e : g.lane_ev)
     if (e) hipEventDestroy(e);
   for (hipStream_t ls : g.lane_st)
@@ -230,6 +242,7 @@ static void release(Group& g) {
   if (g.dmem) hipFree(g.dmem);
   if (g.ev_in) hipEventDestroy(g.ev_in);
   if (g.ev_out) hipEventDestroy(g.ev_out);
+  if (g.ev_fork) hipEventDestroy(g.ev_fork);
   if (g.gs) hipStreamDestroy(g.gs);
   g = Group();
 }
@@ -345,7 +358,8 @@ int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out)
   }
   if (rc == SLQ_OK && (hipStreamCreateWithFlags(&g.gs, hipStreamNonBlocking) != hipSuccess ||
                        hipEventCreateWithFlags(&g.ev_in, hipEventDisableTiming) != hipSuccess ||
-                       hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming) != hipSuccess)) {
+                       hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&g.ev_fork, hipEventDisableTiming) != hipSuccess)) {
     set_error("stream/event creation failed");
     rc = SLQ_ERR_DEVICE;
   }
@@ -369,8 +383,6 @@ int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out)
     }
     g.lane_st.assign(nl, nullptr);
     g.lane_ev.assign(nl, nullptr);
-    g.lane_graph.assign(nl, nullptr);
-    g.lane_exec.assign(nl, nullptr);
     for (int k = 0; k < nl && rc == SLQ_OK; ++k)
       if (hipStreamCreateWithFlags(&g.lane_st[k], hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&g.lane_ev[k], hipEventDisableTiming) != hipSuccess) {

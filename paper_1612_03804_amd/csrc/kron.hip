@@ -173,8 +173,12 @@ __device__ __forceinline__ void line_product_symc(double* __restrict__ S, int ba
   }
 }
 
-// Lanes per line of the compile-time path: two wherever the thread count allows
-constexpr int kron_lanes_per_line(int P, int nbt) { return 2 * P * nbt <= (P >= 32 ? 512 : 1024) ? 2 : 1; }
+// Lanes per line of the compile-time path: two wherever the thread count
+// allows; four on 48-point lines (2 vectors per workgroup: a 96-register line
+// leaves room for three wavefronts per SIMD only when the workgroup has them)
+constexpr int kron_lanes_per_line(int P, int nbt) {
+  return P == 48 && 4 * P * nbt <= 512 ? 4 : (2 * P * nbt <= (P >= 32 ? 512 : 1024) ? 2 : 1);
+}
 // and its workgroup size
 constexpr int kron_fixed_threads(int P, int nbt) { return (P * nbt * kron_lanes_per_line(P, nbt) + 63) / 64 * 64; }
 
@@ -186,9 +190,9 @@ constexpr int kron_fixed_threads(int P, int nbt) { return (P * nbt * kron_lanes_
 // in LDS are then resident together) and every global load of a thread is in flight
 // before the first is waited for; NBT = 0: sizes from the arguments.
 template <int P, bool EXACT, int NBT>
-__global__ __launch_bounds__(P >= 32 ? 512 : 1024) __attribute__((amdgpu_waves_per_eu(NBT == 8 && P <= 20 ? 7 : 1))) void k_kron(KronDev a) {
+__global__ __launch_bounds__(P >= 32 ? 512 : 1024) __attribute__((amdgpu_waves_per_eu(NBT == 8 && P <= 20 ? 7 : (P == 48 && NBT ? 3 : 1)))) void k_kron(KronDev a) {
   extern __shared__ double S[];  // [N][nb], then d_l [2][N] (alternating slices)
-  const int lin = kron_item((int)blockIdx.x);
+  const int lin = kron_item((int)blockIdx.x, kron_group(NBT ? NBT : 1 << a.lognb));
   if (lin >= a.nvb * a.batch) return;
   const int lg = NBT ? __builtin_ctz(NBT) : a.lognb, nb = NBT ? NBT : 1 << lg, N = a.N, lx = a.lx, ly = a.ly;
   constexpr int ROWS = P * NBT;  // NBT > 0: stride of lattice rows in S
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) __attribute__((amdgpu_waves_p
     }
     __syncthreads();
     if constexpr (NBT > 0) {
-      static_assert(EXACT && P <= 32, "compile-time blocks need an exact lattice of side <= 32");
+      static_assert(EXACT && (P <= 32 || P == 48), "compile-time blocks need an exact lattice of side <= 32 or 48");
       constexpr int H = kron_lanes_per_line(P, NBT);
       const int t = tid / H, h = tid % H;
       const auto creg = [&](int d) { return cw[d]; };
@@ -423,7 +427,8 @@ int launch_kron_windows(Plan& p, hipStream_t st) {
 static int kron_max_threads(int P) { return P >= 32 ? 512 : 1024; }
 
 static bool kron_fixed(const Plan& p, int nb) {
-  return p.m.lx == p.kron_P && p.m.ly == p.kron_P && p.kron_P <= 32 && (nb == 8 || nb == 16);
+  if (p.m.lx != p.kron_P || p.m.ly != p.kron_P) return false;
+  return (p.kron_P <= 32 && (nb == 8 || nb == 16)) || (p.kron_P == 48 && (nb == 2 || nb == 4));
 }
 // threads of a workgroup: one per line and vector, or H per line on the fixed path
 static int kron_threads(const Plan& p, int nb) {
@@ -447,6 +452,18 @@ int kron_default_nb(const Plan& p) {
 template <int P>
 static void launch_p(const KronDev& d, bool exact, int nb, bool fixed, dim3 grid, int threads, size_t lds,
                      hipStream_t st) {
+  if constexpr (P == 48) {
+    if (fixed && nb == 2) {
+      allow_max_lds((const void*)k_kron<P, true, 2>);
+      k_kron<P, true, 2><<<grid, threads, lds, st>>>(d);
+      return;
+    }
+    if (fixed && nb == 4) {
+      allow_max_lds((const void*)k_kron<P, true, 4>);
+      k_kron<P, true, 4><<<grid, threads, lds, st>>>(d);
+      return;
+    }
+  }
   if constexpr (P <= 32) {
     if (fixed && nb == 8) {
       allow_max_lds((const void*)k_kron<P, true, 8>);
@@ -520,7 +537,8 @@ int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
   d.batch = a.batch;
   d.first_block = a.first_block;
   d.block = a.block;
-  dim3 grid((unsigned)(((long)d.nvb * a.batch + 15) / 16 * 16));
+  const long gq = 8L * kron_group(nb);
+  dim3 grid((unsigned)(((long)d.nvb * a.batch + gq - 1) / gq * gq));
   switch (P) {
     case 4: launch_p<4>(d, exact, nb, fixed, grid, threads, lds, st); break;
     case 8: launch_p<8>(d, exact, nb, fixed, grid, threads, lds, st); break;

@@ -440,11 +440,16 @@ struct KronArgs {
 };
 int kron_line_size(int lx, int ly);
 // Workgroup-to-block order, XCD-aware: the hardware deals workgroups to the
-// 8 XCDs in turn, so hardware ids g and g + 8 run side by side on one XCD;
-// they take the vector blocks 2p and 2p + 1, which share every 128-byte line
-// of the field's rows in that XCD's L2 (each line is then fetched once, not
-// once per half).  A permutation within each aligned group of 16 ids.
-__device__ __forceinline__ int kron_item(int g) { return (g & ~15) | ((g & 7) << 1) | ((g >> 3) & 1); }
+// 8 XCDs in turn, so hardware ids g, g + 8, ..., g + 8 (G - 1) run side by
+// side on one XCD; they take the G consecutive vector blocks G p .. G p + G - 1,
+// which share the 128-byte lines of the field's rows (nb vectors of 8 bytes
+// per row and block: G = 128 / (8 nb), at least 2), so each line is fetched
+// into one L2 only.  A permutation within each aligned group of 8 G ids (the
+// grid is rounded up to a multiple of 8 G).
+__host__ __device__ inline int kron_group(int nb) { return nb >= 8 ? 2 : 16 / nb; }
+__device__ __forceinline__ int kron_item(int g, int G) {
+  return (g & ~(8 * G - 1)) | ((g & 7) * G) | ((g >> 3) & (G - 1));
+}
 // Checkerboard products (SLQ_PREC_CHECKERBOARD): launch_kron hands them to
 // launch_cb, which takes the same arguments.
 int launch_cb(Plan& p, const KronArgs& a, hipStream_t st);
