@@ -46,6 +46,7 @@ struct CbDev {
   double dpos, dneg;       // d_l for s = +1, -1 (reciprocals for the inverse)
   int nvb, batch;
   int npx, npy;            // plaquettes along x and y
+  int s_words;             // P = 4 and 4-byte aligned fields: a plaquette row's spins as one word
   double* norm2;           // columns: squared 2-norms of the output columns, or null
   const int32_t* first_block;
   int block;
@@ -67,7 +68,7 @@ template <int P, int QP, int NB>
 __global__ __launch_bounds__(QP >= 2 ? 512 : 1024) void k_cb(CbDev a) {
   extern __shared__ double S[];  // two exchange areas [npl][2 edges][P][NB], then one partial norm per thread
   constexpr int PS = P * P;
-  const int lin = kron_item((int)blockIdx.x);
+  const int lin = kron_item((int)blockIdx.x, kron_group(NB));
   if (lin >= a.nvb * a.batch) return;  // uniform over the workgroup
   const int N = a.N, lx = a.lx, npx = a.npx, npy = a.npy, npl = npx * npy;
   const int tid = threadIdx.x, nt = blockDim.x, c = tid % NB, slot = tid / NB, slots = nt / NB;
@@ -203,8 +204,14 @@ __global__ __launch_bounds__(QP >= 2 ? 512 : 1024) void k_cb(CbDev a) {
 #pragma unroll
       for (int dy = 0; dy < P; ++dy) {
         const int8_t* __restrict__ row = f + (ok[q] ? i0[q] + lx * dy : 0);
+        if (P == 4 && a.s_words) {
+          const unsigned w = *(const unsigned*)row;
 #pragma unroll
-        for (int dx = 0; dx < P; ++dx) v[q][dy * P + dx] *= row[dx] > 0 ? dpos : dneg;
+          for (int dx = 0; dx < P; ++dx) v[q][dy * P + dx] *= (w >> (8 * dx + 7)) & 1u ? dneg : dpos;
+        } else {
+#pragma unroll
+          for (int dx = 0; dx < P; ++dx) v[q][dy * P + dx] *= row[dx] > 0 ? dpos : dneg;
+        }
       }
   };
 
@@ -345,11 +352,15 @@ int launch_cb(Plan& p, const KronArgs& a, hipStream_t st) {
   d.batch = a.batch;
   d.npx = p.m.lx / P;
   d.npy = p.m.ly / P;
+  // row starts are multiples of 4 when P = 4 (lx, N and L N are), so the words
+  // are aligned when the field array is
+  d.s_words = P == 4 && a.s && ((uintptr_t)a.s % 4 == 0);
   d.norm2 = a.rows ? nullptr : a.norm2;
   d.first_block = a.first_block;
   d.block = a.block;
   const size_t lds = cb_lds(p, nb);
-  dim3 grid((unsigned)(((long)d.nvb * a.batch + 15) / 16 * 16));
+  const long gq = 8L * kron_group(nb);
+  dim3 grid((unsigned)(((long)d.nvb * a.batch + gq - 1) / gq * gq));
   if (P == 4) {
     if (qp == 1)
       launch_qp<4, 1>(d, nb, grid, threads, lds, st);

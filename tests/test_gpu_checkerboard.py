@@ -180,3 +180,27 @@ def test_48x48_full_size_weight(slq):
     assert host(st)[0] == 0 and host(sg)[0] == ref_sg
     assert abs(host(la)[0] - ref_la) <= LOG_TOL * abs(ref_la)
     plan.close()
+
+
+def test_unaligned_fields_take_the_byte_path(slq):
+    """Fields at an odd byte address are read spin by spin instead of as one
+    word per plaquette row: the same results bit for bit."""
+    from tests.gpu_util import dev, host
+    m = Model(8, 8, 10, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=5)
+    fields = np.stack([iid_field(m, 8600 + i) for i in range(2)])
+    plan = slq.Plan(m, 2, slq.SLQ_PREC_CHECKERBOARD)
+    flat = torch.zeros(fields.size + 1, dtype=torch.int8, device="cuda")
+    odd = flat[1:].view(fields.shape)
+    odd.copy_(dev(fields))
+    assert odd.data_ptr() % 4 == 1
+    out = []
+    for s in (dev(fields), odd):
+        G = _t((2, plan.n, plan.n), torch.float64)
+        la = _t(2, torch.float64)
+        sg = _t(2, torch.int8)
+        st = _t(2, torch.int32)
+        slq.slq_green(plan, s, G, la, sg, st)
+        out.append((host(G), host(la), host(sg), host(st)))
+    plan.close()
+    for x, y in zip(*out):
+        assert np.array_equal(x, y)
