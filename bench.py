@@ -345,6 +345,146 @@ def learned_48x48_rates(slq, fields: int = 64):
             "proposals_per_step": N * L, "net_forward_samples_per_s": F / t_f, "status_ok": ok}
 
 
+def learned_48x48_train(slq, chains, pairs, train_seconds, eval_steps, seed=0x5D0C + 7):
+    """The learned effective action at 48x48 (N = 2304), L = 100: `pairs`
+    (s, log|W_f|) pairs from `chains` chains of cumulative updates proposed by
+    the linear action (one effective sweep each, after 3 burn-in updates;
+    every pair's weight is the exact FP64 one the update computed), the linear
+    action refitted on all of them (Eq. 3), the network trained on the GPU on
+    the residual (FP32 forward and gradient kernels, Adam, batches of 64, 90 %
+    train / 10 % held out, output layer started at zero, `train_seconds` of
+    training), then `eval_steps` cumulative updates of the same chains
+    proposed by linear + network (FP64 moves, if an epoch beat the linear
+    action on held-out fields) and by the linear action alone, from the same
+    start."""
+    import numpy as np
+    import torch
+    from slq_inputs import LEARNED_48x48, iid_fields, default_terms, net_init
+    dev = torch.device("cuda")
+    f64, i8, i32 = torch.float64, torch.int8, torch.int32
+    m = LEARNED_48x48
+    C, N, L = chains, m.n_sites, m.n_slices
+    plan = slq.Plan(m, C, net=True)
+    slq.slq_plan_tune(plan, C)
+    terms = default_terms(L)
+    s = torch.from_numpy(iid_fields(m, C, 6300)).to(dev)
+    la = torch.empty(C, dtype=f64, device=dev)
+    sg = torch.empty(C, dtype=i8, device=dev)
+    st = torch.empty(C, dtype=i32, device=dev)
+    slq.slq_weight(plan, s, la, sg, st)
+    eff = slq.Eff(plan, terms, np.zeros(len(terms)))
+    theta = torch.empty(1 + len(terms), dtype=f64, device=dev)
+    r2 = torch.empty(1, dtype=f64, device=dev)
+    slq.slq_fit_effective(plan, eff, s, la, theta, r2)
+    slq.slq_eff_set_theta(eff, theta)
+    acc = torch.empty(C, dtype=i8, device=dev)
+    logA = torch.empty(C, dtype=f64, device=dev)
+    n_lin = eff.n_classes
+    steps = (pairs + C - 1) // C
+    xs = torch.empty((steps * C, L, N), dtype=i8, device=dev)
+    ys = torch.empty(steps * C, dtype=f64, device=dev)
+    n_acc = 0
+    t0 = time.perf_counter()
+    for k in range(3 + steps):
+        slq.slq_cumulative_step(plan, eff, s, la, sg, n_lin, seed, k, 0, acc, logA, st)
+        if k >= 3:
+            j = (k - 3) * C
+            xs[j:j + C].copy_(s)
+            ys[j:j + C].copy_(la)
+            n_acc += int(acc.sum().item())
+            print(f"# learned 48x48: {j + C} exact-weight pairs", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    ok = bool((st == 0).all().item())
+    P = xs.shape[0]
+    slq.slq_fit_effective(plan, eff, xs, ys, theta, r2)
+    slq.slq_eff_set_theta(eff, theta)
+    torch.cuda.synchronize()
+
+    n_tr = P - P // 10
+    prm = torch.from_numpy(net_init(seed)).to(dev)
+    prm[1960:] = 0.0
+    mom, vel, g = torch.zeros_like(prm), torch.zeros_like(prm), torch.empty_like(prm)
+    loss = torch.empty(1, dtype=f64, device=dev)
+
+    def held_out(params):
+        tot = 0.0
+        for k in range(n_tr, P, C):
+            e = min(P, k + C)
+            slq.slq_net_gradient(plan, eff, slq.SLQ_PREC_FP32, xs[k:e], ys[k:e], params, g, loss)
+            tot += float(loss.item()) * (e - k) / (P - n_tr)
+        return tot
+
+    mse_lin = held_out(torch.zeros_like(prm))
+    best_prm, best_mse, curve = None, mse_lin, []
+    order = np.random.default_rng(seed)
+    t_adam, batch, samples = 0, 64, 0
+    check = max(batch, (n_tr // 4) // batch * batch)   # held-out loss four times per epoch
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < train_seconds:
+        perm = torch.from_numpy(order.permutation(n_tr)).to(dev)
+        for k in range(0, n_tr - batch + 1, batch):
+            idx = perm[k:k + batch]
+            slq.slq_net_gradient(plan, eff, slq.SLQ_PREC_FP32, xs[idx].contiguous(), ys[idx].contiguous(), prm, g,
+                                 loss)
+            t_adam += 1
+            samples += batch
+            slq.slq_net_adam(prm, g, mom, vel, t_adam, lr=1e-3)
+            if samples % check == 0:
+                curve.append(held_out(prm))
+                if curve[-1] < best_mse:
+                    best_mse, best_prm = curve[-1], prm.clone()
+                print(f"# learned 48x48: {samples} training samples, held-out MSE {curve[-1]:.6g} "
+                      f"(linear {mse_lin:.6g})", file=sys.stderr, flush=True)
+            if time.perf_counter() - t0 >= train_seconds:
+                break
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    # proposals: the same chains from the same start, learned then linear
+    s0, la0, sg0 = s.clone(), la.clone(), sg.clone()
+
+    def run(n_moves, step0):
+        s.copy_(s0)
+        la.copy_(la0)
+        sg.copy_(sg0)
+        accs, la_std = [], []
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(eval_steps):
+            slq.slq_cumulative_step(plan, eff, s, la, sg, n_moves, seed, step0 + k, 0, acc, logA, st)
+            accs.append(float(acc.float().mean().item()))
+            la_std.append(float(logA.std().item()))
+        torch.cuda.synchronize()
+        return {"steps": eval_steps, "effective_moves": n_moves, "acceptance": float(np.mean(accs)),
+                "std_logA": float(np.mean(la_std)), "steps_per_s": C * eval_steps / (time.perf_counter() - t1),
+                "status_ok": bool((st == 0).all().item())}
+
+    learned = None
+    if best_prm is not None:
+        slq.slq_eff_set_net(eff, best_prm, slq.SLQ_PREC_FP64)
+        learned = run(slq.slq_eff_net_classes(eff), 10_000)
+        print("# learned 48x48: learned proposals done", file=sys.stderr, flush=True)
+        slq.slq_eff_set_net(eff, None)
+    linear = run(n_lin, 10_000)
+    out = {"workload": "learned_48x48", "model": "48x48, L=100, beta=10, xi=1.5, mu=-0.5",
+           "chains": C, "pairs": P, "pair_generation": {"seconds": t_gen, "acceptance": n_acc / P,
+                                                         "status_ok": ok},
+           "linear_fit": {"terms": len(terms), "r2": float(r2.item())},
+           "training": {"train": n_tr, "held_out": P - n_tr, "seconds": t_train, "adam_steps": t_adam,
+                        "epochs": samples / n_tr, "batch": batch, "lr": 1e-3, "net_prec": "fp32",
+                        "held_out_mse_linear": mse_lin, "held_out_mse_best": best_mse,
+                        "held_out_mse_curve": curve},
+           "proposals_linear": linear, "proposals_learned": learned,
+           "proposals_from": "linear + network" if best_prm is not None else
+                             "linear (fallback: no checkpoint beat the linear action on held-out fields)"}
+    eff.close()
+    plan.close()
+    del xs, ys
+    torch.cuda.empty_cache()
+    return out
+
+
 def precision_rates(slq, fields: int = 32):
     """Chain products of the 40x40, L=100 model (dtau 0.1, xi 1.5, n_s 10) in
     each precision mode: exact weights per second of `fields` fields and the
@@ -399,10 +539,18 @@ def group_rate(slq, dev, reps: int = 5):
         slq.slq_group_weight(grp, s, la, sg)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
-    flops = sum(2.0 * m.n_sites ** 3 * (m.n_slices - 1) for m in models)
+    def work(m):  # algorithmic flops of one exact weight: structured products, QRs, V updates, final step
+        n, blocks = m.n_sites, -(-m.n_slices // m.n_stab)
+        final = 4.0 / 3.0 * n ** 3 if n > 64 else 2.0 / 3.0 * n ** 3
+        return (2.0 * n * n * (m.lx + m.ly) * m.n_slices + blocks * 8.0 / 3.0 * n ** 3
+                + (blocks - 1) * float(n) ** 3 + final)
+    flops = sum(work(m) for m in models)
     info = grp.describe()
     grp.close()
-    return {"evals_per_s": 64 / dt, "ms_per_launch": dt * 1e3, "chain_tflops_effective": flops / dt / 1e12,
+    return {"evals_per_s": 64 / dt, "ms_per_launch": dt * 1e3, "graph_launches_per_eval": 1,
+            "algorithmic_tflops": flops / dt / 1e12,
+            "flops_note": "per chain: 2 N^2 (lx+ly) L structured products, (8/3) N^3 per QR, N^3 per V update, "
+                          "(4/3) N^3 final QR (N > 64) or (2/3) N^3 LU",
             "batches": len(info["batches"]), "tuned": info["tuned"]}
 
 
@@ -618,7 +766,7 @@ def dqmc_long(slq, chains, sweeps, every):
             "sweeps_per_s": chains * sweeps / (time.perf_counter() - t0), "log": log}
 
 
-def bilayer_tau(slq, sizes, chains, sweeps, steps, burn, train_sweeps, eff_sweeps):
+def bilayer_tau(slq, sizes, chains, sweeps, steps, burn, train_sweeps, eff_sweeps, sl_burn=None):
     """The paper's comparison of autocorrelation times (Fig. 3) on its own
     workload, at small sizes: the bilayer weight of Eq. 6 at beta = 1,
     dtau = 0.05, xi = 1, h = 2.774 (J = 1).  For each linear size: `chains`
@@ -631,7 +779,9 @@ def bilayer_tau(slq, sizes, chains, sweeps, steps, burn, train_sweeps, eff_sweep
     paper fits at L = 8 and reuses it) on DQMC configurations and their exact
     weights.  tau_int of M per sweep and per cumulative update, <M^2> and the
     susceptibility chi = dtau^2 <M^2> / (beta^2 N) of both samplers with
-    errors, wall time per sweep and per update."""
+    errors, wall time per sweep and per update.  tau_int is also given for |M|
+    and M^2, which the tunnelling between +M and -M does not set.  sl_burn: cumulative updates
+    before the recorded ones (default: burn)."""
     import numpy as np
     import torch
     from paper_1612_03804_amd.analysis import tau_int_window, mean_and_error, agree
@@ -678,7 +828,9 @@ def bilayer_tau(slq, sizes, chains, sweeps, steps, burn, train_sweeps, eff_sweep
         Mh = Md.cpu().numpy().T.astype(np.float64)
         ok_dq = bool((st == 0).all().item()) and float(drift.max().item()) < 1e-6
         rec = {"N": N, "dqmc": {"sweeps": sweeps, "ms_per_sweep": 1e3 * t_dq / sweeps,
-                                "tau_int_sweeps": tau_int_window(Mh), "M2": mean_and_error(Mh ** 2),
+                                "tau_int_sweeps": tau_int_window(Mh),
+                                "tau_int_sweeps_absM": tau_int_window(np.abs(Mh)),
+                                "tau_int_sweeps_M2": tau_int_window(Mh ** 2), "M2": mean_and_error(Mh ** 2),
                                 "status_ok": ok_dq, "max_drift": float(drift.max().item())}}
         if theta_h is None:   # fit the effective model at the smallest size (Eq. 3)
             terms = default_terms(L)
@@ -699,7 +851,7 @@ def bilayer_tau(slq, sizes, chains, sweeps, steps, burn, train_sweeps, eff_sweep
         Ms = torch.empty((steps, C), dtype=i64, device=dev)
         acc_c = torch.empty((steps, C), dtype=i8, device=dev)
         logA = torch.empty(C, dtype=f64, device=dev)
-        for k in range(burn):
+        for k in range(burn if sl_burn is None else sl_burn):
             slq.slq_bilayer_cumulative_step(plan, eff, BILAYER_J, BILAYER_H, s, lw, n_moves, seed, 100_000 + k, 0,
                                             acc_c[0], logA, st)
         torch.cuda.synchronize()
@@ -717,8 +869,11 @@ def bilayer_tau(slq, sizes, chains, sweeps, steps, burn, train_sweeps, eff_sweep
         m2_sl = mean_and_error(Msh ** 2)
         beta = m.beta
         chi = lambda x: (m.dtau ** 2 * x[0] / (beta ** 2 * N), m.dtau ** 2 * x[1] / (beta ** 2 * N))
-        rec["sldqmc"] = {"steps": steps, "effective_moves": n_moves, "ms_per_step": 1e3 * t_sl / steps,
+        rec["sldqmc"] = {"steps": steps, "effective_sweeps_per_step": eff_sweeps, "effective_moves": n_moves,
+                         "ms_per_step": 1e3 * t_sl / steps,
                          "acceptance": float(acc_c.float().mean().item()), "tau_int_steps": tau_int_window(Msh),
+                         "tau_int_steps_absM": tau_int_window(np.abs(Msh)),
+                         "tau_int_steps_M2": tau_int_window(Msh ** 2),
                          "M2": m2_sl, "status_ok": bool((st == 0).all().item())}
         rec["chi_dqmc"] = chi(rec["dqmc"]["M2"])
         rec["chi_sldqmc"] = chi(m2_sl)
@@ -762,6 +917,13 @@ def main():
     ap.add_argument("--bilayer-steps", type=int, default=400)
     ap.add_argument("--bilayer-burn", type=int, default=200)
     ap.add_argument("--bilayer-eff-sweeps", type=int, default=50)
+    ap.add_argument("--bilayer-sl-burn", type=int, default=None,
+                    help="cumulative updates before the recorded ones (default: --bilayer-burn)")
+    ap.add_argument("--learned-train", type=int, default=0, metavar="PAIRS",
+                    help="the learned action at 48x48, L=100 on this many exact-weight pairs (own JSON line)")
+    ap.add_argument("--learned-chains", type=int, default=256)
+    ap.add_argument("--learned-seconds", type=float, default=240.0)
+    ap.add_argument("--learned-eval-steps", type=int, default=10)
     ap.add_argument("--reports", action="store_true",
                     help="print the uneven-group, precision-mode and learned-proposal reports (own JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -806,7 +968,12 @@ def main():
     if args.bilayer_tau:
         sizes = [int(x) for x in args.bilayer_sizes.split(",")]
         print(json.dumps(bilayer_tau(slq, sizes, args.bilayer_chains, args.bilayer_sweeps, args.bilayer_steps,
-                                     args.bilayer_burn, 40, args.bilayer_eff_sweeps)), flush=True)
+                                     args.bilayer_burn, 40, args.bilayer_eff_sweeps, args.bilayer_sl_burn)),
+              flush=True)
+        return
+    if args.learned_train:
+        print(json.dumps(learned_48x48_train(slq, args.learned_chains, args.learned_train, args.learned_seconds,
+                                             args.learned_eval_steps)), flush=True)
         return
     if args.reports:
         dev = torch.device("cuda")
@@ -822,6 +989,18 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_details and args.workload != "dqmc_20x20":
         details["dqmc_20x20"] = details_20x20(slq, 0x5D0C + 2)
+    if not args.no_details and args.chain == "exact":
+        # the same workload with the checkerboard split (its own discretisation), a few steps
+        cb_args = argparse.Namespace(**{**vars(args), "chain": "checkerboard", "steps": 3, "warmup": 1,
+                                        "block_width": 0})
+        o2, d2, p2, e2, *_ = headline(slq, cb_args, args.workload)
+        e2.close()
+        p2.close()
+        torch.cuda.empty_cache()
+        details["checkerboard"] = {"evals_per_s": o2["value"], "ms_per_step": o2["ms_per_step"],
+                                   "steps": 3, "chain": d2["parts"]["chain"],
+                                   "stabilisation_share": d2["parts"]["stabilisation"]["share_of_step"],
+                                   "vectors_per_workgroup": o2["config"]["chain_block_vectors_per_workgroup"]}
     out["details"] = details
     if not args.no_cpu_baseline:
         print("# oracle timing on the host", file=sys.stderr, flush=True)
