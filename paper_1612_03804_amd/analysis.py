@@ -6,7 +6,11 @@ caption of the paper), estimated jointly from many independent chains: the
 mean is taken over all chains and times, the lagged products are averaged
 over chains and time origins.  The integrated autocorrelation time
 tau_int = 1/2 + sum_{t=1}^{W} C(t) uses the automatic window (smallest W with
-W >= c * tau_int(W), c = 5); effective independent samples = n / (2 tau_int).
+W >= c * tau_int(W), c = 5).  The window presumes positive correlations: when
+its sum is below 1/2 (anticorrelated successive values, e.g. local sweeps that
+flip most spins) it stops at W = 1, and tau_int is then the initial positive
+sequence estimate -1/2 + sum_{k<=K} (C(2k) + C(2k+1)), K the last k before a
+pair sum is not positive (Geyer).  Effective independent samples = n / (2 tau_int).
 """
 from __future__ import annotations
 
@@ -26,28 +30,39 @@ def autocorrelation_chains(m: np.ndarray) -> np.ndarray:
     return np.array([float((d[:, :T - t] * d[:, t:]).mean()) / var for t in range(max(1, T // 2))])
 
 
-def tau_int_chains(m: np.ndarray, c: float = 5.0) -> float:
-    """tau_int with the automatic window, not clamped: a series whose
-    successive values are anticorrelated (e.g. local sweeps that flip most
-    spins) has tau_int < 1/2, i.e. more than one effective sample per step."""
-    rho = autocorrelation_chains(m)
-    tau = 0.5
-    for w in range(1, len(rho)):
-        tau += rho[w]
-        if w >= c * max(tau, 0.0):
+def _initial_positive_sequence(rho: np.ndarray) -> tuple[float, int]:
+    total, k = 0.0, 0
+    while 2 * k + 1 < len(rho):
+        pair = rho[2 * k] + rho[2 * k + 1]
+        if pair <= 0.0:
             break
-    return float(tau)
+        total += pair
+        k += 1
+    return total - 0.5, 2 * k - 1
+
+
+def tau_int_chains(m: np.ndarray, c: float = 5.0) -> float:
+    """tau_int, not clamped: a series whose successive values are
+    anticorrelated has tau_int < 1/2, i.e. more than one effective sample per
+    step (then from the initial positive sequence)."""
+    return tau_int_window(m, c)["tau_int"]
 
 
 def tau_int_window(m: np.ndarray, c: float = 5.0) -> dict:
     """tau_int with its window W and whether the window condition W >= c tau
     was met before the lags ran out (T/2); when it was not, tau is a lower
-    bound of the series' integrated autocorrelation time."""
+    bound of the series' integrated autocorrelation time.  Anticorrelated
+    series (windowed sum below 1/2) take the initial positive sequence; its
+    last lag is reported as the window."""
     rho = autocorrelation_chains(m)
     tau = 0.5
     for w in range(1, len(rho)):
         tau += rho[w]
         if w >= c * max(tau, 0.0):
+            if tau < 0.5:
+                ips, last = _initial_positive_sequence(rho)
+                return {"tau_int": float(ips), "window": last, "converged": True,
+                        "estimator": "initial positive sequence"}
             return {"tau_int": float(tau), "window": w, "converged": True}
     return {"tau_int": float(tau), "window": len(rho) - 1, "converged": False}
 

@@ -257,7 +257,7 @@ def test_fit_on_random_labels_scores_low():
 
 
 # ------------------------------------------------------ autocorrelation ----
-@pytest.mark.parametrize("rho", [0.0, 0.5, 0.9])
+@pytest.mark.parametrize("rho", [-0.9, -0.5, 0.0, 0.5, 0.9])
 def test_tau_int_ar1(rho):
     g = np.random.default_rng(4)
     n = 200000
@@ -268,6 +268,21 @@ def test_tau_int_ar1(rho):
         x[t] = rho * x[t - 1] + noise[t]
     exact = (1 + rho) / (2 * (1 - rho))
     assert abs(autocorr.tau_int(x) - exact) < 0.06 * exact + 0.02
+
+
+def test_tau_int_of_a_period_two_series_is_its_closed_form():
+    """An anticorrelated AR(1) (rho = -0.8): tau_int = (1 + rho) / (2 (1 - rho)),
+    far below 1/2, where the windowed sum alone would stop at a negative value."""
+    g = np.random.default_rng(5)
+    rho, n = -0.8, 400000
+    x = np.empty(n)
+    x[0] = g.normal()
+    noise = g.normal(size=n)
+    for t in range(1, n):
+        x[t] = rho * x[t - 1] + noise[t]
+    exact = (1 + rho) / (2 * (1 - rho))
+    assert 0.5 + autocorr.autocorrelation(x)[1] < 0    # the window's own estimate is negative
+    assert abs(autocorr.tau_int(x) - exact) < 0.01
 
 
 # ------------------------------------------- package analysis vs oracle ----
@@ -283,3 +298,10 @@ def test_package_tau_int_matches_ar1_and_oracle():
     exact = (1 + rho) / (2 * (1 - rho))
     assert abs(tau_int_chains(x) - exact) < 0.05 * exact
     assert abs(tau_int_chains(x[0]) - autocorr.tau_int(x[0])) < 0.1 * exact
+    # anticorrelated chains (rho = -0.7): the initial positive sequence
+    rho = -0.7
+    x[:, 0] = g.normal(size=chains) / np.sqrt(1 - rho * rho)
+    for t in range(1, T):
+        x[:, t] = rho * x[:, t - 1] + noise[:, t]
+    exact = (1 + rho) / (2 * (1 - rho))
+    assert abs(tau_int_chains(x) - exact) < 0.01
