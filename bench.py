@@ -547,11 +547,66 @@ def group_rate(slq, dev, reps: int = 5):
     flops = sum(work(m) for m in models)
     info = grp.describe()
     grp.close()
+    cum = group_cumulative_rate(slq, dev, models, reps)
     return {"evals_per_s": 64 / dt, "ms_per_launch": dt * 1e3, "graph_launches_per_eval": 1,
+            "cumulative_updates": cum,
             "algorithmic_tflops": flops / dt / 1e12,
             "flops_note": "per chain: 2 N^2 (lx+ly) L structured products, (8/3) N^3 per QR, N^3 per V update, "
                           "(4/3) N^3 final QR (N > 64) or (2/3) N^3 LU",
             "batches": len(info["batches"]), "tuned": info["tuned"]}
+
+
+def group_cumulative_rate(slq, dev, models, reps):
+    """Cumulative updates of the 64 uneven chains in one call per update: one
+    batch per distinct model, each with a short linear effective action (one-
+    body, nearest-neighbour, nearest-slice and space-time terms) fitted on the
+    GPU (Eq. 3) to the exact weights of 32 iid fields of its model, one
+    effective sweep per proposal."""
+    import numpy as np
+    import torch
+    from slq_inputs import iid_field, iid_fields
+    grp = slq.Group(models, exact_batches=True)
+    fields = [iid_field(m, 4200 + c) for c, m in enumerate(models)]
+    s = torch.from_numpy(grp.pack(fields)).to(dev)
+    n = len(models)
+    la = torch.empty(n, dtype=torch.float64, device=dev)
+    sg = torch.empty(n, dtype=torch.int8, device=dev)
+    slq.slq_group_weight(grp, s, la, sg)
+    effs = []
+    terms = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    for k in range(grp.n_batches):
+        plan, ids = grp.batch(k)
+        m = models[int(ids[0])]
+        eff = slq.Eff(plan, terms, np.zeros(len(terms)))
+        xs = torch.from_numpy(iid_fields(m, 32, 4300 + k)).to(dev)
+        ys = torch.empty(32, dtype=torch.float64, device=dev)
+        sgw = torch.empty(32, dtype=torch.int8, device=dev)
+        for c0 in range(0, 32, plan.max_batch):
+            c1 = min(32, c0 + plan.max_batch)
+            slq.slq_weight(plan, xs[c0:c1], ys[c0:c1], sgw[c0:c1])
+        theta = torch.empty(1 + len(terms), dtype=torch.float64, device=dev)
+        r2 = torch.empty(1, dtype=torch.float64, device=dev)
+        slq.slq_fit_effective(plan, eff, xs, ys, theta, r2)
+        slq.slq_eff_set_theta(eff, theta)
+        effs.append(eff)
+    acc = torch.empty(n, dtype=torch.int8, device=dev)
+    st = torch.empty(n, dtype=torch.int32, device=dev)
+    slq.slq_group_cumulative_step(grp, effs, 1, 0x5D0C + 4, 0, s, la, sg, acc, None, st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rate = 0.0
+    for k in range(reps):
+        slq.slq_group_cumulative_step(grp, effs, 1, 0x5D0C + 4, 1 + k, s, la, sg, acc, None, st)
+        rate += float(acc.float().mean().item())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ok = bool((st == 0).all().item())
+    nb = grp.n_batches
+    for e in effs:
+        e.close()
+    grp.close()
+    return {"batches": nb, "updates_per_s": n / dt, "ms_per_call": dt * 1e3, "acceptance": rate / reps,
+            "status_ok": ok, "effective_sweeps_per_update": 1}
 
 
 def headline(slq, args, workload):

@@ -100,6 +100,7 @@ typedef struct slq_model {
 } slq_model;
 
 typedef struct slq_plan slq_plan;
+typedef struct slq_eff slq_eff; /* an effective model on a plan: see slq_eff_create */
 
 /* Library version string and the last error message of this thread. */
 const char* slq_version(void);
@@ -283,6 +284,11 @@ int slq_green_displaced(slq_plan* plan, int32_t batch, const int8_t* d_s, int32_
  */
 typedef struct slq_group slq_group;
 int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out);
+/* As slq_group_create; flags SLQ_GROUP_EXACT_BATCHES: only chains with
+ * identical models share a batch (no merging of lengths), which
+ * slq_group_cumulative_step needs. */
+enum { SLQ_GROUP_EXACT_BATCHES = 1 };
+int slq_group_create_flags(const slq_model* models, int32_t n_chains, int32_t flags, slq_group** out);
 int slq_group_destroy(slq_group* group);
 /* Packed layouts (host arrays of n_chains + 1 entries): chain c's field is the
  * int8 [L_c][N_c] block at byte offset s_off[c] of d_s, its G the FP64
@@ -308,6 +314,32 @@ int slq_group_weight(slq_group* group, const int8_t* d_s, double* d_logabs, int8
                      int32_t* d_status, hipStream_t stream);
 int slq_group_green(slq_group* group, const int8_t* d_s, double* d_G, double* d_logabs,
                     int8_t* d_sign, int32_t* d_status, hipStream_t stream);
+/* Batches of the group: their number, and batch k's internal plan (owned by
+ * the group; valid until slq_group_destroy), its chain count and, if
+ * chain_ids is not NULL, the chain index of each batch position (host int32
+ * [n_chains]).  The plan serves to create the batch's effective model
+ * (slq_eff_create) and to fit it (slq_fit_effective on fields of that model). */
+int slq_group_batches(const slq_group* group, int32_t* n_batches);
+int slq_group_batch(slq_group* group, int32_t k, slq_plan** plan, int32_t* n_chains, int32_t* chain_ids);
+/*
+ * slq_group_cumulative_step - one cumulative update (steps (iii)-(iv) of
+ * "Formalism of SLDQMC", Eq. 4) of every chain of the group, each with its
+ * batch's effective model: effs[k] (created on batch k's plan) for batch k,
+ * eff_sweeps sweeps of effective moves (eff_sweeps x its colour classes) per
+ * proposal, judged by the exact FP64 weight of its own model.  In place on
+ * the packed fields d_s and on d_logabs / d_sign [n_chains] (the current
+ * weights); out (may be NULL): d_accepted int8, d_logA FP64, d_status int32
+ * [n_chains].  Batch k's chains draw the random numbers of slq_cumulative_step
+ * with chain0 = the number of chains in batches 0..k-1, batch position b as
+ * chain chain0 + b.  The batches are dealt to the group's streams as for the
+ * weight; the call is ordered after prior work on `stream`, and later work on
+ * `stream` waits for all of it.  Errors: SLQ_ERR_ARG (a NULL effective model,
+ * an effective model of another plan, a group that merged chains of
+ * different lengths: create it with SLQ_GROUP_EXACT_BATCHES), SLQ_ERR_DEVICE.
+ */
+int slq_group_cumulative_step(slq_group* group, slq_eff* const* effs, int32_t eff_sweeps, uint64_t seed,
+                              uint64_t step, int8_t* d_s, double* d_logabs, int8_t* d_sign,
+                              int8_t* d_accepted, double* d_logA, int32_t* d_status, hipStream_t stream);
 
 /*
  * slq_sweep_local - n_sweeps local-update DQMC sweeps ("Basics of DQMC") on
@@ -358,8 +390,8 @@ int slq_sweep_local(slq_plan* plan, int32_t batch, int8_t* d_s, double* d_G,
  * smallest free colour) of the graph of dl = 0 couplings; class index =
  * colour + n_colours*(l-1).  A move draws a class uniformly and applies
  * Metropolis u < exp(dS), dS = -2 s_x sum_k lambda_k h_k(x), to all its sites.
+ * (slq_eff is declared with slq_plan above.)
  */
-typedef struct slq_eff slq_eff;
 
 /* slq_eff_workspace_size - *bytes = device bytes of an effective model with
  * n_terms terms on `plan` (its tables, and room for an attached network's

@@ -31,6 +31,14 @@ struct SubPlan {
   int64_t* d_lead = nullptr;  // [nb] leading slices x N of the batch layout before the chain's own
   int32_t* d_first = nullptr; // [nb] first stabilisation block of each chain
   int lmin = 0;               // shortest chain of the batch (its plan has the longest)
+  std::vector<int32_t> ids;   // host copy of d_ids
+  int chain0 = 0;             // chains in the batches before this one (random-number stream of the batch)
+  // cumulative updates: the batch's current fields and per-chain state
+  int8_t* cur = nullptr;      // [nb][L][N]
+  double* la = nullptr;       // [nb] log|W|
+  double* logA = nullptr;     // [nb]
+  int8_t* sg = nullptr;       // [nb] sign
+  int8_t* acc = nullptr;      // [nb] accepted
 };
 
 struct Group {
@@ -42,6 +50,8 @@ struct Group {
   std::vector<int> tuned_n, tuned_kind, tuned_cfg;  // kind 0: chain GEMM tile, 1: structured vectors/workgroup
   std::vector<double> tuned_tflops;
   void* dmem = nullptr;
+  void* dstep = nullptr;  // cumulative-update buffers of the batches
+  int32_t flags = 0;
   hipStream_t gs = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr;
   // the sub-batches are dealt to up to kLanes streams (largest estimated work
@@ -80,6 +90,37 @@ __global__ void k_scatter(int nb, const int32_t* __restrict__ ids, const double*
   out_la[c] = la[pos];
   out_sg[c] = sg[pos];
   if (out_st) out_st[c] = st[pos];
+}
+
+__global__ void k_gather_state(int nb, const int32_t* __restrict__ ids, const double* __restrict__ la,
+                               const int8_t* __restrict__ sg, double* __restrict__ out_la, int8_t* __restrict__ out_sg) {
+  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= nb) return;
+  out_la[pos] = la[ids[pos]];
+  out_sg[pos] = sg[ids[pos]];
+}
+
+__global__ void k_scatter_state(int nb, const int32_t* __restrict__ ids, const double* __restrict__ la,
+                                const int8_t* __restrict__ sg, const int8_t* __restrict__ acc,
+                                const double* __restrict__ logA, const int32_t* __restrict__ st,
+                                double* __restrict__ out_la, int8_t* __restrict__ out_sg, int8_t* __restrict__ out_acc,
+                                double* __restrict__ out_logA, int32_t* __restrict__ out_st) {
+  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= nb) return;
+  const int c = ids[pos];
+  out_la[c] = la[pos];
+  out_sg[c] = sg[pos];
+  if (out_acc) out_acc[c] = acc[pos];
+  if (out_logA) out_logA[c] = logA[pos];
+  if (out_st) out_st[c] = st[pos];
+}
+
+__global__ void k_scatter_fields(const int8_t* __restrict__ src, const int64_t* __restrict__ soff, long per,
+                                 int8_t* __restrict__ dst) {
+  const int pos = blockIdx.y;
+  const int8_t* s = src + (long)pos * per;
+  int8_t* d = dst + soff[pos];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
 }
 
 __global__ void k_scatter_g(long NN, const int64_t* __restrict__ goff, const double* __restrict__ G,
@@ -240,6 +281,7 @@ static void release(Group& g) {
     if (ls) hipStreamDestroy(ls);
   for (SubPlan& sp : g.subs) slq_plan_destroy(sp.plan);
   if (g.dmem) hipFree(g.dmem);
+  if (g.dstep) hipFree(g.dstep);
   if (g.ev_in) hipEventDestroy(g.ev_in);
   if (g.ev_out) hipEventDestroy(g.ev_out);
   if (g.ev_fork) hipEventDestroy(g.ev_fork);
@@ -258,6 +300,14 @@ using namespace slq;
 extern "C" {
 
 int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out) {
+  return slq_group_create_flags(models, n_chains, 0, out);
+}
+
+int slq_group_create_flags(const slq_model* models, int32_t n_chains, int32_t flags, slq_group** out) {
+  if (flags & ~SLQ_GROUP_EXACT_BATCHES) {
+    set_error("unknown group flags");
+    return SLQ_ERR_ARG;
+  }
   if (!models || !out || n_chains < 1) {
     set_error("models, out and n_chains >= 1 are required");
     return SLQ_ERR_ARG;
@@ -273,6 +323,7 @@ int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out)
     return SLQ_ERR_DEVICE;
   }
   Group& g = h->g;
+  g.flags = flags;
   g.n = n_chains;
   g.models.assign(models, models + n_chains);
   if (hipGetDevice(&g.device) != hipSuccess) {
@@ -297,7 +348,9 @@ int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out)
   for (int c = 0; c < n_chains; ++c) {
     int k = -1;
     for (size_t q = 0; q < rep.size() && k < 0; ++q)
-      if (same_model(models[rep[q]], models[c]) || same_but_length(models[rep[q]], models[c])) k = (int)q;
+      if (same_model(models[rep[q]], models[c]) ||
+          (!(flags & SLQ_GROUP_EXACT_BATCHES) && same_but_length(models[rep[q]], models[c])))
+        k = (int)q;
     if (k < 0) {
       rep.push_back(c);
       members.emplace_back();
@@ -354,7 +407,37 @@ int slq_group_create(const slq_model* models, int32_t n_chains, slq_group** out)
       rc = SLQ_ERR_DEVICE;
     }
     if (varied) sp.plan->p.first_block = sp.d_first;
+    sp.ids = ids;
+    sp.chain0 = g.subs.empty() ? 0 : g.subs.back().chain0 + g.subs.back().nb;
     g.subs.push_back(sp);
+  }
+  // buffers of the cumulative updates: each batch's current fields and state
+  if (rc == SLQ_OK) {
+    size_t sb = 0;
+    auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+    for (SubPlan& sp : g.subs) {
+      const Plan& p = sp.plan->p;
+      sb += align((size_t)sp.nb * p.L * p.n) + 2 * align(8 * (size_t)sp.nb) + 2 * align((size_t)sp.nb);
+    }
+    if (hipMalloc(&g.dstep, sb) != hipSuccess) {
+      set_error("hipMalloc failed");
+      rc = SLQ_ERR_DEVICE;
+    } else {
+      char* q = (char*)g.dstep;
+      for (SubPlan& sp : g.subs) {
+        const Plan& p = sp.plan->p;
+        sp.cur = (int8_t*)q;
+        q += align((size_t)sp.nb * p.L * p.n);
+        sp.la = (double*)q;
+        q += align(8 * (size_t)sp.nb);
+        sp.logA = (double*)q;
+        q += align(8 * (size_t)sp.nb);
+        sp.sg = (int8_t*)q;
+        q += align((size_t)sp.nb);
+        sp.acc = (int8_t*)q;
+        q += align((size_t)sp.nb);
+      }
+    }
   }
   if (rc == SLQ_OK && (hipStreamCreateWithFlags(&g.gs, hipStreamNonBlocking) != hipSuccess ||
                        hipEventCreateWithFlags(&g.ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -469,6 +552,85 @@ int slq_group_describe(const slq_group* grp, char* buf, size_t len) {
     return SLQ_ERR_ARG;
   }
   memcpy(buf, s.c_str(), s.size() + 1);
+  return SLQ_OK;
+}
+
+int slq_group_batches(const slq_group* grp, int32_t* n_batches) {
+  if (!grp || !n_batches) {
+    set_error("NULL argument");
+    return SLQ_ERR_ARG;
+  }
+  *n_batches = (int32_t)grp->g.subs.size();
+  return SLQ_OK;
+}
+
+int slq_group_batch(slq_group* grp, int32_t k, slq_plan** plan, int32_t* n_chains, int32_t* chain_ids) {
+  if (!grp || !plan || !n_chains) {
+    set_error("NULL argument");
+    return SLQ_ERR_ARG;
+  }
+  const Group& g = grp->g;
+  if (k < 0 || k >= (int32_t)g.subs.size()) {
+    set_error("batch index out of range");
+    return SLQ_ERR_ARG;
+  }
+  const SubPlan& sp = g.subs[k];
+  *plan = sp.plan;
+  *n_chains = sp.nb;
+  if (chain_ids) memcpy(chain_ids, sp.ids.data(), sizeof(int32_t) * sp.nb);
+  return SLQ_OK;
+}
+
+int slq_group_cumulative_step(slq_group* grp, slq_eff* const* effs, int32_t eff_sweeps, uint64_t seed, uint64_t step,
+                              int8_t* d_s, double* d_logabs, int8_t* d_sign, int8_t* d_accepted, double* d_logA,
+                              int32_t* d_status, hipStream_t stream) {
+  if (!grp || !effs || !d_s || !d_logabs || !d_sign) {
+    set_error("NULL argument");
+    return SLQ_ERR_ARG;
+  }
+  Group& g = grp->g;
+  if (eff_sweeps < 0) {
+    set_error("eff_sweeps must be >= 0");
+    return SLQ_ERR_ARG;
+  }
+  for (size_t q = 0; q < g.subs.size(); ++q) {
+    if (g.subs[q].lmin != g.subs[q].plan->p.L) {
+      set_error("the group batches chains of different lengths; create it with SLQ_GROUP_EXACT_BATCHES");
+      return SLQ_ERR_ARG;
+    }
+    if (!effs[q]) {
+      set_error("one effective model per batch is required");
+      return SLQ_ERR_ARG;
+    }
+  }
+  SLQ_HIP(hipSetDevice(g.device));
+  SLQ_HIP(hipEventRecord(g.ev_in, stream));
+  for (size_t k = 0; k < g.lane_st.size(); ++k) {
+    hipStream_t ls = g.lane_st[k];
+    SLQ_HIP(hipStreamWaitEvent(ls, g.ev_in, 0));
+    for (int q : g.lane_subs[k]) {
+      SubPlan& sp = g.subs[q];
+      Plan& p = sp.plan->p;
+      const long per = (long)p.L * p.n;
+      const dim3 fgrid((unsigned)std::max<long>(1, std::min<long>((per + 255) / 256, 256)), sp.nb);
+      const unsigned sgrid = (unsigned)((sp.nb + 63) / 64);
+      int32_t classes = 0;
+      SLQ_TRY(slq_eff_classes(effs[q], &classes));
+      k_gather<<<fgrid, 256, 0, ls>>>(d_s, sp.d_soff, sp.d_lead, per, sp.cur);
+      SLQ_LAUNCHED();
+      k_gather_state<<<sgrid, 64, 0, ls>>>(sp.nb, sp.d_ids, d_logabs, d_sign, sp.la, sp.sg);
+      SLQ_LAUNCHED();
+      SLQ_TRY(slq_cumulative_step(sp.plan, effs[q], sp.nb, sp.cur, sp.la, sp.sg, eff_sweeps * classes, seed, step,
+                                  (uint64_t)sp.chain0, sp.acc, sp.logA, p.status, ls));
+      k_scatter_fields<<<fgrid, 256, 0, ls>>>(sp.cur, sp.d_soff, per, d_s);
+      SLQ_LAUNCHED();
+      k_scatter_state<<<sgrid, 64, 0, ls>>>(sp.nb, sp.d_ids, sp.la, sp.sg, sp.acc, sp.logA, p.status, d_logabs,
+                                            d_sign, d_accepted, d_logA, d_status);
+      SLQ_LAUNCHED();
+    }
+    SLQ_HIP(hipEventRecord(g.lane_ev[k], ls));
+    SLQ_HIP(hipStreamWaitEvent(stream, g.lane_ev[k], 0));
+  }
   return SLQ_OK;
 }
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libslq.so")
 SLQ_OK, SLQ_ERR_ARG, SLQ_ERR_DEVICE, SLQ_ERR_WORKSPACE, SLQ_ERR_NUMERIC = 0, -1, -2, -3, -4
 SLQ_ST_BAD_SPIN, SLQ_ST_NONFINITE, SLQ_ST_SINGULAR, SLQ_ST_PIVOT = 1, 2, 4, 8
 SLQ_PLAN_SWEEPS, SLQ_PLAN_NET = 1, 2
+SLQ_GROUP_EXACT_BATCHES = 1
 SLQ_PREC_FP64, SLQ_PREC_FP32, SLQ_PREC_BF16, SLQ_PREC_FP64_DENSE, SLQ_PREC_CHECKERBOARD = 0, 1, 2, 3, 4
 
 # every exported symbol of include/slq.h
@@ -28,7 +29,8 @@ EXPORTS = (
     "slq_profile_enable", "slq_profile_read", "slq_profile_read_part",
     "slq_weight", "slq_green", "slq_udv", "slq_sweep_local", "slq_eff_create", "slq_eff_destroy",
     "slq_eff_classes", "slq_eff_set_theta", "slq_eff_sweep", "slq_eff_features", "slq_cumulative_step",
-    "slq_fit_effective", "slq_group_create", "slq_group_destroy", "slq_group_layout", "slq_group_describe",
+    "slq_fit_effective", "slq_group_create", "slq_group_create_flags", "slq_group_batches", "slq_group_batch",
+    "slq_group_cumulative_step", "slq_group_destroy", "slq_group_layout", "slq_group_describe",
     "slq_group_weight", "slq_group_green", "slq_magnetization", "slq_net_forward", "slq_net_gradient",
     "slq_net_adam", "slq_eff_set_net", "slq_eff_net_classes", "slq_plan_tune", "slq_plan_set_block_width",
     "slq_bilayer_weight", "slq_bilayer_green", "slq_bilayer_sweep_local", "slq_bilayer_cumulative_step",
@@ -96,6 +98,10 @@ def load_library(path: str = LIB_PATH):
         "slq_cumulative_step": ([P, P, i32, P, P, P, i32, u64, u64, u64, P, P, P, P], C.c_int),
         "slq_fit_effective": ([P, P, i64, P, P, P, P, P], C.c_int),
         "slq_group_create": ([P, i32, C.POINTER(P)], C.c_int),
+        "slq_group_create_flags": ([P, i32, i32, C.POINTER(P)], C.c_int),
+        "slq_group_batches": ([P, C.POINTER(i32)], C.c_int),
+        "slq_group_batch": ([P, i32, C.POINTER(P), C.POINTER(i32), P], C.c_int),
+        "slq_group_cumulative_step": ([P, P, i32, u64, u64, P, P, P, P, P, P, P], C.c_int),
         "slq_group_destroy": ([P], C.c_int),
         "slq_group_layout": ([P, P, P], C.c_int),
         "slq_group_describe": ([P, C.c_char_p, C.c_size_t], C.c_int),
@@ -389,16 +395,31 @@ def slq_fit_effective(plan: Plan, eff: Eff, S, logabs, theta, r2, stream=None):
 
 
 # ------------------------------------------------------------------ group ----
-class Group:
-    """Owns an slq_group: chains of uneven (N, L), one graph launch per evaluation."""
+class _BatchPlan:
+    """A group batch's internal plan (owned by the group), usable wherever a
+    Plan is (slq.Eff, slq_fit_effective)."""
 
-    def __init__(self, models, chain_prec: int = 0):
+    def __init__(self, handle, model, n_chains):
+        self.handle = handle
+        self.model = model
+        self.n = model.lx * model.ly
+        self.L = model.n_slices
+        self.max_batch = n_chains
+
+
+class Group:
+    """Owns an slq_group: chains of uneven (N, L), one graph launch per evaluation.
+    exact_batches: only identical models share a batch (needed by
+    slq_group_cumulative_step)."""
+
+    def __init__(self, models, chain_prec: int = 0, exact_batches: bool = False):
         import numpy as np
         lib = load_library()
         self.models = list(models)
         arr = (slq_model * len(self.models))(*[slq_model.of(m, chain_prec) for m in self.models])
         h = C.c_void_p()
-        _check(lib.slq_group_create(arr, len(self.models), C.byref(h)))
+        _check(lib.slq_group_create_flags(arr, len(self.models), SLQ_GROUP_EXACT_BATCHES if exact_batches else 0,
+                                          C.byref(h)))
         self.handle = h
         n = len(self.models)
         so = np.zeros(n + 1, dtype=np.int64)
@@ -411,6 +432,23 @@ class Group:
         buf = C.create_string_buffer(1 << 16)
         _check(load_library().slq_group_describe(self.handle, buf, len(buf)))
         return json.loads(buf.value.decode())
+
+    @property
+    def n_batches(self) -> int:
+        v = C.c_int32()
+        _check(load_library().slq_group_batches(self.handle, C.byref(v)))
+        return v.value
+
+    def batch(self, k: int):
+        """(plan of batch k, chain indices of its positions)."""
+        import numpy as np
+        h = C.c_void_p()
+        n = C.c_int32()
+        _check(load_library().slq_group_batch(self.handle, int(k), C.byref(h), C.byref(n), None))
+        ids = np.zeros(n.value, dtype=np.int32)
+        _check(load_library().slq_group_batch(self.handle, int(k), C.byref(h), C.byref(n),
+                                              ids.ctypes.data_as(C.c_void_p)))
+        return _BatchPlan(h, self.models[int(ids[0])], n.value), ids
 
     def pack(self, fields):
         """Pack per-chain int8 [L_c][N_c] arrays into the group's layout (host)."""
@@ -439,6 +477,20 @@ def slq_group_weight(group: Group, s, logabs, sign, status=None, stream=None):
     _need(sign, torch.int8, (n,), "sign")
     _check(load_library().slq_group_weight(group.handle, _ptr(s), _ptr(logabs), _ptr(sign), _ptr(status),
                                             _stream(stream)))
+
+
+def slq_group_cumulative_step(group: Group, effs, eff_sweeps: int, seed: int, step: int, s, logabs, sign,
+                              accepted=None, logA=None, status=None, stream=None):
+    n = len(group.models)
+    _need(s, torch.int8, (int(group.s_off[-1]),), "s")
+    _need(logabs, torch.float64, (n,), "logabs")
+    _need(sign, torch.int8, (n,), "sign")
+    if len(effs) != group.n_batches:
+        raise SlqError("one effective model per batch is required")
+    arr = (C.c_void_p * len(effs))(*[e.handle for e in effs])
+    _check(load_library().slq_group_cumulative_step(group.handle, arr, int(eff_sweeps), int(seed), int(step),
+                                                     _ptr(s), _ptr(logabs), _ptr(sign), _ptr(accepted), _ptr(logA),
+                                                     _ptr(status), _stream(stream)))
 
 
 def slq_group_green(group: Group, s, G, logabs, sign, status=None, stream=None):

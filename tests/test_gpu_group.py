@@ -103,3 +103,81 @@ def test_lengths_off_the_block_grid_get_their_own_batch(slq):
         assert abs(la0[c] - ref_la) < 1e-12 * max(1.0, abs(ref_la)), (c, la0[c], ref_la)
         assert np.max(np.abs(Gc - ref_G)) < 1e-10, c
     grp.close()
+
+
+def test_group_cumulative_steps_match_the_oracle(slq):
+    """Cumulative updates (Eq. 4) of chains of two models in one call, each
+    batch with its own effective model: every decision, field and weight
+    against the oracle, chain by chain, over three updates."""
+    from oracle import effective, philox
+    from slq_inputs import Model
+    from tests.gpu_util import dev, host
+    seed = 0x6A0
+    a = Model(4, 4, 8, t=1.0, mu=-0.3, dtau=0.1, xi=1.2, n_stab=4)
+    b = Model(6, 4, 10, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=5)
+    models = [a, b, a, b, a]
+    terms = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    lams = {(a.lx, a.ly, a.n_slices): np.array([-0.40, 0.02, 0.03, 0.005]),
+            (b.lx, b.ly, b.n_slices): np.array([-0.55, 0.01, 0.02, 0.004])}
+    grp = slq.Group(models, exact_batches=True)
+    assert grp.n_batches == 2
+    fields = [iid_field(m, 9100 + c) for c, m in enumerate(models)]
+    s = dev(grp.pack(fields))
+    n = len(models)
+    la = torch.empty(n, dtype=torch.float64, device="cuda")
+    sg = torch.empty(n, dtype=torch.int8, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    slq.slq_group_weight(grp, s, la, sg, st)
+    effs, chain_of = [], {}
+    base = 0
+    for k in range(grp.n_batches):
+        plan, ids = grp.batch(k)
+        m = models[int(ids[0])]
+        effs.append(slq.Eff(plan, terms, lams[(m.lx, m.ly, m.n_slices)]))
+        for pos, c in enumerate(ids):
+            chain_of[int(c)] = base + pos
+        base += len(ids)
+    ref_s = [f.copy() for f in fields]
+    ref_w = [stable.weight(m, f) for m, f in zip(models, fields)]
+    acc = torch.empty(n, dtype=torch.int8, device="cuda")
+    logA = torch.empty(n, dtype=torch.float64, device="cuda")
+    sweeps = 2
+    for step in range(3):
+        slq.slq_group_cumulative_step(grp, effs, sweeps, seed, step, s, la, sg, acc, logA, st)
+        gs, gla, gsg, gacc, glogA, gst = host(s), host(la), host(sg), host(acc), host(logA), host(st)
+        for c, m in enumerate(models):
+            lam = lams[(m.lx, m.ly, m.n_slices)]
+            classes = effective.colour_classes(m, terms)
+            ref_s[c], lw, sgn, ok, la_ref = effective.cumulative_step(
+                m, terms, 0.0, lam, ref_s[c], ref_w[c][0], ref_w[c][1], sweeps * len(classes),
+                lambda x, m=m: stable.weight(m, x), seed=seed, step=step, chain=chain_of[c], classes=classes)
+            ref_w[c] = (lw, sgn)
+            u = philox.uniform((0, 0, step, chain_of[c]), (seed, philox.TAG_CUMULATIVE))
+            if abs(np.log(u) - min(0.0, la_ref)) < 1e-8:
+                pytest.skip("near-tie draw")
+            assert gst[c] == 0
+            assert bool(gacc[c]) == ok and abs(glogA[c] - la_ref) < 1e-9 * max(1.0, abs(la_ref))
+            got = gs[int(grp.s_off[c]):int(grp.s_off[c + 1])].reshape(m.n_slices, m.n_sites)
+            assert np.array_equal(got, ref_s[c])
+            assert gsg[c] == sgn and abs(gla[c] - lw) < 1e-10 * max(1.0, abs(lw))
+    for e in effs:
+        e.close()
+    grp.close()
+
+
+def test_group_cumulative_step_refuses_merged_lengths(slq):
+    from slq_inputs import Model
+    a = Model(4, 4, 8, n_stab=4)
+    b = Model(4, 4, 16, n_stab=4)      # the same lattice, two blocks longer: merged by default
+    grp = slq.Group([a, b])
+    assert grp.n_batches == 1
+    plan, _ = grp.batch(0)
+    eff = slq.Eff(plan, [(0, 0), (1, 0)], np.array([-0.4, 0.02]))
+    n = 2
+    s = torch.ones(int(grp.s_off[-1]), dtype=torch.int8, device="cuda")
+    la = torch.zeros(n, dtype=torch.float64, device="cuda")
+    sg = torch.ones(n, dtype=torch.int8, device="cuda")
+    with pytest.raises(RuntimeError, match="EXACT_BATCHES"):
+        slq.slq_group_cumulative_step(grp, [eff], 1, 1, 0, s, la, sg)
+    eff.close()
+    grp.close()
