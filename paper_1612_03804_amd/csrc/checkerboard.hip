@@ -15,8 +15,8 @@
 // circulant lines.
 //
 // A workgroup applies a block of slices to nb vectors (columns, or rows, of
-// one N x N matrix).  A thread holds, in registers, the P x P sites of QP
-// plaquettes (x0, y0 multiples of P) of one vector: the A and C bonds,
+// one N x N matrix).  A thread holds, in registers, the P x P sites of a
+// plaquette (x0, y0 multiples of P) of one vector: the A and C bonds,
 // and the B and D bonds inside a plaquette, are register-local; only the B
 // bond across the right edge and the D bond across the lower edge need the
 // neighbouring plaquette, and both threads of such a bond evaluate it from
@@ -62,8 +62,9 @@ __device__ __forceinline__ void cb_rot(double& u, double& w, double c, double s)
 __host__ __device__ inline int cb_area(int N, int P, int nb) { return 2 * (N / P) * nb; }
 
 // P x P plaquettes (P = 4 when both sides are multiples of 4, else 2), QP of
-// them per thread, NB vectors per workgroup, all compile-time so that every
-// register index and every LDS offset of an edge is a constant.
+// them per thread (the launcher uses one), NB vectors per workgroup, all
+// compile-time so that every register index and every LDS offset of an edge
+// is a constant.
 template <int P, int QP, int NB>
 __global__ __launch_bounds__(QP >= 2 ? 512 : 1024) void k_cb(CbDev a) {
   extern __shared__ double S[];  // two exchange areas [npl][2 edges][P][NB], then one partial norm per thread
@@ -267,28 +268,23 @@ __global__ __launch_bounds__(QP >= 2 ? 512 : 1024) void k_cb(CbDev a) {
 
 static int cb_side(const Plan& p) { return p.m.lx % 4 == 0 && p.m.ly % 4 == 0 ? 4 : 2; }
 
-// Plaquettes per thread for nb vectors (1, or 2 with at most 512 threads:
-// twice the registers) and the threads of a workgroup, or 0 when neither fits.
-static int cb_qp(const Plan& p, int nb, int* threads) {
+// Threads of a workgroup for nb vectors, one plaquette of one vector each,
+// or 0 when they exceed 1024 (a second plaquette per thread would halve the
+// threads but not the work per CU: the widths that need it are not admitted).
+static int cb_threads(const Plan& p, int nb) {
   const int P = cb_side(p), npl = p.n / (P * P);
-  for (int qp = 1; qp <= 2; ++qp) {
-    const int nt = ((npl + qp - 1) / qp * nb + 63) / 64 * 64;
-    if (nt <= (qp == 1 ? 1024 : 512)) {
-      if (threads) *threads = nt;
-      return qp;
-    }
-  }
-  return 0;
+  const int nt = (npl * nb + 63) / 64 * 64;
+  return nt <= 1024 ? nt : 0;
 }
 
 static size_t cb_lds(const Plan& p, int nb) {
-  int nt = 0;
-  if (!cb_qp(p, nb, &nt)) return SIZE_MAX;
+  const int nt = cb_threads(p, nb);
+  if (!nt) return SIZE_MAX;
   return ((size_t)2 * cb_area(p.n, cb_side(p), nb) + nt) * sizeof(double);
 }
 
 bool cb_width_ok(const Plan& p, int nb) {
-  return nb >= 1 && nb <= 16 && (nb & (nb - 1)) == 0 && cb_qp(p, nb, nullptr) > 0 && cb_lds(p, nb) <= 160 * 1024;
+  return nb >= 1 && nb <= 16 && (nb & (nb - 1)) == 0 && cb_threads(p, nb) > 0 && cb_lds(p, nb) <= 160 * 1024;
 }
 
 int cb_default_nb(const Plan& p) {
@@ -297,8 +293,9 @@ int cb_default_nb(const Plan& p) {
   return 1;
 }
 
-template <int P, int QP>
-static void launch_qp(const CbDev& d, int nb, dim3 grid, int threads, size_t lds, hipStream_t st) {
+template <int P>
+static void launch_p(const CbDev& d, int nb, dim3 grid, int threads, size_t lds, hipStream_t st) {
+  constexpr int QP = 1;
   switch (nb) {
 #define SLQ_CB_CASE(NB)                                    \
   case NB:                                                 \
@@ -321,8 +318,7 @@ int launch_cb(Plan& p, const KronArgs& a, hipStream_t st) {
     set_error("checkerboard slice product: vectors per workgroup must be a power of two <= 16 that fits");
     return SLQ_ERR_ARG;
   }
-  int threads = 0;
-  const int qp = cb_qp(p, nb, &threads);
+  const int threads = cb_threads(p, nb);
   const int P = cb_side(p);
   CbDev d;
   d.lx = p.m.lx;
@@ -361,17 +357,10 @@ int launch_cb(Plan& p, const KronArgs& a, hipStream_t st) {
   const size_t lds = cb_lds(p, nb);
   const long gq = 8L * kron_group(nb);
   dim3 grid((unsigned)(((long)d.nvb * a.batch + gq - 1) / gq * gq));
-  if (P == 4) {
-    if (qp == 1)
-      launch_qp<4, 1>(d, nb, grid, threads, lds, st);
-    else
-      launch_qp<4, 2>(d, nb, grid, threads, lds, st);
-  } else {
-    if (qp == 1)
-      launch_qp<2, 1>(d, nb, grid, threads, lds, st);
-    else
-      launch_qp<2, 2>(d, nb, grid, threads, lds, st);
-  }
+  if (P == 4)
+    launch_p<4>(d, nb, grid, threads, lds, st);
+  else
+    launch_p<2>(d, nb, grid, threads, lds, st);
   SLQ_LAUNCHED();
   return SLQ_OK;
 }
