@@ -64,6 +64,8 @@ def run_oracle_sweeps(model, field, n_sweeps, sweep0=0, chain=0):
     (Model(5, 3, 8, t=1.0, mu=-0.2, dtau=0.1, xi=1.3, n_stab=3), 2),     # N=15, L % n_stab != 0
     (Model(8, 8, 12, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=4), 1),    # N=64 > delayed-update depth
     (Model(9, 9, 14, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=4), 1),    # N=81: blocked QR, 3 stack entries
+    (Model(22, 22, 4, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=4), 1),   # N=484: delay depth 16 (LDS tables)
+    (Model(24, 24, 4, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=4), 1),   # N=576: the global-table flip kernel
 ])
 def test_local_sweeps_match_oracle(slq, model, n_sweeps):
     fields = [iid_field(model, 7000 + i) for i in range(2)]
