@@ -522,6 +522,73 @@ def precision_rates(slq, fields: int = 32):
     return {"model": "40x40, L=100", "fields": fields, **out}
 
 
+def precision_table(slq, fields: int = 256, chunk: int = 64, oracle_fields: int = 2):
+    """cfg3's error table: the 40x40, L=100 model on `fields` seeded fields,
+    half iid, half ordered domains with 10 % flips; log|W|, sign and G with
+    FP32 and BF16 chain operands against the FP64 structured chain (the
+    reference, itself checked against the oracle on `oracle_fields` of them,
+    one of each kind)."""
+    import numpy as np
+    import torch
+    from oracle import stable
+    from slq_inputs import MIXED_40x40, mixed_batch
+    dev = torch.device("cuda")
+    m = MIXED_40x40
+    N = m.n_sites
+    S = mixed_batch(m, fields, 9300)
+    kinds = np.array(["iid"] * (fields // 2) + ["domain"] * (fields - fields // 2))
+    res = {}
+    G = np.empty((fields, N, N))  # the FP64 reference's Green's functions
+    for prec in (0, 1, 2):
+        plan = slq.Plan(m, chunk, chain_prec=prec)
+        la = np.empty(fields)
+        sg = np.empty(fields, dtype=np.int8)
+        st = np.empty(fields, dtype=np.int32)
+        dG = np.empty(fields)
+        for c0 in range(0, fields, chunk):
+            c1 = min(fields, c0 + chunk)
+            s = torch.from_numpy(S[c0:c1]).to(dev)
+            Gd = torch.empty((c1 - c0, N, N), dtype=torch.float64, device=dev)
+            lad = torch.empty(c1 - c0, dtype=torch.float64, device=dev)
+            sgd = torch.empty(c1 - c0, dtype=torch.int8, device=dev)
+            std = torch.empty(c1 - c0, dtype=torch.int32, device=dev)
+            slq.slq_green(plan, s, Gd, lad, sgd, std)
+            la[c0:c1], sg[c0:c1], st[c0:c1] = lad.cpu().numpy(), sgd.cpu().numpy(), std.cpu().numpy()
+            if prec == 0:
+                G[c0:c1] = Gd.cpu().numpy()
+            else:
+                dG[c0:c1] = (Gd - torch.from_numpy(G[c0:c1]).to(dev)).abs().amax(dim=(1, 2)).cpu().numpy()
+            del Gd
+        plan.close()
+        torch.cuda.empty_cache()
+        res[prec] = (la, sg, st, dG)
+        print(f"# precision table: chain precision {prec} done", file=sys.stderr, flush=True)
+    la0, sg0 = res[0][0], res[0][1]
+    out = {"model": "40x40, L=100, beta=10, xi=1.5, mu=-0.5", "fields": fields,
+           "reference": "FP64 structured chain on the GPU", "status_ok": True}
+    for prec, name in ((1, "fp32"), (2, "bf16")):
+        la, sg, st, dG = res[prec]
+        rel = np.abs(la - la0) / np.abs(la0)
+        row = {}
+        for kind in ("iid", "domain"):
+            k = kinds == kind
+            row[kind] = {"max_rel_dlogW": float(rel[k].max()), "median_rel_dlogW": float(np.median(rel[k])),
+                         "max_abs_dG": float(dG[k].max()), "median_abs_dG": float(np.median(dG[k])),
+                         "signs_agree": bool((sg[k] == sg0[k]).all())}
+        out[name] = row
+        out["status_ok"] = out["status_ok"] and bool((st == 0).all())
+    checks = []
+    for idx in (0, fields - 1)[:oracle_fields]:
+        t0 = time.perf_counter()
+        rl, rs, rg = stable.green(m, S[idx])
+        checks.append({"field": int(idx), "kind": str(kinds[idx]), "oracle_seconds": time.perf_counter() - t0,
+                       "fp64_rel_dlogW": float(abs(la0[idx] - rl) / abs(rl)),
+                       "fp64_max_abs_dG": float(np.max(np.abs(G[idx] - rg))),
+                       "signs_agree": bool(sg0[idx] == rs)})
+    out["fp64_vs_oracle"] = checks
+    return out
+
+
 def group_rate(slq, dev, reps: int = 5):
     """Exact weights of 64 chains of uneven size (Lx = Ly in {8..24}, L in
     {40..100}) per second, one graph launch per evaluation."""
@@ -979,6 +1046,8 @@ def main():
     ap.add_argument("--learned-chains", type=int, default=256)
     ap.add_argument("--learned-seconds", type=float, default=240.0)
     ap.add_argument("--learned-eval-steps", type=int, default=10)
+    ap.add_argument("--precision-table", action="store_true",
+                    help="reduced-precision error table at 40x40, L=100 over 256 fields (own JSON line)")
     ap.add_argument("--reports", action="store_true",
                     help="print the uneven-group, precision-mode and learned-proposal reports (own JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -1025,6 +1094,9 @@ def main():
         print(json.dumps(bilayer_tau(slq, sizes, args.bilayer_chains, args.bilayer_sweeps, args.bilayer_steps,
                                      args.bilayer_burn, 40, args.bilayer_eff_sweeps, args.bilayer_sl_burn)),
               flush=True)
+        return
+    if args.precision_table:
+        print(json.dumps(precision_table(slq)), flush=True)
         return
     if args.learned_train:
         print(json.dumps(learned_48x48_train(slq, args.learned_chains, args.learned_train, args.learned_seconds,
