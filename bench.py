@@ -895,8 +895,8 @@ def bilayer_tau(slq, sizes, chains, sweeps, steps, burn, train_sweeps, eff_sweep
     local-update DQMC chains (`burn` sweeps, then `sweeps` sweeps recording the
     total magnetisation M), and as many SLDQMC chains started from the DQMC end
     configurations making `steps` cumulative updates of `eff_sweeps` effective
-    sweeps each (the paper: about tau_L sweeps of local updates of the
-    effective model per cumulative update), with the effective model fitted
+    sweeps each (the paper makes roughly tau_L effective sweeps per
+    cumulative update), with the effective model fitted
     once at the smallest size (as the
     paper fits at L = 8 and reuses it) on DQMC configurations and their exact
     weights.  tau_int of M per sweep and per cumulative update, <M^2> and the

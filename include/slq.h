@@ -520,8 +520,8 @@ int slq_fit_effective(slq_plan* plan, const slq_eff* eff, int64_t n_samples,
  * sign-free weight
  *   omega(s) = phi(s) [W_f(s) W_f(-s)]^2,
  * W_f the single-flavour determinant of this header (two of the four flavours
- * see xi s, two -xi s), and phi the weight of the Ising spins alone (Eq. 1's
- * bare part), from the quantum-to-classical mapping of H_s:
+ * see xi s, two -xi s), and phi the weight of the Ising spins alone (the
+ * factor of Eq. 1 without fermions), from the quantum-to-classical mapping of H_s:
  *   ln phi = dtau J sum_l sum_<ij> s_{i,l} s_{j,l} + K_tau sum_{i,l} s_{i,l} s_{i,l+1},
  *   K_tau = -1/2 ln tanh(dtau h)   (up to a constant; bonds as in K).
  * Every call evaluates 2 batch fields [s ; -s], so the plan's max_batch must

@@ -18,7 +18,7 @@ flavours have each, so
 
     omega(s) = phi(s) [W_f(s) W_f(-s)]^2 >= 0        (no sign problem).
 
-phi is the weight of the Ising spins alone (the "bare part" of Eq. 1): the
+phi is the weight of the Ising spins alone (Eq. 1's fermion-free factor): the
 standard quantum-to-classical mapping of H_s = -J sum_<ij> s^z s^z
 - h sum_i s^x with slices of width dtau gives, up to a constant factor
 (sqrt(sinh(2 dtau h) / 2) per site and slice),

@@ -1,7 +1,8 @@
 """Checkerboard (sparse) form of the kinetic factor of a slice matrix.
 
-"Formalism of SLDQMC" counts the chain of a cumulative update as beta N^2
-because each B^tau is a product of O(N) sparse matrices.  On an lx x ly torus
+"Formalism of SLDQMC" counts the chain of a cumulative update as beta N^2,
+which presumes slice matrices that factor into sparse pieces whose number
+grows like N.  On an lx x ly torus
 with even sides the nearest-neighbour bonds split into four groups of
 disjoint bonds: x bonds leaving an even x (A), leaving an odd x (B), y bonds
 leaving an even y (C), leaving an odd y (D).  The hopping of one group,

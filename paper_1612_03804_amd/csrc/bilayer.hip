@@ -7,7 +7,7 @@
 //     omega(s) = phi(s) [W_f(s) W_f(-s)]^2  (sign-free),
 //     ln phi  = dtau J sum_l sum_<ij> s_{i,l} s_{j,l} + K_tau sum_{i,l} s_{i,l} s_{i,l+1},
 //     K_tau   = -1/2 ln tanh(dtau h),
-// phi being the weight of the Ising spins alone (Eq. 1's bare part; the
+// phi being the weight of the Ising spins alone (Eq. 1's fermion-free factor; the
 // quantum-to-classical mapping of H_s, bonds counted as in the hopping
 // matrix).  Every evaluation runs the single-flavour path on the 2B fields
 // [s ; -s]; a local flip changes both determinants, so the local update keeps

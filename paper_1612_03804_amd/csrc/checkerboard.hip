@@ -1,7 +1,7 @@
 // Checkerboard slice products (SLQ_PREC_CHECKERBOARD).
 //
 // The cost count of "Formalism of SLDQMC" (beta N^2 for the chain of a
-// cumulative update) rests on B_l being a product of O(N) sparse factors.
+// cumulative update) presumes slice matrices that factor into sparse pieces.
 // On an lx x ly torus with even sides the nearest-neighbour bonds fall into
 // four groups of disjoint bonds: x bonds leaving an even x (A) or an odd x
 // (B), y bonds leaving an even y (C) or an odd y (D).  exp(-dtau K_g) of one
