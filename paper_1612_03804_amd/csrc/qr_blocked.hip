@@ -574,53 +574,79 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
   // 32-column panels over 512 fields the one-workgroup-per-CU k_tbuild takes
   // 7.8 ms per evaluation, the products less)
   constexpr bool GRAM_T = NB <= 8;
+  // With narrow panels a third level: mid blocks of NBM columns.  A panel's
+  // reflectors update only the rest of its mid block; after the mid block its
+  // combined factor T_mid (the same recursion over its own Gram matrix, on
+  // T_O's diagonal) updates the rest of the outer block as one rank-NBM
+  // product, so the outer block's columns are read and written a quarter as
+  // often by the narrow updates.
+  constexpr int NBM = 32;
+  auto gram = [&](int w, int row0, const double* V0) -> int {  // Gb = V0^T V0 over rows row0..N-1
+    GemmArgs gg{};
+    gg.M = w;
+    gg.N = w;
+    gg.K = N - row0;
+    gg.A = V0;
+    gg.lda = N;
+    gg.strideA = NN;
+    gg.B = V0;
+    gg.ldb = N;
+    gg.strideB = NN;
+    gg.C = Gb;
+    gg.ldc = NBO;
+    gg.strideC = sW;
+    gg.alpha = 1.0;
+    gg.beta = 0.0;
+    gg.batch = batch;
+    gg.cfg = GEMM_32x64;
+    return launch_gemm(gg, true, false, st);
+  };
+  auto tbuild = [&](int w, double* Tsub) -> int {
+    const size_t tl = sizeof(double) * ((size_t)QR_NBO * TB_LT + QR_NBO * TB_CH);
+    allow_max_lds((const void*)k_tbuild);
+    k_tbuild<<<batch, TB_THREADS, tl, st>>>(w, NB, Tsub, sW, Gb, sW);
+    SLQ_LAUNCHED();
+    return SLQ_OK;
+  };
   const int rr = N % NBO;  // width of the short first block (0: none)
   auto bstart = [&](int ob) { return rr == 0 ? ob * NBO : (ob == 0 ? 0 : rr + (ob - 1) * NBO); };
   auto bwidth = [&](int ob) { return rr == 0 ? NBO : (ob == 0 ? rr : NBO); };
   for (int ob = 0; ob < nout; ++ob) {
     const int J0 = bstart(ob), wo = bwidth(ob);
     double* Tb = TO + ob * sT;
-    for (int j0 = J0; j0 < J0 + wo; j0 += NB) {
-      const int nbw = std::min(NB, J0 + wo - j0), m = N - j0, sft = j0 - J0;
-      double* Tp = Tb + (long)sft * NBO + sft;
-      PanelArgs a{N, j0, nbw, p.W, Vbuf, J0, Tp, sW, NBO, wo - sft, o.D, p.invD, o.nref, status};
-      const size_t lds = sizeof(double) * ((size_t)NB * 65 + 2 * 64 * RPL + 2 * NB * (NB + 1) + NB);
-      constexpr bool CACHE = PanelShape<NB, RPL>::CACHE;
-      allow_max_lds((const void*)k_panel<NB, RPL, CACHE, TH>);
-      k_panel<NB, RPL, CACHE, TH><<<batch, TH, lds, st>>>(a);
-      SLQ_LAUNCHED();
-      const int nin = wo - sft - nbw;  // rest of the outer block
-      if (nin > 0) SLQ_TRY(apply(Vbuf + (long)j0 * N + j0, Tp, nbw, p.W + (long)j0 * N + j0 + nbw, m, nin, true));
-      if (!GRAM_T && sft > 0) {  // T_O[0:sft, sft:sft+nbw] = -T_O[0:sft, 0:sft] (V_A^T V_B) T_B, rows j0.. only
-        SLQ_TRY(gemm(sft, nbw, m, Vbuf + (long)j0 * N + J0, N, NN, true, Vbuf + (long)j0 * N + j0, N, NN, Gb, NBO,
-                     sW, 1.0, 0.0));
-        SLQ_TRY(gemm(sft, nbw, nbw, Gb, NBO, sW, false, Tp, NBO, sW, Wt2, N, sW, 1.0, 0.0));
-        SLQ_TRY(gemm(sft, nbw, sft, Tb, NBO, sW, false, Wt2, N, sW, Tb + sft, NBO, sW, -1.0, 0.0));
+    const int wmid = GRAM_T && wo > NBM ? NBM : wo;  // mid-block width (the whole block: two levels)
+    for (int jm0 = J0; jm0 < J0 + wo; jm0 += wmid) {
+      const int wm = std::min(wmid, J0 + wo - jm0), sftm = jm0 - J0;
+      for (int j0 = jm0; j0 < jm0 + wm; j0 += NB) {
+        const int nbw = std::min(NB, jm0 + wm - j0), m = N - j0, sft = j0 - J0;
+        double* Tp = Tb + (long)sft * NBO + sft;
+        PanelArgs a{N, j0, nbw, p.W, Vbuf, J0, Tp, sW, NBO, wo - sft, o.D, p.invD, o.nref, status};
+        const size_t lds = sizeof(double) * ((size_t)NB * 65 + 2 * 64 * RPL + 2 * NB * (NB + 1) + NB);
+        constexpr bool CACHE = PanelShape<NB, RPL>::CACHE;
+        allow_max_lds((const void*)k_panel<NB, RPL, CACHE, TH>);
+        k_panel<NB, RPL, CACHE, TH><<<batch, TH, lds, st>>>(a);
+        SLQ_LAUNCHED();
+        const int nin = jm0 + wm - j0 - nbw;  // rest of the mid block
+        if (nin > 0) SLQ_TRY(apply(Vbuf + (long)j0 * N + j0, Tp, nbw, p.W + (long)j0 * N + j0 + nbw, m, nin, true));
+        if (!GRAM_T && sft > 0) {  // T_O[0:sft, sft:sft+nbw] = -T_O[0:sft, 0:sft] (V_A^T V_B) T_B, rows j0.. only
+          SLQ_TRY(gemm(sft, nbw, m, Vbuf + (long)j0 * N + J0, N, NN, true, Vbuf + (long)j0 * N + j0, N, NN, Gb,
+                       NBO, sW, 1.0, 0.0));
+          SLQ_TRY(gemm(sft, nbw, nbw, Gb, NBO, sW, false, Tp, NBO, sW, Wt2, N, sW, 1.0, 0.0));
+          SLQ_TRY(gemm(sft, nbw, sft, Tb, NBO, sW, false, Wt2, N, sW, Tb + sft, NBO, sW, -1.0, 0.0));
+        }
+      }
+      const int rest = J0 + wo - jm0 - wm;  // columns of the outer block after this mid block
+      if (wm < wo && rest > 0) {
+        double* Tm = Tb + (long)sftm * NBO + sftm;
+        const double* Vm = Vbuf + (long)jm0 * N + jm0;
+        SLQ_TRY(gram(wm, jm0, Vm));
+        SLQ_TRY(tbuild(wm, Tm));
+        SLQ_TRY(apply(Vm, Tm, wm, p.W + (long)jm0 * N + jm0 + wm, N - jm0, rest, true));
       }
     }
     if (GRAM_T && wo > NB) {  // T_O of the whole block from its Gram matrix (rows J0.. of V_O)
-      GemmArgs gg{};
-      gg.M = wo;
-      gg.N = wo;
-      gg.K = N - J0;
-      gg.A = Vbuf + (long)J0 * N + J0;
-      gg.lda = N;
-      gg.strideA = NN;
-      gg.B = gg.A;
-      gg.ldb = N;
-      gg.strideB = NN;
-      gg.C = Gb;
-      gg.ldc = NBO;
-      gg.strideC = sW;
-      gg.alpha = 1.0;
-      gg.beta = 0.0;
-      gg.batch = batch;
-      gg.cfg = GEMM_32x64;
-      SLQ_TRY(launch_gemm(gg, true, false, st));
-      const size_t tl = sizeof(double) * ((size_t)QR_NBO * TB_LT + QR_NBO * TB_CH);
-      allow_max_lds((const void*)k_tbuild);
-      k_tbuild<<<batch, TB_THREADS, tl, st>>>(wo, NB, Tb, sW, Gb, sW);
-      SLQ_LAUNCHED();
+      SLQ_TRY(gram(wo, J0, Vbuf + (long)J0 * N + J0));
+      SLQ_TRY(tbuild(wo, Tb));
     }
     if (J0 + wo < N)
       SLQ_TRY(apply(Vbuf + (long)J0 * N + J0, Tb, wo, p.W + (long)J0 * N + J0 + wo, N - J0, N - J0 - wo, true));
