@@ -271,3 +271,25 @@ def test_48x48_L100_parity(slq):
     f = iid_field(m, 6100)
     G, la, sg, st = gpu_green(slq, m, [f])
     check_parity(m, [f], G, la, sg, st)
+
+
+def test_largest_lattice_matches_the_oracle(slq):
+    """The largest admitted lattice, 60x40 (N = 2400: 64-point generic lines,
+    a 96-column first QR block of three mid blocks), against the oracle on one
+    field; and an empty batch is a no-op."""
+    from tests.gpu_util import dev
+    m = Model(60, 40, 10, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=5)
+    f = iid_field(m, 6200)
+    G, la, sg, st = gpu_green(slq, m, [f])
+    check_parity(m, [f], G, la, sg, st)
+    plan = slq.Plan(m, 1)
+    s = dev(iid_fields(m, 1, 6201))[:0]
+    la0 = torch.empty(0, dtype=torch.float64, device="cuda")
+    sg0 = torch.empty(0, dtype=torch.int8, device="cuda")
+    slq.slq_weight(plan, s, la0, sg0)
+    plan.close()
+
+
+def test_too_large_lattice_is_refused(slq):
+    with pytest.raises(slq.SlqError, match="2400"):
+        slq.Plan(Model(50, 50, 4), 1)
