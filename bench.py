@@ -902,8 +902,9 @@ def bilayer_tau(slq, sizes, chains, sweeps, steps, burn, train_sweeps, eff_sweep
     weights.  tau_int of M per sweep and per cumulative update, <M^2> and the
     susceptibility chi = dtau^2 <M^2> / (beta^2 N) of both samplers with
     errors, wall time per sweep and per update.  tau_int is also given for |M|
-    and M^2, which the tunnelling between +M and -M does not set.  sl_burn: cumulative updates
-    before the recorded ones (default: burn)."""
+    and M^2, which the tunnelling between +M and -M does not set, and <M^2>
+    over each half of the recorded series, which shows an unfinished burn-in.
+    sl_burn: cumulative updates before the recorded ones (default: burn)."""
     import numpy as np
     import torch
     from paper_1612_03804_amd.analysis import tau_int_window, mean_and_error, agree
@@ -914,6 +915,11 @@ def bilayer_tau(slq, sizes, chains, sweeps, steps, burn, train_sweeps, eff_sweep
     out = {"workload": "bilayer (Eq. 6), beta=1, dtau=0.05, M=20, xi=1, h=2.774, J=1, t=1, mu=-0.5",
            "chains": chains, "sizes": {}}
     theta_h, terms = None, None
+
+    def halves(x):   # <M^2> over the first and the second half of the recorded series: a drift shows here
+        h = x.shape[1] // 2
+        return [mean_and_error(x[:, :h]), mean_and_error(x[:, h:])]
+
     for lin in sizes:
         m = bilayer_model(lin)
         N, L = m.n_sites, m.n_slices
@@ -953,7 +959,7 @@ def bilayer_tau(slq, sizes, chains, sweeps, steps, burn, train_sweeps, eff_sweep
                                 "tau_int_sweeps": tau_int_window(Mh),
                                 "tau_int_sweeps_absM": tau_int_window(np.abs(Mh)),
                                 "tau_int_sweeps_M2": tau_int_window(Mh ** 2), "M2": mean_and_error(Mh ** 2),
-                                "status_ok": ok_dq, "max_drift": float(drift.max().item())}}
+                                "M2_halves": halves(Mh ** 2), "status_ok": ok_dq, "max_drift": float(drift.max().item())}}
         if theta_h is None:   # fit the effective model at the smallest size (Eq. 3)
             terms = default_terms(L)
             eff0 = slq.Eff(plan, terms, np.zeros(len(terms)))
@@ -996,7 +1002,7 @@ def bilayer_tau(slq, sizes, chains, sweeps, steps, burn, train_sweeps, eff_sweep
                          "acceptance": float(acc_c.float().mean().item()), "tau_int_steps": tau_int_window(Msh),
                          "tau_int_steps_absM": tau_int_window(np.abs(Msh)),
                          "tau_int_steps_M2": tau_int_window(Msh ** 2),
-                         "M2": m2_sl, "status_ok": bool((st == 0).all().item())}
+                         "M2": m2_sl, "M2_halves": halves(Msh ** 2), "status_ok": bool((st == 0).all().item())}
         rec["chi_dqmc"] = chi(rec["dqmc"]["M2"])
         rec["chi_sldqmc"] = chi(m2_sl)
         rec["M2_agree_2sigma"] = agree(rec["dqmc"]["M2"], m2_sl)
