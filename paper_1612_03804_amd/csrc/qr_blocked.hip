@@ -450,13 +450,14 @@ struct PanelShape {
 // and the Gram matrix S = V_O^T V_O of the block's reflectors:
 //     T_O[0:s, P] = -T_O[0:s, 0:s] S[0:s, P] T_P,  s = first column of panel P,
 // panel by panel (the usual recursive form of T_O = [[T_A, -T_A V_A^T V_B T_B],
-// [0, T_B]]).  One workgroup per field; T_O is built in LDS and written back.
+// [0, T_B]]).  One workgroup per field; T_O is built in LDS and written back
+// (blocks of at most QR_NBO columns).
 constexpr int TB_THREADS = 256;
 constexpr int TB_LT = QR_NBO + 1;  // padded row stride of T in LDS
 constexpr int TB_CH = 8;           // columns of a panel per step
 
-__global__ __launch_bounds__(TB_THREADS) void k_tbuild(int wo, int nb, double* __restrict__ TOall, long strideT,
-                                                       const double* __restrict__ Sall, long strideS) {
+__global__ __launch_bounds__(TB_THREADS) void k_tbuild(int wo, int nb, double* __restrict__ TOall, long strideT, int ldt,
+                                                       const double* __restrict__ Sall, long strideS, int lds_) {
   extern __shared__ double lds[];
   double* T = lds;                    // [QR_NBO][TB_LT]
   double* Y = T + QR_NBO * TB_LT;     // [QR_NBO][TB_CH]
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tbuild(int wo, int nb, double* _
   // the panels' diagonal blocks, zeros elsewhere
   for (int e = tid; e < wo * wo; e += TB_THREADS) {
     const int i = e / wo, j = e % wo;
-    T[i * TB_LT + j] = (i / nb == j / nb && i <= j) ? Tg[(long)i * QR_NBO + j] : 0.0;
+    T[i * TB_LT + j] = (i / nb == j / nb && i <= j) ? Tg[(long)i * ldt + j] : 0.0;
   }
   __syncthreads();
   for (int s0 = nb; s0 < wo; s0 += nb) {
@@ -478,7 +479,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tbuild(int wo, int nb, double* _
       for (int e = tid; e < s0 * nc; e += TB_THREADS) {
         const int k = e / nc, c = e % nc;
         double y = 0.0;
-        for (int d = 0; d <= c0 + c; ++d) y += S[(long)k * QR_NBO + s0 + d] * T[(s0 + d) * TB_LT + s0 + c0 + c];
+        for (int d = 0; d <= c0 + c; ++d) y += S[(long)k * lds_ + s0 + d] * T[(s0 + d) * TB_LT + s0 + c0 + c];
         Y[k * TB_CH + c] = y;
       }
       __syncthreads();
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tbuild(int wo, int nb, double* _
   }
   for (int e = tid; e < wo * wo; e += TB_THREADS) {
     const int i = e / wo, j = e % wo;
-    Tg[(long)i * QR_NBO + j] = T[i * TB_LT + j];
+    Tg[(long)i * ldt + j] = T[i * TB_LT + j];
   }
 }
 
@@ -502,31 +503,41 @@ __global__ void k_zero_i32(int32_t* x, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = 0;
 }
 
-// Two levels: panels of NB columns inside outer blocks of QR_NBO columns.  A
-// panel's reflectors update the rest of its outer block at once; the
-// trailing columns beyond the block, and later Q, are updated once per outer
+// Blocking: panels of NB columns inside outer blocks of NBOT columns.  A
+// panel's reflectors update the rest of its block at once; the trailing
+// columns beyond the outer block, and later Q, are updated once per outer
 // block with its combined compact-WY factor
 //     T_O = [[T_A, -T_A (V_A^T V_B) T_B], [0, T_B]]
-// built panel by panel, so the large blocks are read and written a quarter
-// as often as with one level.  When QR_NBO does not divide N the short block
-// comes first: every later block then starts QR_NBO-aligned from the end, so
-// the large updates have row and column counts that are multiples of the
-// 128 x 64 tiles (N = 400: 384 x 256 and 256 x 128 instead of 400 x 272 and
-// 272 x 144).
-template <int NB, int RPL, int TH = PQ_THREADS>
+// so the large blocks are read and written once per NBOT columns.  When NBOT
+// does not divide N the short block comes first: every later block then
+// starts NBOT-aligned from the end, so the large updates have row and column
+// counts that are multiples of the 128 x 64 tiles (N = 400: 384 x 256 and
+// 256 x 128 instead of 400 x 272 and 272 x 144).
+//
+// With narrow panels (NB <= 8, large N) there are two more levels: mid
+// blocks of NBM columns inside sub-blocks of at most QR_NBO columns inside the
+// outer block.  A panel updates only the rest of its mid block; a mid block,
+// with its factor T_mid, the rest of its sub-block (rank NBM); a sub-block,
+// with T_sub, the rest of the outer block (rank QR_NBO); the outer block the
+// trailing matrix (rank NBOT).  T_mid and T_sub come from the Gram matrix of
+// their reflectors and the panels' T (k_tbuild); T_O of two sub-blocks from
+// the formula above, with V_A^T V_B over the rows of V_B and two small
+// products.  Each level reads and writes the columns to its right a quarter
+// (half, for the outer level) as often as the level below would.
+template <int NB, int RPL, int NBOT, int TH = PQ_THREADS>
 static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st,
                        const double* norm2, bool form_q) {
+  static_assert(NBOT == QR_NBO || NBOT == 2 * QR_NBO, "an outer block holds one or two sub-blocks");
   const int N = p.n;
   const long NN = (long)N * N;
-  constexpr int NBO = QR_NBO;
-  const int nout = (N + NBO - 1) / NBO;
+  const int nout = (N + NBOT - 1) / NBOT;
   double* Vbuf = (X == p.Xa) ? p.Xb : p.Xa;  // free once W holds the pivoted copy of X
   const long sW = qr_workspace_per_field(N);
-  const long sT = (long)NBO * NBO;
-  double* TO = p.qrws;               // [b]: [nout][NBO][NBO] outer factors
-  double* Gb = TO + nout * sT;       // [NBO][NBO] Gram blocks
-  double* Wt = Gb + sT;              // [NBO][N]
-  double* Wt2 = Wt + (long)NBO * N;  // [NBO][N]
+  const long sT = (long)NBOT * NBOT;
+  double* TO = p.qrws;                   // [b]: [nout][NBOT][NBOT] outer factors
+  double* Gb = TO + nout * sT;           // [QR_NBO][QR_NBO] Gram blocks
+  double* Wt = Gb + (long)QR_NBO * QR_NBO;  // [NBOT][N]
+  double* Wt2 = Wt + (long)NBOT * N;     // [NBOT][N]
   const size_t lpp = sizeof(double) * N + sizeof(int) * N;
   allow_max_lds((const void*)k_prepivot);
   k_prepivot<<<batch, PQ_THREADS, lpp, st>>>(N, X, p.W, o.D, p.perm, status, norm2);
@@ -560,26 +571,20 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     g.batch = batch;
     return launch_gemm(g, ta, false, st);
   };
-  // B <- B - V op(T) (V^T B): V m x k (ld N), T k x k (ld NBO), B m x n (ld N)
+  // B <- B - V op(T) (V^T B): V m x k (ld N), T k x k (ld NBOT), B m x n (ld N)
   auto apply = [&](const double* Vp, const double* Tp, int k, double* Bp, int m, int n, bool transT) -> int {
     int rc = gemm(k, n, m, Vp, N, NN, true, Bp, N, NN, Wt, N, sW, 1.0, 0.0);
-    if (rc == SLQ_OK) rc = gemm(k, n, k, Tp, NBO, sW, transT, Wt, N, sW, Wt2, N, sW, 1.0, 0.0);
+    if (rc == SLQ_OK) rc = gemm(k, n, k, Tp, NBOT, sW, transT, Wt, N, sW, Wt2, N, sW, 1.0, 0.0);
     if (rc == SLQ_OK) rc = gemm(m, n, k, Vp, N, NN, false, Wt2, N, sW, Bp, N, NN, -1.0, 1.0);
     return rc;
   };
-  // How T_O grows panel by panel: with narrow panels (many per block) from one
-  // Gram product V_O^T V_O and k_tbuild after the block's panels (at N = 2304,
-  // 8-column panels: 36 ms per 64-field evaluation against 150 ms of thin
-  // products), with wide ones by three small products per panel (at N = 400,
-  // 32-column panels over 512 fields the one-workgroup-per-CU k_tbuild takes
-  // 7.8 ms per evaluation, the products less)
+  // How a block's T grows panel by panel: with narrow panels (many per block)
+  // from one Gram product V^T V and k_tbuild after the block's panels (at N =
+  // 2304, 8-column panels: 36 ms per 64-field evaluation against 150 ms of
+  // thin products), with wide ones by three small products per panel (at N =
+  // 400, 32-column panels over 512 fields the one-workgroup-per-CU k_tbuild
+  // takes 7.8 ms per evaluation, the products less)
   constexpr bool GRAM_T = NB <= 8;
-  // With narrow panels a third level: mid blocks of NBM columns.  A panel's
-  // reflectors update only the rest of its mid block; after the mid block its
-  // combined factor T_mid (the same recursion over its own Gram matrix, on
-  // T_O's diagonal) updates the rest of the outer block as one rank-NBM
-  // product, so the outer block's columns are read and written a quarter as
-  // often by the narrow updates.
   constexpr int NBM = 32;
   auto gram = [&](int w, int row0, const double* V0) -> int {  // Gb = V0^T V0 over rows row0..N-1
     GemmArgs gg{};
@@ -593,7 +598,7 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     gg.ldb = N;
     gg.strideB = NN;
     gg.C = Gb;
-    gg.ldc = NBO;
+    gg.ldc = QR_NBO;
     gg.strideC = sW;
     gg.alpha = 1.0;
     gg.beta = 0.0;
@@ -601,52 +606,69 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     gg.cfg = GEMM_32x64;
     return launch_gemm(gg, true, false, st);
   };
-  auto tbuild = [&](int w, double* Tsub) -> int {
+  auto tbuild = [&](int w, double* Tsub) -> int {  // w <= QR_NBO
     const size_t tl = sizeof(double) * ((size_t)QR_NBO * TB_LT + QR_NBO * TB_CH);
     allow_max_lds((const void*)k_tbuild);
-    k_tbuild<<<batch, TB_THREADS, tl, st>>>(w, NB, Tsub, sW, Gb, sW);
+    k_tbuild<<<batch, TB_THREADS, tl, st>>>(w, NB, Tsub, sW, NBOT, Gb, sW, QR_NBO);
     SLQ_LAUNCHED();
     return SLQ_OK;
   };
-  const int rr = N % NBO;  // width of the short first block (0: none)
-  auto bstart = [&](int ob) { return rr == 0 ? ob * NBO : (ob == 0 ? 0 : rr + (ob - 1) * NBO); };
-  auto bwidth = [&](int ob) { return rr == 0 ? NBO : (ob == 0 ? rr : NBO); };
+  // blocks of width `full` over [0, n), the short one (n mod full) first
+  auto bstart = [](int n, int full, int k) { const int r = n % full; return r == 0 ? k * full : (k == 0 ? 0 : r + (k - 1) * full); };
+  auto bwidth = [](int n, int full, int k) { const int r = n % full; return r == 0 ? full : (k == 0 ? r : full); };
   for (int ob = 0; ob < nout; ++ob) {
-    const int J0 = bstart(ob), wo = bwidth(ob);
+    const int J0 = bstart(N, NBOT, ob), wo = bwidth(N, NBOT, ob);
     double* Tb = TO + ob * sT;
-    const int wmid = GRAM_T && wo > NBM ? NBM : wo;  // mid-block width (the whole block: two levels)
-    for (int jm0 = J0; jm0 < J0 + wo; jm0 += wmid) {
-      const int wm = std::min(wmid, J0 + wo - jm0), sftm = jm0 - J0;
-      for (int j0 = jm0; j0 < jm0 + wm; j0 += NB) {
-        const int nbw = std::min(NB, jm0 + wm - j0), m = N - j0, sft = j0 - J0;
-        double* Tp = Tb + (long)sft * NBO + sft;
-        PanelArgs a{N, j0, nbw, p.W, Vbuf, J0, Tp, sW, NBO, wo - sft, o.D, p.invD, o.nref, status};
-        const size_t lds = sizeof(double) * ((size_t)NB * 65 + 2 * 64 * RPL + 2 * NB * (NB + 1) + NB);
-        constexpr bool CACHE = PanelShape<NB, RPL>::CACHE;
-        allow_max_lds((const void*)k_panel<NB, RPL, CACHE, TH>);
-        k_panel<NB, RPL, CACHE, TH><<<batch, TH, lds, st>>>(a);
-        SLQ_LAUNCHED();
-        const int nin = jm0 + wm - j0 - nbw;  // rest of the mid block
-        if (nin > 0) SLQ_TRY(apply(Vbuf + (long)j0 * N + j0, Tp, nbw, p.W + (long)j0 * N + j0 + nbw, m, nin, true));
-        if (!GRAM_T && sft > 0) {  // T_O[0:sft, sft:sft+nbw] = -T_O[0:sft, 0:sft] (V_A^T V_B) T_B, rows j0.. only
-          SLQ_TRY(gemm(sft, nbw, m, Vbuf + (long)j0 * N + J0, N, NN, true, Vbuf + (long)j0 * N + j0, N, NN, Gb,
-                       NBO, sW, 1.0, 0.0));
-          SLQ_TRY(gemm(sft, nbw, nbw, Gb, NBO, sW, false, Tp, NBO, sW, Wt2, N, sW, 1.0, 0.0));
-          SLQ_TRY(gemm(sft, nbw, sft, Tb, NBO, sW, false, Wt2, N, sW, Tb + sft, NBO, sW, -1.0, 0.0));
+    const int nsub = (wo + QR_NBO - 1) / QR_NBO;
+    for (int sb = 0; sb < nsub; ++sb) {
+      const int S0 = J0 + bstart(wo, QR_NBO, sb), ws = bwidth(wo, QR_NBO, sb);
+      const int wmid = GRAM_T && ws > NBM ? NBM : ws;  // mid-block width (the whole sub-block: two levels)
+      for (int jm0 = S0; jm0 < S0 + ws; jm0 += wmid) {
+        const int wm = std::min(wmid, S0 + ws - jm0), sftm = jm0 - J0;
+        for (int j0 = jm0; j0 < jm0 + wm; j0 += NB) {
+          const int nbw = std::min(NB, jm0 + wm - j0), m = N - j0, sft = j0 - J0;
+          double* Tp = Tb + (long)sft * NBOT + sft;
+          PanelArgs a{N, j0, nbw, p.W, Vbuf, J0, Tp, sW, NBOT, wo - sft, o.D, p.invD, o.nref, status};
+          const size_t lds = sizeof(double) * ((size_t)NB * 65 + 2 * 64 * RPL + 2 * NB * (NB + 1) + NB);
+          constexpr bool CACHE = PanelShape<NB, RPL>::CACHE;
+          allow_max_lds((const void*)k_panel<NB, RPL, CACHE, TH>);
+          k_panel<NB, RPL, CACHE, TH><<<batch, TH, lds, st>>>(a);
+          SLQ_LAUNCHED();
+          const int nin = jm0 + wm - j0 - nbw;  // rest of the mid block
+          if (nin > 0) SLQ_TRY(apply(Vbuf + (long)j0 * N + j0, Tp, nbw, p.W + (long)j0 * N + j0 + nbw, m, nin, true));
+          const int sfs = j0 - S0;
+          if (!GRAM_T && sfs > 0) {  // T_sub[0:sfs, sfs:sfs+nbw] = -T_sub[0:sfs, 0:sfs] (V_A^T V_B) T_B, rows j0.. only
+            double* Ts = Tb + (long)(S0 - J0) * (NBOT + 1);
+            SLQ_TRY(gemm(sfs, nbw, m, Vbuf + (long)j0 * N + S0, N, NN, true, Vbuf + (long)j0 * N + j0, N, NN, Gb,
+                         QR_NBO, sW, 1.0, 0.0));
+            SLQ_TRY(gemm(sfs, nbw, nbw, Gb, QR_NBO, sW, false, Tp, NBOT, sW, Wt2, N, sW, 1.0, 0.0));
+            SLQ_TRY(gemm(sfs, nbw, sfs, Ts, NBOT, sW, false, Wt2, N, sW, Ts + sfs, NBOT, sW, -1.0, 0.0));
+          }
+        }
+        const int rest = S0 + ws - jm0 - wm;  // columns of the sub-block after this mid block
+        if (wm < ws && rest > 0) {
+          double* Tm = Tb + (long)sftm * NBOT + sftm;
+          const double* Vm = Vbuf + (long)jm0 * N + jm0;
+          SLQ_TRY(gram(wm, jm0, Vm));
+          SLQ_TRY(tbuild(wm, Tm));
+          SLQ_TRY(apply(Vm, Tm, wm, p.W + (long)jm0 * N + jm0 + wm, N - jm0, rest, true));
         }
       }
-      const int rest = J0 + wo - jm0 - wm;  // columns of the outer block after this mid block
-      if (wm < wo && rest > 0) {
-        double* Tm = Tb + (long)sftm * NBO + sftm;
-        const double* Vm = Vbuf + (long)jm0 * N + jm0;
-        SLQ_TRY(gram(wm, jm0, Vm));
-        SLQ_TRY(tbuild(wm, Tm));
-        SLQ_TRY(apply(Vm, Tm, wm, p.W + (long)jm0 * N + jm0 + wm, N - jm0, rest, true));
+      if (GRAM_T && ws > NB) {  // T_sub from its Gram matrix (rows S0.. of V_sub)
+        SLQ_TRY(gram(ws, S0, Vbuf + (long)S0 * N + S0));
+        SLQ_TRY(tbuild(ws, Tb + (long)(S0 - J0) * (NBOT + 1)));
       }
+      const int rso = J0 + wo - S0 - ws;  // columns of the outer block after this sub-block
+      if (rso > 0)
+        SLQ_TRY(apply(Vbuf + (long)S0 * N + S0, Tb + (long)(S0 - J0) * (NBOT + 1), ws, p.W + (long)S0 * N + S0 + ws,
+                      N - S0, rso, true));
     }
-    if (GRAM_T && wo > NB) {  // T_O of the whole block from its Gram matrix (rows J0.. of V_O)
-      SLQ_TRY(gram(wo, J0, Vbuf + (long)J0 * N + J0));
-      SLQ_TRY(tbuild(wo, Tb));
+    if (nsub == 2) {  // T_O[0:wa, wa:wo] = -T_A (V_A^T V_B) T_B
+      const int wa = bwidth(wo, QR_NBO, 0), wb = wo - wa, SB = J0 + wa;
+      SLQ_TRY(gemm(wa, wb, N - SB, Vbuf + (long)SB * N + J0, N, NN, true, Vbuf + (long)SB * N + SB, N, NN, Gb, QR_NBO,
+                   sW, 1.0, 0.0));
+      SLQ_TRY(gemm(wa, wb, wb, Gb, QR_NBO, sW, false, Tb + (long)wa * (NBOT + 1), NBOT, sW, Wt2, N, sW, 1.0, 0.0));
+      SLQ_TRY(gemm(wa, wb, wa, Tb, NBOT, sW, false, Wt2, N, sW, Tb + wa, NBOT, sW, -1.0, 0.0));
     }
     if (J0 + wo < N)
       SLQ_TRY(apply(Vbuf + (long)J0 * N + J0, Tb, wo, p.W + (long)J0 * N + J0 + wo, N - J0, N - J0 - wo, true));
@@ -660,13 +682,13 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
   // written U[J0+wo:, J0+wo:], the rank-wo GEMMs read the rest of their C as the
   // identity's entries (zeros in rows J0..J0+wo-1 beyond the block, I on it).
   for (int ob = nout - 1; ob >= 0; --ob) {
-    const int J0 = bstart(ob), wo = bwidth(ob), m = N - J0;
+    const int J0 = bstart(N, NBOT, ob), wo = bwidth(N, NBOT, ob), m = N - J0;
     const double* Vp = Vbuf + (long)J0 * N + J0;
     double* Ub = o.U + (long)J0 * N + J0;
     if (m > wo) {  // columns beyond the block: their rows J0..J0+wo-1 are still zero
       const int n2 = m - wo;
       SLQ_TRY(gemm(wo, n2, n2, Vp + (long)wo * N, N, NN, true, Ub + (long)wo * N + wo, N, NN, Wt, N, sW, 1.0, 0.0));
-      SLQ_TRY(gemm(wo, n2, wo, TO + ob * sT, NBO, sW, false, Wt, N, sW, Wt2, N, sW, 1.0, 0.0));
+      SLQ_TRY(gemm(wo, n2, wo, TO + ob * sT, NBOT, sW, false, Wt, N, sW, Wt2, N, sW, 1.0, 0.0));
       SLQ_TRY(gemm(m, n2, wo, Vp, N, NN, false, Wt2, N, sW, Ub + wo, N, NN, -1.0, 1.0, 0, wo));
     }
     GemmArgs y{};  // Wt2 = T_O V_top^T
@@ -674,7 +696,7 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     y.N = wo;
     y.K = wo;
     y.A = TO + ob * sT;
-    y.lda = NBO;
+    y.lda = NBOT;
     y.strideA = sW;
     y.B = Vp;
     y.ldb = N;
@@ -691,18 +713,24 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
   return SLQ_OK;
 }
 
+// Outer block width by matrix size: two sub-blocks of QR_NBO columns where the
+// panels are narrow (N = 2304, 256 fields: the rank-256 trailing and Q
+// updates read and write the large blocks half as often as rank-128 ones)
+static int qr_outer_width(int N) { return N > 1152 ? 2 * QR_NBO : QR_NBO; }
+
 long qr_workspace_per_field(int N) {
-  const long nout = (N + QR_NBO - 1) / QR_NBO;
-  return (nout + 1) * QR_NBO * QR_NBO + 2L * QR_NBO * N;
+  const long nbo = qr_outer_width(N);
+  const long nout = (N + nbo - 1) / nbo;
+  return nout * nbo * nbo + (long)QR_NBO * QR_NBO + 2L * nbo * N;
 }
 
 int launch_qr_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int32_t* status, hipStream_t st,
                       const double* norm2, bool form_q) {
-  if (p.n <= 448) return run_blocked<32, 7>(p, batch, X, o, status, st, norm2, form_q);
-  if (p.n <= 1152) return run_blocked<16, 18>(p, batch, X, o, status, st, norm2, form_q);
+  if (p.n <= 448) return run_blocked<32, 7, QR_NBO>(p, batch, X, o, status, st, norm2, form_q);
+  if (p.n <= 1152) return run_blocked<16, 18, QR_NBO>(p, batch, X, o, status, st, norm2, form_q);
   // (16 columns at 38 rows per lane spill registers both as two columns per
   // wave of 512 threads and as one per wave of 1024)
-  return run_blocked<8, 38>(p, batch, X, o, status, st, norm2, form_q);
+  return run_blocked<8, 38, 2 * QR_NBO>(p, batch, X, o, status, st, norm2, form_q);
 }
 
 }  // namespace slq

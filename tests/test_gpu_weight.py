@@ -290,6 +290,25 @@ def test_largest_lattice_matches_the_oracle(slq):
     plan.close()
 
 
+def test_outer_block_of_two_unequal_sub_blocks(slq):
+    """38x38 (N = 1444): the first 256-column outer block of the QR is 164
+    columns, a 36-column sub-block and a 128-column one whose factors combine
+    into the block's T; G, the weight from the G path and the weight-only path
+    (R-only QR of M, same blocking) against the oracle on two fields."""
+    from tests.gpu_util import dev, host
+    m = Model(38, 38, 10, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=5)
+    fields = [iid_field(m, 6300), iid_field(m, 6301)]
+    G, la, sg, st = gpu_green(slq, m, fields)
+    check_parity(m, fields, G, la, sg, st)
+    plan = slq.Plan(m, 2)
+    lw = torch.empty(2, dtype=torch.float64, device="cuda")
+    sw = torch.empty(2, dtype=torch.int8, device="cuda")
+    slq.slq_weight(plan, dev(np.stack(fields)), lw, sw)
+    assert np.array_equal(host(sw), sg)
+    assert np.all(np.abs(host(lw) - la) < 1e-12 * np.abs(la))
+    plan.close()
+
+
 def test_too_large_lattice_is_refused(slq):
     with pytest.raises(slq.SlqError, match="2400"):
         slq.Plan(Model(50, 50, 4), 1)
