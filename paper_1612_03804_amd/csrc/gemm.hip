@@ -136,15 +136,22 @@ __global__ __launch_bounds__(64 * GM * GN) void k_gemm(GemmArgs g, int ntm, int 
     }
   };
 
+  // A triangular A runs K backwards, from the last K tile down to the tile's
+  // diagonal: every tile then starts at the same K, and the tiles resident
+  // together read the same rows of op(B) at about the same time (forwards,
+  // each row of tiles would start at its own diagonal and the B panels would
+  // be fetched once per row of tiles).
+  const int klast = g.K > 0 ? ((g.K - 1) / TK) * TK : 0;
+  const int kfirst = AUP ? klast : kbeg, kstep = AUP ? -TK : TK;
   if (kbeg < g.K) {
-    load(kbeg);
+    load(kfirst);
     store(0);
   }
   __syncthreads();
   int cur = 0;
-  for (int k0 = kbeg; k0 < g.K; k0 += TK) {
-    const bool more = k0 + TK < g.K;
-    if (more) load(k0 + TK);
+  for (int k0 = kfirst; kbeg < g.K && (AUP ? k0 >= kbeg : k0 < g.K); k0 += kstep) {
+    const bool more = AUP ? k0 - TK >= kbeg : k0 + TK < g.K;
+    if (more) load(k0 + kstep);
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       const int kr = ks + (lane >> 4);
@@ -248,6 +255,8 @@ int launch_gemm_cfg(const GemmArgs& a, bool ta, bool tb, int cfg, hipStream_t st
     case GEMM_128x64: return run<2, 2, 4, 2, 8>(a, ta, tb, st);
     case GEMM_16x64: return run<1, 1, 1, 4, 16>(a, ta, tb, st);
     case GEMM_128x16: return run<2, 1, 4, 1, 8>(a, ta, tb, st);
+    case GEMM_32x64_K32: return run<2, 1, 1, 4, 32>(a, ta, tb, st);
+    case GEMM_16x64_K32: return run<1, 1, 1, 4, 32>(a, ta, tb, st);
     default:
       set_error("unknown GEMM tile configuration");
       return SLQ_ERR_ARG;

@@ -544,16 +544,21 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
   SLQ_LAUNCHED();
   k_zero_i32<<<(batch + 255) / 256, 256, 0, st>>>(o.nref, batch);
   SLQ_LAUNCHED();
+  constexpr bool GRAM_T = NB <= 8;  // narrow panels: block factors from Gram products (below)
   // tiles from a sweep of these shapes on MI355X (N = 400, 256 fields): 128 x 64
   // with 8 wavefronts wherever the output has 64 rows or more, 32 x 64 with K 16
-  // for the thin products of the panels, 16 x 64 for those of a 16-column block
+  // for the thin products of the panels, 16 x 64 for those of a 16-column block.
+  // With narrow panels (N = 2304) the thin products stage K 32 deep: 298.6
+  // against 304.1 ms per stabilisation of 256 fields (at N = 400, 6.37 against
+  // 6.32 ms: K 16 stays there)
+  constexpr int THIN32 = GRAM_T ? GEMM_32x64_K32 : GEMM_32x64, THIN16 = GRAM_T ? GEMM_16x64_K32 : GEMM_16x64;
   auto gemm = [&](int M, int Nc, int K, const double* A, long lda, long sA, bool ta, const double* B, long ldb,
                   long sB, double* C, long ldc, long sC, double alpha, double beta, int c_ident = 0,
                   int c_zero_rows = 0) -> int {
     GemmArgs g{};
     g.c_ident = c_ident;
     g.c_zero_rows = c_zero_rows;
-    g.cfg = M >= 64 ? GEMM_128x64 : (M <= 16 ? GEMM_16x64 : GEMM_32x64);
+    g.cfg = M >= 64 ? GEMM_128x64 : (M <= 16 ? THIN16 : THIN32);
     g.M = M;
     g.N = Nc;
     g.K = K;
@@ -584,7 +589,6 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
   // thin products), with wide ones by three small products per panel (at N =
   // 400, 32-column panels over 512 fields the one-workgroup-per-CU k_tbuild
   // takes 7.8 ms per evaluation, the products less)
-  constexpr bool GRAM_T = NB <= 8;
   constexpr int NBM = 32;
   auto gram = [&](int w, int row0, const double* V0) -> int {  // Gb = V0^T V0 over rows row0..N-1
     GemmArgs gg{};
@@ -603,7 +607,7 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     gg.alpha = 1.0;
     gg.beta = 0.0;
     gg.batch = batch;
-    gg.cfg = GEMM_32x64;
+    gg.cfg = THIN32;
     return launch_gemm(gg, true, false, st);
   };
   auto tbuild = [&](int w, double* Tsub) -> int {  // w <= QR_NBO
@@ -706,7 +710,7 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     y.strideC = sW;
     y.alpha = 1.0;
     y.batch = batch;
-    y.cfg = GEMM_32x64;
+    y.cfg = THIN32;
     SLQ_TRY(launch_gemm(y, false, true, st));
     SLQ_TRY(gemm(m, wo, wo, Vp, N, NN, false, Wt2, N, sW, Ub, N, NN, -1.0, 1.0, 1));
   }

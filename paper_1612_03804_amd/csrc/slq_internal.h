@@ -385,6 +385,8 @@ enum GemmCfg {
   GEMM_128x64,     // 128 x 64, 8 wavefronts, K 8 (products of the blocked QR)
   GEMM_16x64,      // 16 x 64, 4 wavefronts, K 16 (16-row products)
   GEMM_128x16,     // 128 x 16, 4 wavefronts, K 8 (16-column edges)
+  GEMM_32x64_K32,  // 32 x 64, 4 wavefronts, K 32 (thin products with long K)
+  GEMM_16x64_K32,  // 16 x 64, 4 wavefronts, K 32
   GEMM_NCFG
 };
 int launch_gemm_cfg(const GemmArgs& a, bool transA, bool transB, int cfg, hipStream_t st);
