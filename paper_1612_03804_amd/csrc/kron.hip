@@ -16,10 +16,13 @@
 // line in registers; the circulant coefficients are wave-uniform (scalar
 // loads from a short window table).
 #include <algorithm>
+#include <type_traits>
 
 #include "slq_internal.h"
 
 namespace slq {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
 
 struct KronDev {
   int lx, ly, N, L;
@@ -408,6 +411,141 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) __attribute__((amdgpu_waves_p
   }
 }
 
+// 48 x 48 lattice, columns, B_l = E diag(d_l), on the matrix cores.  A vector
+// of the block is the 48 x 48 grid G[y][x] of its sites (i = x + 48 y), and
+// E diag(d) G = e^{dtau mu} Cy (diag(d) G) Cx^T with Cx = Cy = C, the
+// 48-point circulant of the y window.  Wavefront w of the workgroup owns the
+// 16-row strip s = w mod 3 of vector w / 3 and computes, with
+// v_mfma_f64_16x16x4_f64 (16 x 16 blocks, K = 48 in 12 steps of 4):
+//   T^T[:, strip] = G^T C^T[:, strip]   (the y-lines; A from the grid in LDS)
+//   G'[strip, :]  = T[strip, :] C^T     (the x-lines; A straight from the
+//                                        first product's accumulators)
+// The accumulator of block (a, s) of T^T holds, in register r of lane l,
+// T[16 s + l % 16][16 a + 4 r + l / 16], which is the A operand of K step
+// 4 a + r of the second product, so T never goes through LDS.  The B operands
+// are circulant: block (k, b) of C^T depends on (k - 4 b) mod 12 only, so the
+// twelve distinct operands stay in registers for the whole launch.
+constexpr int KM_P = 48, KM_NB = 4, KM_WAVES = 3 * KM_NB, KM_THREADS = 64 * KM_WAVES;
+constexpr int KM_N = KM_P * KM_P;
+
+__global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(6))) void k_kron_mma48(KronDev a) {
+  extern __shared__ double S[];  // [KM_NB][N] grids, then the next slice's spins [N] (bytes), then norm parts
+  int8_t* sp = (int8_t*)(S + KM_NB * KM_N);
+  double* part = (double*)(sp + KM_N);  // [KM_WAVES][KM_NB]
+  const int lin = kron_item((int)blockIdx.x, kron_group(KM_NB));
+  if (lin >= a.nvb * a.batch) return;
+  const int b = lin / a.nvb, v0 = (lin % a.nvb) * KM_NB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int vw = wave / 3, strip = wave % 3;
+  const double fmu = a.consts[a.inv ? 3 : 2];
+  const double dpos = a.consts[a.inv ? 1 : 0] * fmu, dneg = a.consts[a.inv ? 0 : 1] * fmu;
+  const bool idle = a.first_block && a.block < a.first_block[b];
+  auto spins = [&](int k) {
+    int sl = (a.slice0 + k * a.step) % a.L;
+    if (sl < 0) sl += a.L;
+    return a.s + (long)b * a.strideS + (long)sl * KM_N;
+  };
+  // the twelve B operands: F[q] = C^T[4 k + l / 16][16 b + l % 16] for (k - 4 b) mod 12 = q,
+  // i.e. c[(l % 16 - l / 16 - 4 q) mod 48], c[d] = wy[47 - d]
+  double F[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) {
+    const int d = (((lane & 15) - (lane >> 4) - 4 * q) % KM_P + KM_P) % KM_P;
+    F[q] = a.wy[KM_P - 1 - d];
+  }
+  // the block of vectors, scaled by the first slice's d (sites i, vector c fastest)
+  {
+    const double* __restrict__ in = a.in ? a.in + (long)b * a.strideIn : nullptr;
+    const int8_t* __restrict__ f0 = spins(0);
+    const bool sc = !idle && a.count > 0;
+    for (int e = tid; e < KM_N * KM_NB; e += KM_THREADS) {
+      const int i = e / KM_NB, c = e % KM_NB, j = v0 + c;
+      double v = in ? in[(long)i * KM_N + j] : (i == j ? 1.0 : 0.0);
+      if (sc) v *= f0[i] > 0 ? dpos : dneg;
+      S[c * KM_N + i] = v;
+    }
+  }
+  __syncthreads();
+  const double* G = S + vw * KM_N;
+  const int rA = lane >> 4, cA = lane & 15;
+  for (int k = 0; k < (idle ? 0 : a.count); ++k) {
+    const bool more = k + 1 < a.count;
+    int8_t nsp[KM_N / KM_THREADS];
+    if (more) {
+      const int8_t* __restrict__ f = spins(k + 1);
+#pragma unroll
+      for (int q = 0; q < KM_N / KM_THREADS; ++q) nsp[q] = f[tid + q * KM_THREADS];
+    }
+    // T^T blocks (a, strip), a = 0..2: A = G^T block (a, kk): G[4 kk + l / 16][16 a + l % 16]
+    d4_t t[3];
+#pragma unroll
+    for (int aa = 0; aa < 3; ++aa) t[aa] = d4_t{0.0, 0.0, 0.0, 0.0};
+    auto ylines = [&](auto st_) {  // the strip as a compile-time constant: F indexed statically
+      constexpr int st = decltype(st_)::value;
+#pragma unroll
+      for (int kk = 0; kk < 12; ++kk) {
+        const double* row = G + (4 * kk + rA) * KM_P + cA;
+        const int q = ((kk - 4 * st) % 12 + 12) % 12;
+#pragma unroll
+        for (int aa = 0; aa < 3; ++aa) t[aa] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * aa], F[q], t[aa], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);  // K step by K step: three operands in registers at a time
+      }
+    };
+    if (strip == 0)
+      ylines(std::integral_constant<int, 0>{});
+    else if (strip == 1)
+      ylines(std::integral_constant<int, 1>{});
+    else
+      ylines(std::integral_constant<int, 2>{});
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < KM_N / KM_THREADS; ++q) sp[tid + q * KM_THREADS] = nsp[q];
+    }
+    __syncthreads();  // every wave has read the grids; the next spins are in LDS
+    // G' blocks (strip, bj): A operand of K step kk = 4 aa + r is register r of t[aa]
+    double* Gw = S + vw * KM_N;
+#pragma unroll
+    for (int bj = 0; bj < 3; ++bj) {
+      d4_t g = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 12; ++kk) {
+        const int q = ((kk - 4 * bj) % 12 + 12) % 12;
+        g = __builtin_amdgcn_mfma_f64_16x16x4f64(t[kk >> 2][kk & 3], F[q], g, 0, 0, 0);
+      }
+      // register r of lane l: G'[16 strip + 4 r + l / 16][16 bj + l % 16], times the next slice's d
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = (16 * strip + 4 * r + rA) * KM_P + 16 * bj + cA;
+        double v = g[r];
+        if (more) v *= sp[i] > 0 ? dpos : dneg;
+        Gw[i] = v;
+      }
+      __builtin_amdgcn_sched_barrier(0);  // one output block's accumulators live at a time
+    }
+    __syncthreads();
+  }
+  // out, and the squared norms of the output columns
+  double* __restrict__ out = a.out + (long)b * a.strideOut;
+  const int c = tid % KM_NB;
+  double ss = 0.0;
+  for (int i = tid / KM_NB; i < KM_N; i += KM_THREADS / KM_NB) {
+    const double v = S[c * KM_N + i];
+    out[(long)i * KM_N + v0 + c] = v;
+    ss += v * v;
+  }
+  if (a.norm2) {  // lanes equal mod KM_NB hold parts of one column
+#pragma unroll
+    for (int o = 32; o >= KM_NB; o >>= 1) ss += __shfl_xor(ss, o, 64);
+    if (lane < KM_NB) part[wave * KM_NB + lane] = ss;
+    __syncthreads();
+    if (tid < KM_NB) {
+      double tt = 0.0;
+      for (int w = 0; w < KM_WAVES; ++w) tt += part[w * KM_NB + tid];
+      a.norm2[(long)b * KM_N + v0 + tid] = tt;
+    }
+  }
+}
+
 static const int kKronSizes[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 64};
 
 int kron_line_size(int lx, int ly) {
@@ -537,6 +675,17 @@ int launch_kron(Plan& p, const KronArgs& a, hipStream_t st) {
   d.batch = a.batch;
   d.first_block = a.first_block;
   d.block = a.block;
+  if (P == KM_P && exact && !a.rows && a.scale == 1) {
+    // the matrix-core path of the 48 x 48 lattice (its own width of 4 vectors)
+    d.nvb = KM_N / KM_NB;
+    d.lognb = 2;
+    const long gm = 8L * kron_group(KM_NB);
+    const size_t lm = sizeof(double) * KM_NB * KM_N + KM_N + sizeof(double) * KM_WAVES * KM_NB;
+    allow_max_lds((const void*)k_kron_mma48);
+    k_kron_mma48<<<dim3((unsigned)(((long)d.nvb * a.batch + gm - 1) / gm * gm)), KM_THREADS, lm, st>>>(d);
+    SLQ_LAUNCHED();
+    return SLQ_OK;
+  }
   const long gq = 8L * kron_group(nb);
   dim3 grid((unsigned)(((long)d.nvb * a.batch + gq - 1) / gq * gq));
   switch (P) {
