@@ -775,8 +775,10 @@ def headline(slq, args, workload):
                          "chain": {**part_info("chain", FP64_PEAK_TFLOPS),
                                    "note": ("checkerboard FP64 slice products (bond rotations in registers, edge "
                                             "exchanges in LDS): 22 N^2 flops per slice and field" if cb else
-                                            "structured FP64 slice products (vector FMA): 2 N^2 (lx+ly) flops per "
-                                            "slice and field")},
+                                            ("structured FP64 slice products (48 x 48: circulant lines on the "
+                                             "matrix cores; otherwise vector FMA): " if model.lx == model.ly == 48 else
+                                             "structured FP64 slice products (vector FMA): ") +
+                                            "2 N^2 (lx+ly) flops per slice and field")},
                          "final": {**part_info("final", FP64_PEAK_TFLOPS),
                                    "note": "QR of M for the determinant: (4/3) N^3 per field"}}}
     return out, details, plan, eff, s, logabs, sign, status, theta_h, fields, model, terms, seed
