@@ -76,6 +76,35 @@ def test_uneven_group_parity_and_replays(slq):
     grp.close()
 
 
+def test_48x48_chains_of_two_lengths_in_one_batch(slq):
+    """48x48 chains of 10 and 20 slices share one batch: the shorter chain's
+    first stabilisation blocks pass its X through the slice products (the
+    matrix-core chain kernel of this lattice) unchanged.  G and the weight of
+    each chain against the oracle."""
+    from tests.gpu_util import dev, host
+    from slq_inputs import Model
+    base = Model(48, 48, 20, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=5)
+    models = [base.with_(n_slices=20), base.with_(n_slices=10), base.with_(n_slices=20)]
+    fields = [iid_field(m, 4300 + c) for c, m in enumerate(models)]
+    grp = slq.Group(models)
+    info = grp.describe()
+    assert len(info["batches"]) == 1 and info["batches"][0]["L_min"] == 10
+    s = dev(grp.pack(fields))
+    G = torch.empty(int(grp.g_off[-1]), dtype=torch.float64, device="cuda")
+    la = torch.empty(3, dtype=torch.float64, device="cuda")
+    sg = torch.empty(3, dtype=torch.int8, device="cuda")
+    st = torch.empty(3, dtype=torch.int32, device="cuda")
+    slq.slq_group_green(grp, s, G, la, sg, st)
+    G0, la0, sg0, st0 = host(G), host(la), host(sg), host(st)
+    assert np.all(st0 == 0)
+    for c, m in enumerate(models):
+        ref_la, ref_sg, ref_G = stable.green(m, fields[c])
+        Gc = G0[grp.g_off[c]:grp.g_off[c + 1]].reshape(m.n_sites, m.n_sites)
+        assert sg0[c] == ref_sg and abs(la0[c] - ref_la) < 1e-12 * abs(ref_la), c
+        assert np.max(np.abs(Gc - ref_G)) < 1e-10, c
+    grp.close()
+
+
 def test_lengths_off_the_block_grid_get_their_own_batch(slq):
     """Chains whose lengths differ by a whole number of stabilisation blocks
     share a batch, the others do not; every chain matches the oracle."""
