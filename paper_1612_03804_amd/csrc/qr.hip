@@ -435,9 +435,15 @@ int launch_v_update(Plan& p, int batch, const double* V_in, double* V_out, hipSt
   v.beta = 0.0;
   v.a_upper = 1;
   v.batch = batch;
+  // large tile-aligned N: 128 x 128 tiles of 64 x 64 per wavefront (N = 2304,
+  // 256 fields: 60.6 against 62.2 ms per update on 64 x 128 tiles); otherwise
   // columns up to the last multiple of 128 on 64 x 128 tiles, a 16-column
   // remainder on 128 x 16 tiles (no padded columns)
   const int Nm = N / 128 * 128;
+  if (N > 1152 && Nm == N) {
+    v.cfg = GEMM_BIG;
+    return launch_gemm(v, false, false, st);
+  }
   if (Nm == 0 || Nm == N || (N - Nm) % 16 != 0) return launch_gemm(v, false, false, st);
   v.N = Nm;
   v.cfg = GEMM_64x128;

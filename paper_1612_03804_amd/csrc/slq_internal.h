@@ -387,9 +387,14 @@ enum GemmCfg {
   GEMM_128x16,     // 128 x 16, 4 wavefronts, K 8 (16-column edges)
   GEMM_32x64_K32,  // 32 x 64, 4 wavefronts, K 32 (thin products with long K)
   GEMM_16x64_K32,  // 16 x 64, 4 wavefronts, K 32
+  GEMM_BIG,        // 128 x 128, 4 wavefronts of 64 x 64, K 16 (tile-aligned, else 128 x 64)
   GEMM_NCFG
 };
 int launch_gemm_cfg(const GemmArgs& a, bool transA, bool transB, int cfg, hipStream_t st);
+// GEMM_BIG: whether the large-tile kernel takes the product (shape multiple of its
+// tiles, aligned operands, no transposed B, no field scaling), and its launch
+bool gemm_big_ok(const GemmArgs& a, bool transA, bool transB);
+int launch_gemm_big(const GemmArgs& a, bool transA, hipStream_t st);
 int default_gemm(int M, int N);
 struct Plan;
 int tune_chain_gemm(Plan& p, int batch, hipStream_t st, float* best_ms);
