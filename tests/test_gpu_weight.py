@@ -198,6 +198,32 @@ def test_dense_fp64_products_agree(slq, model):
     plan.close()
 
 
+def test_48x48_matrix_core_chain_matches_dense_products(slq):
+    """At 48x48 the structured chain runs its circulant lines on the matrix
+    cores; G and log|W| of four fields (one started from an ordered domain)
+    against the dense FP64 chain (E as a full matrix) and, for one field,
+    against the oracle."""
+    from tests.gpu_util import dev, host
+    m = Model(48, 48, 10, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=5)
+    fields = list(mixed_batch(m, 4, 5300))
+    out = []
+    for prec in (slq.SLQ_PREC_FP64, slq.SLQ_PREC_FP64_DENSE):
+        plan = slq.Plan(m, 4, chain_prec=prec)
+        s = dev(np.stack(fields).astype(np.int8))
+        G = torch.empty((4, plan.n, plan.n), dtype=torch.float64, device="cuda")
+        la = torch.empty(4, dtype=torch.float64, device="cuda")
+        sg = torch.empty(4, dtype=torch.int8, device="cuda")
+        st = torch.empty(4, dtype=torch.int32, device="cuda")
+        slq.slq_green(plan, s, G, la, sg, st)
+        out.append((host(G), host(la), host(sg), host(st)))
+        plan.close()
+    (G1, la1, sg1, st1), (G2, la2, sg2, st2) = out
+    assert np.all(st1 == 0) and np.all(st2 == 0) and np.array_equal(sg1, sg2)
+    assert np.all(np.abs(la1 - la2) <= LOG_TOL * np.abs(la2))
+    assert np.max(np.abs(G1 - G2)) <= G_TOL
+    check_parity(m, fields[:1], G1[:1], la1[:1], sg1[:1], st1[:1])
+
+
 def test_tuned_block_width_keeps_parity(slq):
     """slq_plan_tune picks a power-of-two block width (structured products) or
     a tile shape (dense products) and results stay exact."""
