@@ -258,6 +258,7 @@ int launch_gemm_cfg(const GemmArgs& a, bool ta, bool tb, int cfg, hipStream_t st
     case GEMM_32x64_K32: return run<2, 1, 1, 4, 32>(a, ta, tb, st);
     case GEMM_16x64_K32: return run<1, 1, 1, 4, 32>(a, ta, tb, st);
     case GEMM_BIG: return gemm_big_ok(a, ta, tb) ? launch_gemm_big(a, ta, st) : run<2, 2, 4, 2, 8>(a, ta, tb, st);
+    case GEMM_LEAN: return gemm_lean_ok(a, ta, tb) ? launch_gemm_lean(a, st) : run<2, 2, 4, 2, 8>(a, ta, tb, st);
     default:
       set_error("unknown GEMM tile configuration");
       return SLQ_ERR_ARG;

@@ -154,6 +154,114 @@ __global__ __launch_bounds__(BG_THREADS) void k_gemm_big(GemmArgs g, int ntm, in
     }
 }
 
+// The 128 x 64 tiles of the general kernel (eight wavefronts of 32 x 32, K 8
+// deep) without its bounds checks, loading pairs of doubles: for the rank-k
+// updates of large blocks, where eight wavefronts per SIMD hide the short K.
+constexpr int LN_M = 128, LN_N = 64, LN_K = 8, LN_THREADS = 512;
+
+__global__ __launch_bounds__(LN_THREADS) void k_gemm_lean(GemmArgs g, int ntm, int ntn) {
+  __shared__ __attribute__((aligned(16))) double As[2][LN_K][LN_M + 2];
+  __shared__ __attribute__((aligned(16))) double Bs[2][LN_K][LN_N + 2];
+  const int tpi = ntm * ntn;
+  const int gid = blockIdx.x;
+  const int x = gid % NXCD, j = gid / NXCD;
+  const int b = (j / tpi) * NXCD + x;
+  if (b >= g.batch) return;
+  const int tile = j % tpi;
+  const int tn = tile / ntm, tmi = tile % ntm;
+  const int m0 = tmi * LN_M, n0 = tn * LN_N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+  const double* A = g.A + (long)b * g.strideA;
+  const double* B = g.B + (long)b * g.strideB;
+  d4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) acc[i][jj] = d4_t{0.0, 0.0, 0.0, 0.0};
+  // a stage: A 128 x 8 as 512 pairs along k (one per thread), B 8 x 64 as 256 pairs along n
+  const int arow = tid >> 2, akp = (tid & 3) * 2, bkr = (tid & 255) >> 5, bnp = (tid & 31) * 2;
+  const bool bthr = tid < 256;
+  double a0, a1, b0 = 0.0, b1 = 0.0;
+  auto load = [&](int k0) {
+    const double2 v = *(const double2*)(A + (long)(m0 + arow) * g.lda + k0 + akp);
+    a0 = v.x;
+    a1 = v.y;
+    if (bthr) {
+      const double2 w = *(const double2*)(B + (long)(k0 + bkr) * g.ldb + n0 + bnp);
+      b0 = w.x;
+      b1 = w.y;
+    }
+  };
+  auto store = [&](int buf) {
+    As[buf][akp][arow] = a0;
+    As[buf][akp + 1][arow] = a1;
+    if (bthr) *(double2*)&Bs[buf][bkr][bnp] = make_double2(b0, b1);
+  };
+  const int nst = g.K / LN_K;
+  if (nst > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int st = 0; st < nst; ++st) {
+    const bool more = st + 1 < nst;
+    if (more) load((st + 1) * LN_K);
+#pragma unroll
+    for (int ks = 0; ks < LN_K; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) af[i] = As[cur][kr][wm0 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) bf[jj] = Bs[cur][kr][wn0 + jj * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+          acc[i][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[jj], acc[i][jj], 0, 0, 0);
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  double* C = g.C + (long)b * g.strideC;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gm = m0 + wm0 + i * 16 + acc_row(lane, r);
+      const bool zrow = gm < g.c_zero_rows;
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const int gn = n0 + wn0 + jj * 16 + acc_col(lane, r);
+        double v = g.alpha * acc[i][jj][r];
+        const long o = (long)gm * g.ldc + gn;
+        if (g.beta != 0.0) {
+          const double cin = g.c_ident ? (gm == gn ? 1.0 : 0.0) : (zrow ? 0.0 : C[o]);
+          v += g.beta * cin;
+        }
+        C[o] = v;
+      }
+    }
+}
+
+bool gemm_lean_ok(const GemmArgs& a, bool ta, bool tb) {
+  auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  if (ta || tb || a.S || a.a_upper || a.brow || a.rowscale) return false;
+  if (a.M % LN_M || a.N % LN_N || a.K % LN_K || a.M <= 0 || a.N <= 0 || a.K <= 0) return false;
+  return a.lda % 2 == 0 && a.ldb % 2 == 0 && a.strideA % 2 == 0 && a.strideB % 2 == 0 && al(a.A) && al(a.B);
+}
+
+int launch_gemm_lean(const GemmArgs& a, hipStream_t st) {
+  const int ntm = a.M / LN_M, ntn = a.N / LN_N;
+  const long groups = ((long)a.batch + NXCD - 1) / NXCD * NXCD * ntm * ntn;
+  k_gemm_lean<<<dim3((unsigned)groups), LN_THREADS, 0, st>>>(a, ntm, ntn);
+  SLQ_LAUNCHED();
+  return SLQ_OK;
+}
+
 bool gemm_big_ok(const GemmArgs& a, bool ta, bool tb) {
   auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   if (tb || a.S || (a.a_upper && ta) || (a.brow && !a.a_upper)) return false;

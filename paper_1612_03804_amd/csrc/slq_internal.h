@@ -388,6 +388,7 @@ enum GemmCfg {
   GEMM_32x64_K32,  // 32 x 64, 4 wavefronts, K 32 (thin products with long K)
   GEMM_16x64_K32,  // 16 x 64, 4 wavefronts, K 32
   GEMM_BIG,        // 128 x 128, 4 wavefronts of 64 x 64, K 16 (tile-aligned, else 128 x 64)
+  GEMM_LEAN,       // 128 x 64, 8 wavefronts, K 8, no bounds checks (tile-aligned, else 128 x 64)
   GEMM_NCFG
 };
 int launch_gemm_cfg(const GemmArgs& a, bool transA, bool transB, int cfg, hipStream_t st);
@@ -395,6 +396,9 @@ int launch_gemm_cfg(const GemmArgs& a, bool transA, bool transB, int cfg, hipStr
 // tiles, aligned operands, no transposed B, no field scaling), and its launch
 bool gemm_big_ok(const GemmArgs& a, bool transA, bool transB);
 int launch_gemm_big(const GemmArgs& a, bool transA, hipStream_t st);
+// GEMM_LEAN: 128 x 64 tiles without bounds checks (untransposed, tile-aligned, aligned operands)
+bool gemm_lean_ok(const GemmArgs& a, bool transA, bool transB);
+int launch_gemm_lean(const GemmArgs& a, hipStream_t st);
 int default_gemm(int M, int N);
 struct Plan;
 int tune_chain_gemm(Plan& p, int batch, hipStream_t st, float* best_ms);
