@@ -414,7 +414,8 @@ __global__ __launch_bounds__(P >= 32 ? 512 : 1024) __attribute__((amdgpu_waves_p
 // 48 x 48 lattice, columns, B_l = E diag(d_l), on the matrix cores.  A vector
 // of the block is the 48 x 48 grid G[y][x] of its sites (i = x + 48 y), and
 // E diag(d) G = e^{dtau mu} Cy (diag(d) G) Cx^T with Cx = Cy = C, the
-// 48-point circulant of the y window.  Wavefront w of the workgroup owns the
+// 48-point circulant of the y window (on the square lattice the x window is
+// e^{+-dtau mu} times it; that factor rides on d).  Wavefront w of the workgroup owns the
 // 16-row strip s = w mod 3 of vector w / 3 and computes, with
 // v_mfma_f64_16x16x4_f64 (16 x 16 blocks, K = 48 in 12 steps of 4):
 //   T^T[:, strip] = G^T C^T[:, strip]   (the y-lines; A from the grid in LDS)
