@@ -558,12 +558,14 @@ static int run_blocked(Plan& p, int batch, const double* X, const UdvRef& o, int
     GemmArgs g{};
     g.c_ident = c_ident;
     g.c_zero_rows = c_zero_rows;
-    // with narrow panels (N = 2304) the products with a long K take 128 x 128
-    // tiles of 64 x 64 per wavefront (V^T A: 0.82 against 0.75 of the FP64
-    // peak); untransposed products with a short K (the rank-k updates) take the
-    // 128 x 64 tiles, whose eight wavefronts per SIMD hide a short K better (0.66
-    // against 0.57), without bounds checks where the shape allows (0.70)
-    const bool big = GRAM_T && (ta || K > 256);
+    // the transposed products (V^T A) and, with narrow panels (N = 2304), all
+    // products with a long K take 128 x 128 tiles of 64 x 64 per wavefront (V^T A
+    // at N = 2304: 0.82 against 0.75 of the FP64 peak; at N = 400 6.20 against
+    // 6.25 ms per stabilisation); untransposed products with a short K (the
+    // rank-k updates) take the 128 x 64 tiles, whose eight wavefronts per SIMD
+    // hide a short K better (0.66 against 0.57), without bounds checks where the
+    // shape allows (0.70)
+    const bool big = ta || (GRAM_T && K > 256);
     g.cfg = M >= 64 ? (big ? GEMM_BIG : (ta ? GEMM_128x64 : GEMM_LEAN)) : (M <= 16 ? THIN16 : THIN32);
     g.M = M;
     g.N = Nc;
