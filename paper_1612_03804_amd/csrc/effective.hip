@@ -117,6 +117,10 @@ __device__ __forceinline__ int wrap2(int v, int n) {  // v in [-2n, 3n)
   return v;
 }
 
+// BITS: the field as one bit per spin (1 for s = +1) in 32-bit LDS words,
+// flipped with an LDS atomic xor (sites of a class can share a word); the
+// 48x48, L = 100 field takes 28.8 KB so, against 230 KB as bytes.
+template <bool BITS>
 __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t* s_all, int n_moves, uint64_t seed,
                                                                 uint64_t step, uint64_t chain0, int64_t* accepts,
                                                                 double* dS_out) {
@@ -130,7 +134,8 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
   int16_t* spart = (int16_t*)(pr + np);        // [n_uoff][N]: partner site of each site under offset u
   int16_t* csite = spart + d.n_uoff * N;       // [N] sites by colour
   int16_t* coff = csite + N;                   // [n_colours + 1]
-  int8_t* f = (int8_t*)(coff + d.n_colours + 1); // [L][N]
+  int8_t* f = (int8_t*)(coff + d.n_colours + 1); // [L][N] bytes, or (BITS) [ceil(L N / 32)] words:
+  uint32_t* fw = (uint32_t*)(((uintptr_t)f + 3) & ~(uintptr_t)3);
   const int b = blockIdx.x, tid = threadIdx.x;
   int8_t* s = s_all + (long)b * L * N;
   const uint64_t chain = chain0 + b;
@@ -152,8 +157,23 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
       if (d.terms[2 * k] == 0 && d.terms[2 * k + 1] == 0) h += d.theta[1 + k];
     one_body = h;
   }
-  for (long i = tid; i < (long)L * N; i += EFF_THREADS) f[i] = s[i];
+  const long LN = (long)L * N;
+  if constexpr (BITS) {
+    for (long w = tid; w < (LN + 31) / 32; w += EFF_THREADS) {
+      uint32_t v = 0;
+      for (int k = 0; k < 32 && 32 * w + k < LN; ++k) v |= (uint32_t)(s[32 * w + k] > 0) << k;
+      fw[w] = v;
+    }
+  } else {
+    for (long i = tid; i < LN; i += EFF_THREADS) f[i] = s[i];
+  }
   __syncthreads();
+  auto spin = [&](int q) -> int {  // s at flat index q = l N + i, as +-1
+    if constexpr (BITS)
+      return (int)((fw[q >> 5] >> (q & 31)) & 1u) * 2 - 1;
+    else
+      return f[q];
+  };
   const int sub = tid & (EFF_LPS - 1), slot = tid / EFF_LPS, nslot = EFF_THREADS / EFF_LPS;
   const double h1 = one_body;
   long long acc = 0;
@@ -185,7 +205,7 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
           int ll = l + (e[u] >> 16) - 2048;
           if (ll < 0) ll += L;
           if (ll >= L) ll -= L;
-          sp[u] = (double)f[__umul24(ll, N) + sp_i[e[u] & 0xffff]];
+          sp[u] = (double)spin(__umul24(ll, N) + sp_i[e[u] & 0xffff]);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) hs += w[u] * sp[u];
@@ -193,12 +213,16 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
       hs += dpp_move<DPP_QUAD_XOR1>(hs);
       hs += dpp_move<DPP_QUAD_XOR2>(hs);
       if (sub == 0) {
-        const int8_t sv = f[l * N + i];
+        const int q = l * N + i;
+        const int sv = spin(q);
         const double dS = -2.0 * (double)sv * (h1 + hs);
         const double u = philox_uniform((uint64_t)(1 + (long)l * N + i), (uint64_t)mv, step, chain, seed,
                                         TAG_EFFECTIVE);
         if (u < exp(dS)) {
-          f[l * N + i] = (int8_t)(-sv);
+          if constexpr (BITS)
+            atomicXor(&fw[q >> 5], 1u << (q & 31));
+          else
+            f[q] = (int8_t)(-sv);
           ++acc;
           dsum += dS;
         }
@@ -206,7 +230,7 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
     }
     __syncthreads();
   }
-  for (long i = tid; i < (long)L * N; i += EFF_THREADS) s[i] = f[i];
+  for (long i = tid; i < LN; i += EFF_THREADS) s[i] = (int8_t)spin((int)i);
   dsum = wave_sum(dsum);
   const double a2 = wave_sum((double)acc);  // exact: counts stay far below 2^53
   if ((tid & 63) == 0) {
@@ -226,20 +250,28 @@ __global__ __launch_bounds__(EFF_THREADS) void k_eff_sweep_lds(EffDev d, int8_t*
   }
 }
 
-static size_t eff_lds_bytes(const Plan& p, const Eff& e) {
+static size_t eff_lds_bytes(const Plan& p, const Eff& e, bool bits) {
+  const size_t field = bits ? 4 + 4 * (((size_t)p.L * p.n + 31) / 32) : (size_t)p.L * p.n;
   return (size_t)e.n_pairs * (sizeof(double) + sizeof(int32_t)) +
-         ((size_t)e.n_uoff * p.n + p.n + e.n_colours + 1) * sizeof(int16_t) + (size_t)p.L * p.n;
+         ((size_t)e.n_uoff * p.n + p.n + e.n_colours + 1) * sizeof(int16_t) + field;
 }
 
 int launch_eff_sweep(Plan& p, const Eff& e, int batch, int8_t* s, int n_moves, uint64_t seed, uint64_t step,
                      uint64_t chain0, int64_t* accepts, double* dS, hipStream_t st) {
   if (batch <= 0) return SLQ_OK;
   if (e.net_on) return launch_eff_sweep_net(p, e, batch, s, n_moves, seed, step, chain0, accepts, dS, st);
-  const size_t lds = eff_lds_bytes(p, e);
-  if (e.d_pairs && lds <= 150 * 1024 && p.L <= 4094) {
-    allow_max_lds((const void*)k_eff_sweep_lds);
-    k_eff_sweep_lds<<<batch, EFF_THREADS, lds, st>>>(eff_dev_view(p, e), s, n_moves, seed, step, chain0, accepts,
-                                                     dS);
+  // the field in LDS as bytes where it fits, else as bits (the 48x48, L = 100
+  // field: 28.8 KB), else the kernel that reads it from global memory
+  const size_t lds = eff_lds_bytes(p, e, false), ldsb = eff_lds_bytes(p, e, true);
+  const bool lds_ok = e.d_pairs && p.L <= 4094;
+  if (lds_ok && lds <= 150 * 1024) {
+    allow_max_lds((const void*)k_eff_sweep_lds<false>);
+    k_eff_sweep_lds<false><<<batch, EFF_THREADS, lds, st>>>(eff_dev_view(p, e), s, n_moves, seed, step, chain0,
+                                                            accepts, dS);
+  } else if (lds_ok && ldsb <= 150 * 1024) {
+    allow_max_lds((const void*)k_eff_sweep_lds<true>);
+    k_eff_sweep_lds<true><<<batch, EFF_THREADS, ldsb, st>>>(eff_dev_view(p, e), s, n_moves, seed, step, chain0,
+                                                            accepts, dS);
   } else {
     k_eff_sweep<<<batch, 256, 0, st>>>(eff_dev_view(p, e), s, n_moves, seed, step, chain0, accepts, dS);
   }

@@ -321,9 +321,10 @@ def test_cumulative_steps_20x20_full_size(slq):
 
 
 def test_cumulative_step_48x48_full_size(slq):
-    """The 48x48, L=100 workload (its 230 KB field exceeds the LDS, so the
-    effective moves run from global memory): one chain, one cumulative update
-    of N L = 230 400 single-flip proposals (n_classes class moves)."""
+    """The 48x48, L=100 workload (its 230 KB field exceeds the LDS as bytes, so
+    the effective moves keep it there as bits, 28.8 KB): one chain, one
+    cumulative update of N L = 230 400 single-flip proposals (n_classes class
+    moves)."""
     from slq_inputs import LEARNED_48x48
     m = LEARNED_48x48
     terms = [(0, 0), (1, 0), (2, 0), (0, 1), (0, 2), (1, 1)]
@@ -333,14 +334,25 @@ def test_cumulative_step_48x48_full_size(slq):
     _cumulative_parity(slq, m, terms, 0.0, lam, [iid_field(m, 7800)], n_classes, 1)
 
 
-def test_cumulative_steps_global_moves_small_lattice(slq):
+def test_cumulative_steps_bit_field_small_lattice(slq):
     """A small lattice with a long time axis (12x12, L = 1100: a 158 KB
-    field, above the LDS budget of the effective-move kernel) so that the
-    global-memory move kernel runs where the oracle is cheap: 2 chains x 2
-    cumulative updates."""
+    field, above the LDS budget as bytes) so that the move kernel keeps the
+    field as bits where the oracle is cheap: 2 chains x 2 cumulative updates."""
     m = Model(12, 12, 1100, t=1.0, mu=-0.5, dtau=0.1, xi=1.5, n_stab=10)
     terms = [(0, 0), (1, 0), (2, 0), (0, 1), (0, 2), (0, 7), (1, 1), (2, 3)]
     lam = np.array([-0.45, 0.01, 0.005, 0.02, 0.01, 0.003, 0.004, 0.002])
     assert m.n_slices * m.n_sites > 150 * 1024
     fields = [iid_field(m, 7900 + b) for b in range(2)]
     _cumulative_parity(slq, m, terms, 0.0, lam, fields, 60, 2)
+
+
+def test_cumulative_steps_global_moves(slq):
+    """A time axis beyond the LDS kernels' slice-offset encoding (4x4, L =
+    4200) sends the effective moves to the kernel that reads the field from
+    global memory: 2 chains x 2 cumulative updates of 80 class moves."""
+    m = Model(4, 4, 4200, t=1.0, mu=-0.5, dtau=0.002, xi=1.5, n_stab=10)  # beta = 8.4
+    terms = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    lam = np.array([-0.45, 0.01, 0.02, 0.004])
+    assert m.n_slices > 4094
+    fields = [iid_field(m, 7950 + b) for b in range(2)]
+    _cumulative_parity(slq, m, terms, 0.0, lam, fields, 80, 2)
