@@ -20,8 +20,18 @@ Modules
                effective sweep and cumulative update (Eqs. 2 and 4)
     fit        multi-linear regression and R^2      (Eq. 3, Results)
     autocorr   autocorrelation function and integrated time (Fig. 1 caption)
+    checkerboard  sparse (checkerboard) split of the kinetic factor and the
+               weight and G built on it             (Formalism of SLDQMC)
+    measure    equal-time observables from G, time-displaced G, Ising
+               susceptibility                       (Basics of DQMC, Results)
+    net        convolutional correction to the effective action, its
+               gradient and Adam                    (Formalism of SLDQMC, Eq. 2)
+    bilayer    the four-flavour bilayer weight with the bare Ising action
+               and its local sweep                  (Results, Eq. 6)
 
 Every function says which passage it follows.  Parity of the physics-level
-claims of the paper (autocorrelation times of its bilayer model, critical
-exponents) is unpinned: they need the paper's model and production runs.
+numbers of the paper (autocorrelation times of its bilayer model at its
+parameters, critical exponents) is unpinned: they need couplings the paper
+does not state and production runs; the bilayer module reproduces the
+method's comparison at small sizes, not those numbers.
 """
